@@ -1,0 +1,308 @@
+/*
+ * sbp.h -- C-ABI of the sliding-ball (point-cloud) photoacoustic reconstruction
+ * hot path on AMD Instinct MI355X (gfx950).
+ *
+ * The method is SlingBAG Pro (Li et al., arXiv 2601.00551): a 3-D photoacoustic
+ * source is a cloud of balls (centre x, y, z, peak pressure p0, size a); a
+ * differentiable forward model ("Simulate", section 4.2 and 4.3) predicts every
+ * transducer's time series; the squared L2 residual is minimised by gradient
+ * steps on the ball parameters (section 4.1, Algorithm 1), after a
+ * zero-gradient filter has pruned the initial cloud (section 4.2) and while
+ * the sampling rate is raised level by level (section 4.3).
+ *
+ * Conventions shared by every call
+ *   Units: mm, us; c in mm/us.
+ *   Memory: every data pointer is DEVICE memory owned by the caller.  The
+ *     library never frees or keeps a pointer past the call.  Outputs are
+ *     preallocated by the caller at the sizes stated.  The context owns only
+ *     its internal scratch memory.
+ *   Balls are structure-of-arrays.  Frames (independent reconstructions that
+ *     share one transducer array) are stored back to back: frame f owns balls
+ *     [ball_off[f], ball_off[f+1]).  ball_off is a DEVICE array of F+1 int64
+ *     with ball_off[0] = 0; B_cap is a host-side upper bound on ball_off[F]
+ *     (it sizes launches; the kernels read the true counts on the device, so a
+ *     call can be captured in a HIP graph while counts change between replays).
+ *   Signals are [F][D][T] row-major, T = the level's sample count T_k.
+ *   Streams: `stream` is a hipStream_t (NULL = the null stream).  Every call is
+ *     asynchronous on it; host-visible results (loss, counts) are ready only
+ *     after the caller synchronises, unless a call says otherwise.
+ *   Errors: every call returns SBP_OK (0) or a negative code and then sets a
+ *     thread-local message readable with sbp_last_error().  Arguments are
+ *     validated on the host BEFORE anything is enqueued, in the order: pointers
+ *     and sizes, model fields, then the context; so a failed call enqueues
+ *     nothing.  NaN inputs propagate to NaN outputs; there are no device-side
+ *     checks.  A context is used by one host thread at a time.
+ */
+#ifndef SBP_H
+#define SBP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ codes ----- */
+#define SBP_OK 0
+#define SBP_E_ARG (-1)      /* null pointer, negative or inconsistent size, F < 1 */
+#define SBP_E_DOMAIN (-2)   /* c <= 0, dt <= 0, f < 1, T < 1, unknown enum, K <= 0 */
+#define SBP_E_HIP (-3)      /* a HIP runtime error; message in sbp_last_error() */
+#define SBP_E_NOMEM (-4)    /* the context could not grow its scratch memory */
+#define SBP_E_CAPACITY (-5) /* an output would exceed the caller's capacity */
+
+#define SBP_PROFILE_UNIFORM 0 /* fhat(s) = 1 for |s| < a: the textbook N-shaped pulse */
+#define SBP_PROFILE_GAUSS 1   /* fhat(s) = exp(-s^2 / (2 a^2)) for |s| < K a (section 4.1) */
+#define SBP_DIR_OMNI 0        /* every transducer hears every direction equally */
+#define SBP_DIR_COS 1         /* trace scaled by max(0, n_hat . e_hat) */
+
+/* Gradient / update masks over the five ball parameters. */
+#define SBP_X 1u
+#define SBP_Y 2u
+#define SBP_Z 4u
+#define SBP_P0 8u
+#define SBP_A 16u
+#define SBP_XYZ 7u
+#define SBP_ALL 31u
+#define SBP_COARSE (SBP_P0 | SBP_A) /* coarse stage: positions fixed (section 4.1) */
+
+#define SBP_MAX_FRAMES 64 /* F may not exceed this */
+
+/* ------------------------------------------------------------ types ----- */
+
+/* Forward model of one temporal level k (section 4.3: dt_k = f_k dt, T_k = T/f_k).
+ * Sample n of a transducer is the mean pressure over the time bin
+ * [t0 + n f dt, t0 + (n+1) f dt).  a_softplus = 1 means the `a` arrays hold the
+ * unconstrained a~ and the size is a = softplus(a~) = log(1 + e^a~) (the
+ * positivity-constrained refinement of section 4.3); gradients are then with
+ * respect to a~. */
+typedef struct sbp_model {
+    double c;          /* speed of sound, mm/us, > 0 */
+    double dt;         /* base sample interval, us, > 0 */
+    double t0;         /* time of the first bin edge, us */
+    double gauss_K;    /* GAUSS truncation in units of a, > 0 (5 is the default) */
+    int32_t T;         /* samples at this level, >= 1 */
+    int32_t f;         /* downsampling factor of this level, >= 1 */
+    int32_t profile;   /* SBP_PROFILE_* */
+    int32_t directivity; /* SBP_DIR_* */
+    int32_t a_softplus;  /* 0 or 1 */
+    int32_t reserved;    /* must be 0 */
+} sbp_model;
+
+/* Transducer array: D positions q and unit normals n (SoA, device, float). */
+typedef struct sbp_array {
+    const float *qx, *qy, *qz;
+    const float *nx, *ny, *nz;
+    int32_t D;
+    int32_t reserved;
+} sbp_array;
+
+/* Ball parameters or their gradients (SoA, device, float). */
+typedef struct sbp_balls {
+    float *x, *y, *z, *p0, *a;
+} sbp_balls;
+
+/* FP64 twins, used only by the double-precision entry points. */
+typedef struct sbp_array_f64 {
+    const double *qx, *qy, *qz;
+    const double *nx, *ny, *nz;
+    int32_t D;
+    int32_t reserved;
+} sbp_array_f64;
+
+typedef struct sbp_balls_f64 {
+    double *x, *y, *z, *p0, *a;
+} sbp_balls_f64;
+
+/* Adam hyper-parameters (PyTorch semantics: bias-corrected moments, eps added
+ * after the square root).  lr is per parameter (x, y, z, p0, a). */
+typedef struct sbp_adam_params {
+    float lr[5];
+    float beta1, beta2, eps;
+    int32_t step;      /* 1-based step count of this update */
+    uint32_t mask;     /* parameters to update (SBP_* bits) */
+} sbp_adam_params;
+
+/* Everything one reconstruction iteration touches (all device memory except
+ * the two sizes).  grad is a gradient workspace of capacity B_cap; m and v are
+ * the Adam moments. */
+typedef struct sbp_state {
+    sbp_balls balls;
+    sbp_balls grad;
+    sbp_balls m;
+    sbp_balls v;
+    int64_t *ball_off; /* F+1, device */
+    int32_t F;
+    int32_t reserved;
+    int64_t B_cap;
+} sbp_state;
+
+/* Plain growth rule (section 4.1: split / destroy / duplicate by thresholds on
+ * pressure and size; the paper does not give the thresholds).  Per frame:
+ * destroy balls with p0 < destroy_frac * max p0 or a < a_min; split balls with
+ * a > a_split into two children at -/+ a/2 along the axis of the largest
+ * |position gradient| (size a / 2^(1/3), same p0); duplicate the
+ * floor(dup_frac * n) non-split survivors of largest |grad r| (ties: lower
+ * index) with a clone offset by -dup_offset * a * grad r / |grad r|.  Output per
+ * frame: survivors in input order with split balls replaced in place by their
+ * two children, then the clones in input order.  New balls get zero moments. */
+typedef struct sbp_growth_rule {
+    float destroy_frac;
+    float a_min;
+    float a_split;
+    float dup_frac;
+    float dup_offset;
+    int32_t reserved;
+} sbp_growth_rule;
+
+/* Launch shape of the forward and adjoint kernels (chosen by the autotuner).
+ * sbp_ctx_set_tuning rejects values outside the ranges below.  When a level's
+ * rows do not fit the LDS, the row count is lowered for that call. */
+typedef struct sbp_tuning {
+    int32_t fwd_dets;     /* transducer rows accumulated in LDS per workgroup, 1..16 */
+    int32_t fwd_block;    /* threads per workgroup: 64, 128, 256 or 512 */
+    int32_t fwd_bpt;      /* balls per thread per work item, 1..16 */
+    int32_t fwd_grid;     /* persistent workgroups, 0 = as many as fit on the device */
+    int32_t adj_dets;     /* transducer rows staged in LDS per pass, 1..16 */
+    int32_t adj_block;    /* threads per workgroup: 64, 128, 256 or 512 */
+    int32_t adj_bpt;      /* balls per thread, 1..4 */
+    int32_t adj_grid;     /* persistent workgroups, 0 = as many as fit on the device */
+} sbp_tuning;
+
+typedef struct sbp_ctx sbp_ctx;
+typedef struct sbp_graph sbp_graph;
+
+/* ---------------------------------------------------- context & errors -- */
+
+/* Message of the last failed call on this thread ("" if none).  The pointer
+ * stays valid until the next call on this thread. */
+const char *sbp_last_error(void);
+
+/* Create a context on HIP device `device` (it becomes current on this thread).
+ * Errors: SBP_E_ARG (out NULL, device < 0), SBP_E_HIP (no such device). */
+int sbp_ctx_create(sbp_ctx **out, int device);
+
+/* Free the context and its scratch memory; NULL is accepted. */
+int sbp_ctx_destroy(sbp_ctx *ctx);
+
+/* Number of compute units of the context's device (host value). */
+int sbp_ctx_num_cus(const sbp_ctx *ctx, int32_t *out);
+
+/* Set / read the forward and adjoint launch shapes of this context. */
+int sbp_ctx_set_tuning(sbp_ctx *ctx, const sbp_tuning *t);
+int sbp_ctx_get_tuning(const sbp_ctx *ctx, sbp_tuning *t);
+
+/* ------------------------------------------------------------ the path -- */
+
+/* Downsample_f of section 4.3: y_out[r][n] = (1/f) sum_{j<f} y[r][n f + j] for
+ * n < T/f (integer division; a tail shorter than f is dropped), for R = F*D
+ * rows of length T.  y_out holds R * (T/f) floats.
+ * Errors: SBP_E_ARG (NULL, R < 1), SBP_E_DOMAIN (f < 1, T/f < 1). */
+int sbp_downsample(sbp_ctx *ctx, const float *y, int64_t R, int32_t T, int32_t f,
+                   float *y_out, void *stream);
+
+/* Simulate of section 4.2 / 4.3: y[f][d][n] = sum over the balls i of frame f of
+ *   p0_i * D_id / (2 rho_id c dt_k) * (psi(u_n) - psi(u_{n+1})),
+ *   u_m = rho_id - c (t0 + m dt_k),
+ * the bin mean of the closed-form pressure pulse of ball i at transducer d
+ * (psi is the antiderivative of u * fhat(u), zero outside the support;
+ * rho_id = |r_i - q_d|; D_id is the directivity).  Pairs with
+ * rho_id <= support half-width and balls with a <= 0 contribute nothing.
+ * y is [F][D][model->T]; it is overwritten unless accumulate = 1.
+ * Errors: SBP_E_ARG, SBP_E_DOMAIN, SBP_E_HIP. */
+int sbp_simulate_signals(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *balls,
+                         const int64_t *ball_off, int32_t F, int64_t B_cap,
+                         const sbp_model *model, float *y, int32_t accumulate, void *stream);
+
+/* Data-fidelity loss of section 4.2 / 4.3: with e = y_sim - y_ref,
+ * loss[f] = sum over frame f of e^2 (a sum, no 1/N), computed in FP64, and
+ * (if v_out is not NULL) v_out = 2 e = dL/dy_sim.  v_out may alias y_sim.
+ * n_per_frame = D * T.  loss is a DEVICE array of F doubles.
+ * Errors: SBP_E_ARG. */
+int sbp_residual_loss(sbp_ctx *ctx, const float *y_sim, const float *y_ref, int64_t n_per_frame,
+                      int32_t F, float *v_out, double *loss, void *stream);
+
+/* Backpropagation of section 4.2 / Algorithm 1 as a vector-Jacobian product:
+ * grad.theta[i] = sum_{d,n} v[f][d][n] * d y[f][d][n] / d theta_i for every
+ * parameter theta in `mask` (SBP_* bits).  v = dL/dy; for the L2 loss the
+ * caller passes v = 2 (y_sim - y_ref) (the factor 2 is not applied here).
+ * Gradient arrays outside `mask` may be NULL and are not touched; those in
+ * the mask are overwritten for balls [0, ball_off[F]).
+ * Errors: SBP_E_ARG (mask 0 or a needed pointer NULL), SBP_E_DOMAIN, SBP_E_HIP. */
+int sbp_adjoint_gradients(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *balls,
+                          const int64_t *ball_off, int32_t F, int64_t B_cap,
+                          const sbp_model *model, const float *v, uint32_t mask,
+                          sbp_balls *grad, void *stream);
+
+/* Zero-gradient filtering of section 4.2 and Algorithm 1.  With every p0 set
+ * to 0 the simulated signal vanishes, so g_i = dL/dp0_i = -2 <y_ref, h_i>
+ * with h_i ball i's unit-p0 signal; ball i is kept if g_i < 0 (strict = 1,
+ * Algorithm 1) or g_i <= 0 (strict = 0, the inequalities of section 4.2).
+ * Kept balls are copied, in their original order, to `out` with their stored
+ * p0 (the restore step); off_out (device, F+1) receives the new frame
+ * offsets.  g_out (nullable, [B_cap]) receives g.  mom_in/mom_out (both
+ * nullable; if one is given the other must be) compact the Adam moments the
+ * same way.  `out` must not overlap `in`.  Capacity of `out`: B_cap.
+ * Errors: SBP_E_ARG, SBP_E_DOMAIN, SBP_E_HIP, SBP_E_NOMEM. */
+int sbp_filter_zero_grad(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *in,
+                         const int64_t *off_in, int32_t F, int64_t B_cap, const sbp_model *model,
+                         const float *y_ref, int32_t strict, sbp_balls *out, int64_t *off_out,
+                         float *g_out, const sbp_balls *m_in, const sbp_balls *v_in,
+                         sbp_balls *m_out, sbp_balls *v_out, void *stream);
+
+/* One Adam update (PyTorch semantics) of the parameters in p->mask for balls
+ * [0, ball_off[F]):  m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ * theta -= lr / (1 - b1^t) * m / (sqrt(v) / sqrt(1 - b2^t) + eps).
+ * If step_dev is not NULL the step count t is read from that device int32
+ * (so a captured graph can advance it) instead of p->step.
+ * Errors: SBP_E_ARG, SBP_E_DOMAIN (betas outside [0,1), step < 1). */
+int sbp_adam_update(sbp_ctx *ctx, sbp_state *state, const sbp_adam_params *p,
+                    const int32_t *step_dev, void *stream);
+
+/* One reconstruction iteration of Algorithm 1 at level `model`:
+ * simulate (y_work) -> residual and loss (y_work becomes 2 e) -> adjoint for
+ * p->mask -> Adam on p->mask.  loss (device, F doubles) receives the loss of
+ * the balls as they were before the update.  y_ref and y_work are [F][D][T].
+ * Errors: as the calls above. */
+int sbp_step(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state, const sbp_model *model,
+             const float *y_ref, float *y_work, const sbp_adam_params *p, double *loss,
+             void *stream);
+
+/* Capture `iters` consecutive sbp_step iterations into one HIP graph.  The
+ * step count starts at *step_dev (device int32) and is incremented on the
+ * device after each iteration, so successive launches continue the Adam
+ * schedule.  loss receives iters * F doubles (iteration-major).  The ball
+ * counts in state->ball_off may change between launches (up to B_cap).  The
+ * graph keeps the pointers it was created with.
+ * Errors: as sbp_step, plus SBP_E_HIP on capture failure. */
+int sbp_step_graph_create(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state,
+                          const sbp_model *model, const float *y_ref, float *y_work,
+                          const sbp_adam_params *p, int32_t *step_dev, double *loss,
+                          int32_t iters, sbp_graph **out, void *stream);
+int sbp_graph_launch(sbp_graph *g, void *stream);
+int sbp_graph_destroy(sbp_graph *g);
+
+/* Plain growth rule (see sbp_growth_rule) applied to `in` (uses in->grad for
+ * the split axis and the duplication ranking) and written to `out`
+ * (balls, zeroed-or-copied moments, ball_off); out->B_cap is its capacity.
+ * This call synchronises `stream` to return the new total in *count (host).
+ * Errors: SBP_E_ARG, SBP_E_CAPACITY (out->B_cap too small; out is then
+ * unspecified), SBP_E_HIP. */
+int sbp_grow(sbp_ctx *ctx, const sbp_state *in, const sbp_growth_rule *rule, sbp_state *out,
+             int64_t *count, void *stream);
+
+/* Double-precision twins of sbp_simulate_signals and sbp_adjoint_gradients
+ * (same contract, FP64 buffers), used to check gradients by finite
+ * differences. */
+int sbp_simulate_signals_f64(sbp_ctx *ctx, const sbp_array_f64 *arr, const sbp_balls_f64 *balls,
+                             const int64_t *ball_off, int32_t F, int64_t B_cap,
+                             const sbp_model *model, double *y, int32_t accumulate, void *stream);
+int sbp_adjoint_gradients_f64(sbp_ctx *ctx, const sbp_array_f64 *arr, const sbp_balls_f64 *balls,
+                              const int64_t *ball_off, int32_t F, int64_t B_cap,
+                              const sbp_model *model, const double *v, uint32_t mask,
+                              sbp_balls_f64 *grad, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBP_H */

@@ -222,7 +222,8 @@ class GrowthRule:
     """Thresholds of the plain growth rule (the paper gives none; section 4.1).
 
     Thresholds are given as FP32 values and every decision is taken in FP32, the
-    precision of the stored ball parameters.
+    precision of the stored ball parameters (the duplicate count is
+    floor(n * dup_frac) in FP64 with dup_frac rounded to FP32 first).
     """
     destroy_frac: float = 0.02     # destroy if p0 < destroy_frac * max p0 (per frame)
     a_min: float = 0.02            # destroy if a < a_min (mm)
@@ -272,7 +273,7 @@ def grow(balls, grads, rule: GrowthRule, ball_off=None):
         gz = np.asarray(grads["z"], dtype=f32)[lo:hi].astype(np.float64)
         key = (gx * gx + gy * gy) + gz * gz
         cand = np.nonzero(alive & ~split)[0]
-        k = int(np.floor(len(cand) * float(rule.dup_frac)))
+        k = int(np.floor(len(cand) * float(f32(rule.dup_frac))))
         dup = np.zeros(n, dtype=bool)
         if k > 0:
             order = sorted(cand.tolist(), key=lambda i: (-key[i], i))

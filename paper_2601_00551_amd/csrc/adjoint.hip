@@ -1,0 +1,249 @@
+// Adjoint (vector-Jacobian product) of the forward model on gfx950, and the
+// p0-only variant that zero-gradient filtering (section 4.2) runs.
+//
+// Gather form, no atomics: a lane owns up to four balls and keeps their five
+// gradient sums in registers while the workgroup streams every transducer's
+// cotangent row through LDS, `ds` rows per pass.  Rows are staged pre-
+// differenced, w_m = v_m - v_{m-1} (v_{-1} = v_T = 0), so that by summation by
+// parts
+//     sum_n v_n (h(u_n) - h(u_{n+1})) = sum_m h(u_m) w_m
+// for any edge function h; one LDS read per edge then serves the three sums
+//     A0 = sum w max(q, 0)-part, A1 = sum w psi'(u), A2 = sum w d psi / d a
+// from which the pair's gradients follow in closed form:
+//     G = D / (2 rho c dt),  dL/dp0 = G S0,  dL/da = p0 G S2,
+//     dL/dr = p0 G (S1 - S0 / rho) e_hat + p0 S0 / (2 rho c dt) (n_hat - D e_hat) / rho
+// (the last term only for COS directivity and D > 0).
+#include "sbp_internal.hpp"
+
+namespace sbp {
+
+constexpr int kMaxBpt = 4;
+
+template <typename R, int PROF, int DIR, bool FULL>
+__device__ inline void adj_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx, R ny, R nz,
+                                const Level &lc, const R *__restrict__ wr, R acc[5]) {
+    PairG<R> g;
+    if (!pair_geometry<R, DIR>(b.x, b.y, b.z, b.w, qx, qy, qz, nx, ny, nz, lc, g)) return;
+    const double lo = floor((g.s - b.w) * lc.inv_cdt);
+    const double hi = floor((g.s + b.w) * lc.inv_cdt) + 1.0;
+    if (hi < 0.0 || lo > (double)lc.T) return;
+    const int mb = lo < 0.0 ? 0 : (int)lo;
+    const int me = hi > (double)lc.T ? lc.T : (int)hi;
+    const R eK = LevelR<R>::eK(lc);
+    const R cdt = LevelR<R>::cdt(lc);
+    const R u0 = (R)(g.s - (double)mb * lc.cdt);
+    R A0 = R(0), A1 = R(0), A2 = R(0);
+    R j = R(0);
+    for (int m = mb; m <= me; ++m, j += R(1)) {
+        const R u = fma(-j, cdt, u0);
+        const R wv = wr[m];
+        const R t = u * u;
+        if (PROF == GAUSS) {
+            const R e = ex2(t * b.q0);
+            const R we = e > eK ? wv : R(0);
+            A0 = fma(we, e - eK, A0);
+            if (FULL) {
+                const R wee = we * e;
+                A1 = fma(wee, u, A1);
+                A2 = fma(wee, t, A2);
+            }
+        } else {
+            const R q = b.q0 - t;
+            const R we = q > R(0) ? wv : R(0);
+            A0 = fma(we, q, A0);
+            if (FULL) {
+                A1 = fma(we, u, A1);
+                A2 += we;
+            }
+        }
+    }
+    R S0, S1, S2;
+    if (PROF == GAUSS) {
+        S0 = -(b.a * b.a) * A0;
+        S1 = A1;
+        S2 = R(-2) * b.a * A0 - A2 / b.a;
+    } else {
+        S0 = R(-0.5) * A0;
+        S1 = A1;
+        S2 = -b.a * A2;
+    }
+    const R G = g.dir * LevelR<R>::inv2cdt(lc) * g.inv_rho;
+    acc[3] = fma(G, S0, acc[3]);
+    if (FULL) {
+        const R pG = b.p * G;
+        acc[4] = fma(pG, S2, acc[4]);
+        const R radial = pG * (S1 - S0 * g.inv_rho);
+        acc[0] = fma(radial, g.ex, acc[0]);
+        acc[1] = fma(radial, g.ey, acc[1]);
+        acc[2] = fma(radial, g.ez, acc[2]);
+        if (DIR == COS) {
+            const R ct = b.p * LevelR<R>::inv2cdt(lc) * S0 * g.inv_rho * g.inv_rho;
+            acc[0] = fma(ct, nx - g.dir * g.ex, acc[0]);
+            acc[1] = fma(ct, ny - g.dir * g.ey, acc[1]);
+            acc[2] = fma(ct, nz - g.dir * g.ez, acc[2]);
+        }
+    }
+}
+
+template <typename R, int PROF, int DIR, bool FULL>
+__global__ __launch_bounds__(512) void k_adjoint(ArrayP<R> arr, BallsP<R> balls,
+                                                 const int64_t *__restrict__ ball_off, int F,
+                                                 int ds, int bpt, Level lc,
+                                                 const R *__restrict__ v, R vscale,
+                                                 uint32_t mask, BallsP<R> grad) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    R *rows = reinterpret_cast<R *>(lds_raw);
+    __shared__ int64_t s_off[SBP_MAX_FRAMES + 1];
+    __shared__ int64_t s_cpre[SBP_MAX_FRAMES + 1];
+    const int tid = threadIdx.x;
+    const int nth = blockDim.x;
+    const int T = lc.T;
+    const int D = arr.D;
+    const int64_t CH = (int64_t)nth * bpt;
+    for (int i = tid; i <= F; i += nth) s_off[i] = ball_off[i];
+    __syncthreads();
+    if (tid == 0) {
+        s_cpre[0] = 0;
+        for (int f = 0; f < F; ++f)
+            s_cpre[f + 1] = s_cpre[f] + (s_off[f + 1] - s_off[f] + CH - 1) / CH;
+    }
+    __syncthreads();
+    const int64_t I = s_cpre[F];
+    for (int64_t it = blockIdx.x; it < I; it += gridDim.x) {
+        int f = 0;
+        while (it >= s_cpre[f + 1]) ++f;
+        const int64_t base = s_off[f] + (it - s_cpre[f]) * CH;
+        const int64_t end = min(base + CH, s_off[f + 1]);
+        BallK<R, PROF> b[kMaxBpt];
+        R acc[kMaxBpt][5];
+        bool act[kMaxBpt];
+#pragma unroll
+        for (int jb = 0; jb < kMaxBpt; ++jb) {
+            const int64_t i = base + (int64_t)jb * nth + tid;
+            act[jb] = jb < bpt && i < end;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) acc[jb][k] = R(0);
+            if (act[jb]) {
+                b[jb] = load_ball<R, PROF>(balls.x[i], balls.y[i], balls.z[i], balls.p0[i],
+                                           balls.a[i], lc);
+                act[jb] = b[jb].live;
+            }
+        }
+        const R *vf = v + (int64_t)f * D * (int64_t)T;
+        for (int d0 = 0; d0 < D; d0 += ds) {
+            const int nd = min(ds, D - d0);
+            __syncthreads();
+            for (int dl = 0; dl < nd; ++dl) {
+                const R *vr = vf + (int64_t)(d0 + dl) * T;
+                R *wr = rows + (int64_t)dl * (T + 1);
+                for (int m = tid; m <= T; m += nth) {
+                    const R cur = m < T ? vr[m] : R(0);
+                    const R prv = m > 0 ? vr[m - 1] : R(0);
+                    wr[m] = vscale * (cur - prv);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int jb = 0; jb < kMaxBpt; ++jb) {
+                if (!act[jb]) continue;
+                for (int dl = 0; dl < nd; ++dl) {
+                    const int d = __builtin_amdgcn_readfirstlane(d0 + dl);
+                    adj_pair<R, PROF, DIR, FULL>(b[jb], arr.qx[d], arr.qy[d], arr.qz[d], arr.nx[d],
+                                                 arr.ny[d], arr.nz[d], lc,
+                                                 rows + (int64_t)dl * (T + 1), acc[jb]);
+                }
+            }
+        }
+#pragma unroll
+        for (int jb = 0; jb < kMaxBpt; ++jb) {
+            const int64_t i = base + (int64_t)jb * nth + tid;
+            if (!(jb < bpt && i < end)) continue;
+            // dead balls (a <= 0) get exact zeros
+            if (mask & SBP_X) grad.x[i] = acc[jb][0];
+            if (mask & SBP_Y) grad.y[i] = acc[jb][1];
+            if (mask & SBP_Z) grad.z[i] = acc[jb][2];
+            if (mask & SBP_P0) grad.p0[i] = acc[jb][3];
+            if (mask & SBP_A) {
+                R ga = acc[jb][4];
+                if (lc.a_softplus) ga *= sigmoid_dev(balls.a[i]);
+                grad.a[i] = ga;
+            }
+        }
+    }
+}
+
+template <typename R, int PROF, int DIR, bool FULL>
+static int run_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
+                       const int64_t *ball_off, int F, int64_t B_cap, const Level &lc, const R *v,
+                       R vscale, uint32_t mask, const BallsP<R> &grad, hipStream_t st) {
+    auto kern = k_adjoint<R, PROF, DIR, FULL>;
+    const size_t reserve = 2 * (SBP_MAX_FRAMES + 1) * sizeof(int64_t) + 256;
+    const size_t row_bytes = (size_t)(lc.T + 1) * sizeof(R);
+    int ds = c->tuning.adj_dets;
+    while (ds > 1 && ds * row_bytes + reserve > c->lds_max) --ds;
+    if (ds * row_bytes + reserve > c->lds_max)
+        return fail(SBP_E_DOMAIN, "T = %d samples do not fit one LDS row", lc.T);
+    if (ds > arr.D) ds = arr.D;
+    const int block = c->tuning.adj_block;
+    const int bpt = c->tuning.adj_bpt;
+    const size_t lds = (size_t)ds * row_bytes;
+    SBP_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    int grid = c->tuning.adj_grid;
+    if (grid <= 0) {
+        int per_cu = 0;
+        SBP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, block, lds));
+        if (per_cu < 1) per_cu = 1;
+        grid = per_cu * c->num_cus;
+    }
+    const int64_t CH = (int64_t)block * bpt;
+    const int64_t max_items = (B_cap + CH - 1) / CH + F;
+    if (grid > max_items) grid = (int)max_items;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, arr, balls, ball_off, F, ds, bpt,
+                       lc, v, vscale, mask, grad);
+    SBP_HIP(hipGetLastError());
+    return SBP_OK;
+}
+
+template <typename R, bool FULL>
+static int dispatch_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
+                            const int64_t *ball_off, int F, int64_t B_cap, const sbp_model *m,
+                            const R *v, R vscale, uint32_t mask, const BallsP<R> &grad,
+                            hipStream_t st) {
+    const Level lc = make_level(m);
+    if (m->profile == SBP_PROFILE_GAUSS) {
+        if (m->directivity == SBP_DIR_COS)
+            return run_adjoint<R, GAUSS, COS, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v,
+                                                    vscale, mask, grad, st);
+        return run_adjoint<R, GAUSS, OMNI, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v, vscale,
+                                                 mask, grad, st);
+    }
+    if (m->directivity == SBP_DIR_COS)
+        return run_adjoint<R, UNIFORM, COS, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v, vscale,
+                                                  mask, grad, st);
+    return run_adjoint<R, UNIFORM, OMNI, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v, vscale,
+                                               mask, grad, st);
+}
+
+template <typename R>
+int launch_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
+                   int F, int64_t B_cap, const sbp_model *m, const R *v, R vscale,
+                   uint32_t mask, const BallsP<R> &grad, hipStream_t st) {
+    if (B_cap == 0) return SBP_OK;
+    if ((mask & ~SBP_P0) == 0)
+        return dispatch_adjoint<R, false>(c, arr, balls, ball_off, F, B_cap, m, v, vscale, mask,
+                                          grad, st);
+    return dispatch_adjoint<R, true>(c, arr, balls, ball_off, F, B_cap, m, v, vscale, mask, grad,
+                                     st);
+}
+
+template int launch_adjoint<float>(Ctx *, const ArrayP<float> &, const BallsP<float> &,
+                                   const int64_t *, int, int64_t, const sbp_model *, const float *,
+                                   float, uint32_t, const BallsP<float> &, hipStream_t);
+template int launch_adjoint<double>(Ctx *, const ArrayP<double> &, const BallsP<double> &,
+                                    const int64_t *, int, int64_t, const sbp_model *,
+                                    const double *, double, uint32_t, const BallsP<double> &,
+                                    hipStream_t);
+
+}  // namespace sbp

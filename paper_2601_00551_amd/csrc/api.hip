@@ -1,0 +1,526 @@
+// Host side of the C-ABI declared in include/sbp.h: argument validation (all
+// of it before anything is enqueued), the context, error reporting, and the
+// composition of the kernels into the calls of the reconstruction loop.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "sbp_internal.hpp"
+
+struct sbp_ctx {
+    sbp::Ctx c;
+};
+
+struct sbp_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void *ws = nullptr;  // residual partial sums owned by the graph
+    int device = 0;
+};
+
+namespace sbp {
+
+static thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(SBP_E_HIP, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+int ensure_scratch(Ctx *c, size_t bytes) {
+    if (bytes <= c->scratch_bytes) return SBP_OK;
+    size_t nb = c->scratch_bytes * 2;
+    if (nb < bytes) nb = bytes;
+    nb = (nb + 4095) & ~(size_t)4095;
+    if (c->scratch) {
+        hipError_t e = hipFree(c->scratch);
+        c->scratch = nullptr;
+        c->scratch_bytes = 0;
+        if (e != hipSuccess) return hip_fail(e, "hipFree(scratch)");
+    }
+    if (hipMalloc(&c->scratch, nb) != hipSuccess) {
+        c->scratch = nullptr;
+        (void)hipGetLastError();
+        return fail(SBP_E_NOMEM, "could not allocate %zu bytes of scratch", nb);
+    }
+    c->scratch_bytes = nb;
+    return SBP_OK;
+}
+
+Level make_level(const sbp_model *m) {
+    Level lc;
+    const double dtk = (double)m->f * m->dt;
+    lc.ct0 = m->c * m->t0;
+    lc.cdt = m->c * dtk;
+    lc.inv_cdt = 1.0 / lc.cdt;
+    lc.inv2cdt_d = 1.0 / (2.0 * lc.cdt);
+    lc.K_d = m->gauss_K;
+    lc.eK_d = std::exp(-0.5 * m->gauss_K * m->gauss_K);
+    lc.cdt_f = (float)lc.cdt;
+    lc.inv2cdt = (float)lc.inv2cdt_d;
+    lc.K = (float)lc.K_d;
+    lc.eK = (float)lc.eK_d;
+    lc.T = m->T;
+    lc.a_softplus = m->a_softplus;
+    return lc;
+}
+
+// ----------------------------------------------------------- validation --
+
+static int check_model(const sbp_model *m) {
+    if (!m) return fail(SBP_E_ARG, "model is NULL");
+    if (!(m->c > 0.0) || !std::isfinite(m->c)) return fail(SBP_E_DOMAIN, "c must be > 0");
+    if (!(m->dt > 0.0) || !std::isfinite(m->dt)) return fail(SBP_E_DOMAIN, "dt must be > 0");
+    if (!std::isfinite(m->t0)) return fail(SBP_E_DOMAIN, "t0 must be finite");
+    if (m->f < 1) return fail(SBP_E_DOMAIN, "f must be >= 1");
+    if (m->T < 1) return fail(SBP_E_DOMAIN, "T must be >= 1");
+    if (m->profile != SBP_PROFILE_UNIFORM && m->profile != SBP_PROFILE_GAUSS)
+        return fail(SBP_E_DOMAIN, "unknown profile %d", m->profile);
+    if (m->directivity != SBP_DIR_OMNI && m->directivity != SBP_DIR_COS)
+        return fail(SBP_E_DOMAIN, "unknown directivity %d", m->directivity);
+    if (m->a_softplus != 0 && m->a_softplus != 1) return fail(SBP_E_DOMAIN, "a_softplus must be 0 or 1");
+    if (m->reserved != 0) return fail(SBP_E_DOMAIN, "model.reserved must be 0");
+    if (m->profile == SBP_PROFILE_GAUSS && (!(m->gauss_K > 0.0) || !std::isfinite(m->gauss_K)))
+        return fail(SBP_E_DOMAIN, "gauss_K must be > 0");
+    return SBP_OK;
+}
+
+template <typename A>
+static int check_array(const A *a) {
+    if (!a) return fail(SBP_E_ARG, "array is NULL");
+    if (!a->qx || !a->qy || !a->qz || !a->nx || !a->ny || !a->nz)
+        return fail(SBP_E_ARG, "array has a NULL coordinate pointer");
+    if (a->D < 1) return fail(SBP_E_ARG, "array D must be >= 1");
+    return SBP_OK;
+}
+
+// Ball arrays may be NULL only when the capacity is zero.
+template <typename B>
+static int check_balls(const B *b, const char *what, int64_t B_cap = 1) {
+    if (!b) return fail(SBP_E_ARG, "%s is NULL", what);
+    if (B_cap == 0) return SBP_OK;
+    if (!b->x || !b->y || !b->z || !b->p0 || !b->a) return fail(SBP_E_ARG, "%s has a NULL array", what);
+    return SBP_OK;
+}
+
+static int check_frames(const int64_t *off, int32_t F, int64_t B_cap) {
+    if (!off) return fail(SBP_E_ARG, "ball_off is NULL");
+    if (F < 1 || F > SBP_MAX_FRAMES) return fail(SBP_E_ARG, "F must be in [1, %d]", SBP_MAX_FRAMES);
+    if (B_cap < 0) return fail(SBP_E_ARG, "B_cap must be >= 0");
+    return SBP_OK;
+}
+
+template <typename B>
+static int check_grad(const B *g, uint32_t mask, int64_t B_cap) {
+    if (mask == 0 || (mask & ~SBP_ALL)) return fail(SBP_E_ARG, "mask must be a non-empty subset of SBP_ALL");
+    if (!g) return fail(SBP_E_ARG, "grad is NULL");
+    if (B_cap == 0) return SBP_OK;
+    if (((mask & SBP_X) && !g->x) || ((mask & SBP_Y) && !g->y) || ((mask & SBP_Z) && !g->z) ||
+        ((mask & SBP_P0) && !g->p0) || ((mask & SBP_A) && !g->a))
+        return fail(SBP_E_ARG, "grad array for a masked parameter is NULL");
+    return SBP_OK;
+}
+
+static int check_ctx(const sbp_ctx *ctx) {
+    if (!ctx) return fail(SBP_E_ARG, "ctx is NULL");
+    return SBP_OK;
+}
+
+static int check_adam(const sbp_adam_params *p, bool need_step) {
+    if (!p) return fail(SBP_E_ARG, "adam params are NULL");
+    if (p->mask == 0 || (p->mask & ~SBP_ALL)) return fail(SBP_E_ARG, "adam mask must be a non-empty subset of SBP_ALL");
+    if (!(p->beta1 >= 0.0f && p->beta1 < 1.0f) || !(p->beta2 >= 0.0f && p->beta2 < 1.0f))
+        return fail(SBP_E_DOMAIN, "betas must be in [0, 1)");
+    if (!(p->eps >= 0.0f)) return fail(SBP_E_DOMAIN, "eps must be >= 0");
+    for (int k = 0; k < 5; ++k)
+        if (!std::isfinite(p->lr[k])) return fail(SBP_E_DOMAIN, "lr must be finite");
+    if (need_step && p->step < 1) return fail(SBP_E_DOMAIN, "step must be >= 1");
+    return SBP_OK;
+}
+
+static int check_state(const sbp_state *s, uint32_t mask, bool need_moments) {
+    if (!s) return fail(SBP_E_ARG, "state is NULL");
+    int rc = check_frames(s->ball_off, s->F, s->B_cap);
+    if (rc) return rc;
+    rc = check_balls(&s->balls, "state.balls", s->B_cap);
+    if (rc) return rc;
+    if (s->B_cap == 0) return SBP_OK;
+    const float *g[5] = {s->grad.x, s->grad.y, s->grad.z, s->grad.p0, s->grad.a};
+    const float *m[5] = {s->m.x, s->m.y, s->m.z, s->m.p0, s->m.a};
+    const float *v[5] = {s->v.x, s->v.y, s->v.z, s->v.p0, s->v.a};
+    for (int k = 0; k < 5; ++k) {
+        if (!(mask & (1u << k))) continue;
+        if (!g[k]) return fail(SBP_E_ARG, "state.grad array for a masked parameter is NULL");
+        if (need_moments && (!m[k] || !v[k]))
+            return fail(SBP_E_ARG, "state moment array for a masked parameter is NULL");
+    }
+    return SBP_OK;
+}
+
+template <typename R, typename A>
+static ArrayP<R> arrp(const A *a) {
+    return ArrayP<R>{a->qx, a->qy, a->qz, a->nx, a->ny, a->nz, a->D};
+}
+
+template <typename R, typename B>
+static BallsP<R> ballsp(const B *b) {
+    return BallsP<R>{b->x, b->y, b->z, b->p0, b->a};
+}
+
+static int set_device(const Ctx &c) {
+    SBP_HIP(hipSetDevice(c.device));
+    return SBP_OK;
+}
+
+static int check_tuning(const sbp_tuning *t) {
+    if (!t) return fail(SBP_E_ARG, "tuning is NULL");
+    auto okb = [](int b) { return b == 64 || b == 128 || b == 256 || b == 512; };
+    if (t->fwd_dets < 1 || t->fwd_dets > 16 || t->adj_dets < 1 || t->adj_dets > 16)
+        return fail(SBP_E_DOMAIN, "dets must be in [1, 16]");
+    if (!okb(t->fwd_block) || !okb(t->adj_block)) return fail(SBP_E_DOMAIN, "block must be 64, 128, 256 or 512");
+    if (t->fwd_bpt < 1 || t->fwd_bpt > 16) return fail(SBP_E_DOMAIN, "fwd_bpt must be in [1, 16]");
+    if (t->adj_bpt < 1 || t->adj_bpt > 4) return fail(SBP_E_DOMAIN, "adj_bpt must be in [1, 4]");
+    if (t->fwd_grid < 0 || t->adj_grid < 0) return fail(SBP_E_DOMAIN, "grid must be >= 0");
+    return SBP_OK;
+}
+
+// One iteration, shared by sbp_step and the graph capture.
+static int step_body(Ctx *c, const sbp_array *arr, sbp_state *s, const sbp_model *model,
+                     const float *y_ref, float *y_work, const sbp_adam_params *p,
+                     const int32_t *step_dev, double *loss, double *partial, hipStream_t st) {
+    const ArrayP<float> a = arrp<float>(arr);
+    const BallsP<float> b = ballsp<float>(&s->balls);
+    const BallsP<float> g = ballsp<float>(&s->grad);
+    int rc = launch_forward<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 0, st);
+    if (rc) return rc;
+    const int64_t n = (int64_t)arr->D * model->T;
+    rc = launch_residual_loss(partial, y_work, y_ref, n, s->F, y_work, loss, st);
+    if (rc) return rc;
+    rc = launch_adjoint<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 1.0f, p->mask, g, st);
+    if (rc) return rc;
+    return launch_adam(s, p, step_dev, model->a_softplus, st);
+}
+
+}  // namespace sbp
+
+using namespace sbp;
+
+extern "C" {
+
+const char *sbp_last_error(void) { return g_err; }
+
+int sbp_ctx_create(sbp_ctx **out, int device) {
+    g_err[0] = 0;
+    if (!out) return fail(SBP_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (device < 0) return fail(SBP_E_ARG, "device must be >= 0");
+    int n = 0;
+    SBP_HIP(hipGetDeviceCount(&n));
+    if (device >= n) return fail(SBP_E_HIP, "device %d does not exist (%d visible)", device, n);
+    SBP_HIP(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    SBP_HIP(hipGetDeviceProperties(&prop, device));
+    sbp_ctx *ctx = new sbp_ctx();
+    ctx->c.device = device;
+    ctx->c.num_cus = prop.multiProcessorCount;
+    size_t lds = prop.sharedMemPerBlock;
+    if (prop.maxSharedMemoryPerMultiProcessor > lds) lds = prop.maxSharedMemoryPerMultiProcessor;
+    ctx->c.lds_max = lds;
+    ctx->c.tuning = sbp_tuning{4, 512, 2, 0, 4, 256, 2, 0};
+    *out = ctx;
+    return SBP_OK;
+}
+
+int sbp_ctx_destroy(sbp_ctx *ctx) {
+    if (!ctx) return SBP_OK;
+    int rc = SBP_OK;
+    if (ctx->c.scratch) {
+        if (hipSetDevice(ctx->c.device) == hipSuccess && hipFree(ctx->c.scratch) != hipSuccess)
+            rc = fail(SBP_E_HIP, "hipFree(scratch) failed");
+    }
+    delete ctx;
+    return rc;
+}
+
+int sbp_ctx_num_cus(const sbp_ctx *ctx, int32_t *out) {
+    if (!out) return fail(SBP_E_ARG, "out is NULL");
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    *out = ctx->c.num_cus;
+    return SBP_OK;
+}
+
+int sbp_ctx_set_tuning(sbp_ctx *ctx, const sbp_tuning *t) {
+    int rc = check_tuning(t);
+    if (rc) return rc;
+    rc = check_ctx(ctx);
+    if (rc) return rc;
+    ctx->c.tuning = *t;
+    return SBP_OK;
+}
+
+int sbp_ctx_get_tuning(const sbp_ctx *ctx, sbp_tuning *t) {
+    if (!t) return fail(SBP_E_ARG, "tuning is NULL");
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    *t = ctx->c.tuning;
+    return SBP_OK;
+}
+
+int sbp_downsample(sbp_ctx *ctx, const float *y, int64_t R, int32_t T, int32_t f, float *y_out,
+                   void *stream) {
+    if (!y || !y_out) return fail(SBP_E_ARG, "y or y_out is NULL");
+    if (R < 1) return fail(SBP_E_ARG, "R must be >= 1");
+    if (f < 1) return fail(SBP_E_DOMAIN, "f must be >= 1");
+    if (T < 1 || T / f < 1) return fail(SBP_E_DOMAIN, "T / f must be >= 1");
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = set_device(ctx->c))) return rc;
+    return launch_downsample(y, R, T, f, y_out, (hipStream_t)stream);
+}
+
+int sbp_simulate_signals(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *balls,
+                         const int64_t *ball_off, int32_t F, int64_t B_cap, const sbp_model *model,
+                         float *y, int32_t accumulate, void *stream) {
+    int rc;
+    if ((rc = check_array(arr)) || (rc = check_frames(ball_off, F, B_cap)) ||
+        (rc = check_balls(balls, "balls", B_cap)))
+        return rc;
+    if (!y) return fail(SBP_E_ARG, "y is NULL");
+    if (accumulate != 0 && accumulate != 1) return fail(SBP_E_ARG, "accumulate must be 0 or 1");
+    if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
+    if ((rc = set_device(ctx->c))) return rc;
+    return launch_forward<float>(&ctx->c, arrp<float>(arr), ballsp<float>(balls), ball_off, F,
+                                 B_cap, model, y, accumulate, (hipStream_t)stream);
+}
+
+int sbp_simulate_signals_f64(sbp_ctx *ctx, const sbp_array_f64 *arr, const sbp_balls_f64 *balls,
+                             const int64_t *ball_off, int32_t F, int64_t B_cap,
+                             const sbp_model *model, double *y, int32_t accumulate, void *stream) {
+    int rc;
+    if ((rc = check_array(arr)) || (rc = check_frames(ball_off, F, B_cap)) ||
+        (rc = check_balls(balls, "balls", B_cap)))
+        return rc;
+    if (!y) return fail(SBP_E_ARG, "y is NULL");
+    if (accumulate != 0 && accumulate != 1) return fail(SBP_E_ARG, "accumulate must be 0 or 1");
+    if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
+    if ((rc = set_device(ctx->c))) return rc;
+    return launch_forward<double>(&ctx->c, arrp<double>(arr), ballsp<double>(balls), ball_off, F,
+                                  B_cap, model, y, accumulate, (hipStream_t)stream);
+}
+
+int sbp_residual_loss(sbp_ctx *ctx, const float *y_sim, const float *y_ref, int64_t n_per_frame,
+                      int32_t F, float *v_out, double *loss, void *stream) {
+    if (!y_sim || !y_ref || !loss) return fail(SBP_E_ARG, "y_sim, y_ref or loss is NULL");
+    if (n_per_frame < 0) return fail(SBP_E_ARG, "n_per_frame must be >= 0");
+    if (F < 1 || F > SBP_MAX_FRAMES) return fail(SBP_E_ARG, "F must be in [1, %d]", SBP_MAX_FRAMES);
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = set_device(ctx->c))) return rc;
+    if ((rc = ensure_scratch(&ctx->c, residual_ws_bytes(F)))) return rc;
+    return launch_residual_loss((double *)ctx->c.scratch, y_sim, y_ref, n_per_frame, F, v_out, loss,
+                                (hipStream_t)stream);
+}
+
+int sbp_adjoint_gradients(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *balls,
+                          const int64_t *ball_off, int32_t F, int64_t B_cap,
+                          const sbp_model *model, const float *v, uint32_t mask, sbp_balls *grad,
+                          void *stream) {
+    int rc;
+    if ((rc = check_array(arr)) || (rc = check_frames(ball_off, F, B_cap)) ||
+        (rc = check_balls(balls, "balls", B_cap)) || (rc = check_grad(grad, mask, B_cap)))
+        return rc;
+    if (!v) return fail(SBP_E_ARG, "v is NULL");
+    if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
+    if ((rc = set_device(ctx->c))) return rc;
+    return launch_adjoint<float>(&ctx->c, arrp<float>(arr), ballsp<float>(balls), ball_off, F,
+                                 B_cap, model, v, 1.0f, mask, ballsp<float>(grad),
+                                 (hipStream_t)stream);
+}
+
+int sbp_adjoint_gradients_f64(sbp_ctx *ctx, const sbp_array_f64 *arr, const sbp_balls_f64 *balls,
+                              const int64_t *ball_off, int32_t F, int64_t B_cap,
+                              const sbp_model *model, const double *v, uint32_t mask,
+                              sbp_balls_f64 *grad, void *stream) {
+    int rc;
+    if ((rc = check_array(arr)) || (rc = check_frames(ball_off, F, B_cap)) ||
+        (rc = check_balls(balls, "balls", B_cap)) || (rc = check_grad(grad, mask, B_cap)))
+        return rc;
+    if (!v) return fail(SBP_E_ARG, "v is NULL");
+    if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
+    if ((rc = set_device(ctx->c))) return rc;
+    return launch_adjoint<double>(&ctx->c, arrp<double>(arr), ballsp<double>(balls), ball_off, F,
+                                  B_cap, model, v, 1.0, mask, ballsp<double>(grad),
+                                  (hipStream_t)stream);
+}
+
+int sbp_filter_zero_grad(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *in,
+                         const int64_t *off_in, int32_t F, int64_t B_cap, const sbp_model *model,
+                         const float *y_ref, int32_t strict, sbp_balls *out, int64_t *off_out,
+                         float *g_out, const sbp_balls *m_in, const sbp_balls *v_in,
+                         sbp_balls *m_out, sbp_balls *v_out, void *stream) {
+    int rc;
+    if ((rc = check_array(arr)) || (rc = check_frames(off_in, F, B_cap)) ||
+        (rc = check_balls(in, "in", B_cap)) || (rc = check_balls(out, "out", B_cap)))
+        return rc;
+    if (!y_ref || !off_out) return fail(SBP_E_ARG, "y_ref or off_out is NULL");
+    if (strict != 0 && strict != 1) return fail(SBP_E_ARG, "strict must be 0 or 1");
+    const bool any_mom = m_in || v_in || m_out || v_out;
+    if (any_mom) {
+        if ((rc = check_balls(m_in, "m_in", B_cap)) || (rc = check_balls(v_in, "v_in", B_cap)) ||
+            (rc = check_balls(m_out, "m_out", B_cap)) || (rc = check_balls(v_out, "v_out", B_cap)))
+            return rc;
+    }
+    if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
+    if ((rc = set_device(ctx->c))) return rc;
+    // scratch: [filter gradient (if g_out is NULL)][compaction workspace]
+    const size_t g_bytes = g_out ? 0 : (((size_t)B_cap * sizeof(float) + 255) & ~(size_t)255);
+    if ((rc = ensure_scratch(&ctx->c, g_bytes + compact_ws_bytes(B_cap)))) return rc;
+    float *g = g_out ? g_out : (float *)ctx->c.scratch;
+    void *ws = (char *)ctx->c.scratch + g_bytes;
+    hipStream_t st = (hipStream_t)stream;
+    BallsP<float> gp{nullptr, nullptr, nullptr, g, nullptr};
+    rc = launch_adjoint<float>(&ctx->c, arrp<float>(arr), ballsp<float>(in), off_in, F, B_cap, model,
+                               y_ref, -2.0f, SBP_P0, gp, st);
+    if (rc) return rc;
+    BallsP<float> mi, vi, mo, vo;
+    if (any_mom) {
+        mi = ballsp<float>(m_in);
+        vi = ballsp<float>(v_in);
+        mo = ballsp<float>(m_out);
+        vo = ballsp<float>(v_out);
+    }
+    return launch_compact(ws, g, strict, ballsp<float>(in), off_in, F, B_cap, ballsp<float>(out),
+                          off_out, any_mom ? &mi : nullptr, any_mom ? &vi : nullptr,
+                          any_mom ? &mo : nullptr, any_mom ? &vo : nullptr, st);
+}
+
+int sbp_adam_update(sbp_ctx *ctx, sbp_state *state, const sbp_adam_params *p,
+                    const int32_t *step_dev, void *stream) {
+    int rc;
+    if ((rc = check_adam(p, step_dev == nullptr))) return rc;
+    if ((rc = check_state(state, p->mask, true))) return rc;
+    if ((rc = check_ctx(ctx))) return rc;
+    if ((rc = set_device(ctx->c))) return rc;
+    return launch_adam(state, p, step_dev, 0, (hipStream_t)stream);
+}
+
+int sbp_step(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state, const sbp_model *model,
+             const float *y_ref, float *y_work, const sbp_adam_params *p, double *loss,
+             void *stream) {
+    int rc;
+    if ((rc = check_array(arr)) || (rc = check_adam(p, true)) ||
+        (rc = check_state(state, p->mask, true)))
+        return rc;
+    if (!y_ref || !y_work || !loss) return fail(SBP_E_ARG, "y_ref, y_work or loss is NULL");
+    if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
+    if ((rc = set_device(ctx->c))) return rc;
+    if ((rc = ensure_scratch(&ctx->c, residual_ws_bytes(state->F)))) return rc;
+    return step_body(&ctx->c, arr, state, model, y_ref, y_work, p, nullptr, loss,
+                     (double *)ctx->c.scratch, (hipStream_t)stream);
+}
+
+int sbp_step_graph_create(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state,
+                          const sbp_model *model, const float *y_ref, float *y_work,
+                          const sbp_adam_params *p, int32_t *step_dev, double *loss, int32_t iters,
+                          sbp_graph **out, void *stream) {
+    int rc;
+    if (!out) return fail(SBP_E_ARG, "out is NULL");
+    *out = nullptr;
+    if ((rc = check_array(arr)) || (rc = check_adam(p, false)) ||
+        (rc = check_state(state, p->mask, true)))
+        return rc;
+    if (!y_ref || !y_work || !loss || !step_dev) return fail(SBP_E_ARG, "y_ref, y_work, loss or step_dev is NULL");
+    if (iters < 1) return fail(SBP_E_ARG, "iters must be >= 1");
+    if (!stream) return fail(SBP_E_ARG, "graph capture needs a non-null stream");
+    if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
+    if ((rc = set_device(ctx->c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    sbp_graph *g = new sbp_graph();
+    g->device = ctx->c.device;
+    if (hipMalloc(&g->ws, residual_ws_bytes(state->F)) != hipSuccess) {
+        delete g;
+        (void)hipGetLastError();
+        return fail(SBP_E_NOMEM, "could not allocate the graph workspace");
+    }
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+        (void)hipFree(g->ws);
+        delete g;
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    int body = SBP_OK;
+    for (int it = 0; it < iters && body == SBP_OK; ++it) {
+        body = step_body(&ctx->c, arr, state, model, y_ref, y_work, p, step_dev,
+                         loss + (int64_t)it * state->F, (double *)g->ws, st);
+        if (body == SBP_OK) body = launch_incr(step_dev, st);
+    }
+    e = hipStreamEndCapture(st, &g->graph);
+    if (body != SBP_OK || e != hipSuccess) {
+        char msg[512];
+        snprintf(msg, sizeof msg, "%s", g_err);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        (void)hipFree(g->ws);
+        delete g;
+        if (body != SBP_OK) return fail(body, "during capture: %s", msg);
+        return hip_fail(e, "hipStreamEndCapture");
+    }
+    e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g->graph);
+        (void)hipFree(g->ws);
+        delete g;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    *out = g;
+    return SBP_OK;
+}
+
+int sbp_graph_launch(sbp_graph *g, void *stream) {
+    if (!g) return fail(SBP_E_ARG, "graph is NULL");
+    SBP_HIP(hipSetDevice(g->device));
+    SBP_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return SBP_OK;
+}
+
+int sbp_graph_destroy(sbp_graph *g) {
+    if (!g) return SBP_OK;
+    int rc = SBP_OK;
+    if (hipSetDevice(g->device) != hipSuccess) rc = fail(SBP_E_HIP, "hipSetDevice failed");
+    if (g->exec && hipGraphExecDestroy(g->exec) != hipSuccess) rc = fail(SBP_E_HIP, "hipGraphExecDestroy failed");
+    if (g->graph && hipGraphDestroy(g->graph) != hipSuccess) rc = fail(SBP_E_HIP, "hipGraphDestroy failed");
+    if (g->ws && hipFree(g->ws) != hipSuccess) rc = fail(SBP_E_HIP, "hipFree failed");
+    delete g;
+    return rc;
+}
+
+int sbp_grow(sbp_ctx *ctx, const sbp_state *in, const sbp_growth_rule *rule, sbp_state *out,
+             int64_t *count, void *stream) {
+    int rc;
+    if (!in || !out || !rule) return fail(SBP_E_ARG, "in, out or rule is NULL");
+    if ((rc = check_frames(in->ball_off, in->F, in->B_cap)) ||
+        (rc = check_balls(&in->balls, "in.balls", in->B_cap)) ||
+        (rc = check_frames(out->ball_off, out->F, out->B_cap)) ||
+        (rc = check_balls(&out->balls, "out.balls", out->B_cap)))
+        return rc;
+    if (in->B_cap > 0 && (!in->grad.x || !in->grad.y || !in->grad.z))
+        return fail(SBP_E_ARG, "in.grad x, y, z are needed");
+    if (out->F != in->F) return fail(SBP_E_ARG, "out.F must equal in.F");
+    if (!(rule->destroy_frac >= 0.0f) || !(rule->a_min >= 0.0f) || !(rule->a_split > 0.0f) ||
+        !(rule->dup_frac >= 0.0f && rule->dup_frac <= 1.0f) || !std::isfinite(rule->dup_offset) ||
+        rule->reserved != 0)
+        return fail(SBP_E_DOMAIN, "growth rule out of range");
+    if ((rc = check_ctx(ctx))) return rc;
+    if ((rc = set_device(ctx->c))) return rc;
+    return launch_grow(&ctx->c, in, rule, out, count, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,334 @@
+// Bandwidth-bound steps of the iteration on gfx950: fill, Downsample_f
+// (section 4.3), residual + loss (section 4.2 / 4.3), Adam, and the stable
+// stream compaction behind zero-gradient filtering (section 4.2).
+#include "sbp_internal.hpp"
+
+namespace sbp {
+
+constexpr int kEw = 256;  // threads per workgroup of the elementwise kernels
+
+template <typename R>
+__global__ void k_fill(R *__restrict__ p, int64_t n, R value) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+static int ew_grid(int64_t n) {
+    int64_t g = (n + kEw - 1) / kEw;
+    if (g > 65536) g = 65536;
+    return g < 1 ? 1 : (int)g;
+}
+
+template <typename R>
+int launch_fill(R *p, int64_t n, R value, hipStream_t st) {
+    if (n <= 0) return SBP_OK;
+    hipLaunchKernelGGL(k_fill<R>, dim3(ew_grid(n)), dim3(kEw), 0, st, p, n, value);
+    SBP_HIP(hipGetLastError());
+    return SBP_OK;
+}
+template int launch_fill<float>(float *, int64_t, float, hipStream_t);
+template int launch_fill<double>(double *, int64_t, double, hipStream_t);
+template int launch_fill<int32_t>(int32_t *, int64_t, int32_t, hipStream_t);
+template int launch_fill<int64_t>(int64_t *, int64_t, int64_t, hipStream_t);
+template int launch_fill<uint64_t>(uint64_t *, int64_t, uint64_t, hipStream_t);
+
+// ------------------------------------------------------------ downsample --
+
+__global__ void k_downsample(const float *__restrict__ y, int64_t R_, int T, int f, int Tk,
+                             float *__restrict__ out) {
+    const int64_t n_out = R_ * (int64_t)Tk;
+    const float inv = 1.0f / (float)f;
+    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n_out;
+         o += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = o / Tk;
+        const int n = (int)(o - r * Tk);
+        const float *src = y + r * (int64_t)T + (int64_t)n * f;
+        float s = 0.0f;
+        for (int j = 0; j < f; ++j) s += src[j];
+        out[o] = (f & (f - 1)) == 0 ? s * inv : s / (float)f;
+    }
+}
+
+int launch_downsample(const float *y, int64_t R_, int T, int f, float *out, hipStream_t st) {
+    const int Tk = T / f;
+    hipLaunchKernelGGL(k_downsample, dim3(ew_grid(R_ * (int64_t)Tk)), dim3(kEw), 0, st, y, R_, T,
+                       f, Tk, out);
+    SBP_HIP(hipGetLastError());
+    return SBP_OK;
+}
+
+// ------------------------------------------------------- residual + loss --
+
+__device__ inline double block_sum(double x, double *s_part) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) s_part[wid] = x;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) t += s_part[w];
+    return t;
+}
+
+constexpr int kLossBlocks = 512;  // partial sums per frame (fixed: deterministic order)
+
+__global__ void k_residual(const float *__restrict__ ys, const float *__restrict__ yr, int64_t n,
+                           float *v, double *__restrict__ partial) {
+    __shared__ double s_part[kEw / 64];
+    const int f = blockIdx.y;
+    const float *a = ys + (int64_t)f * n;
+    const float *b = yr + (int64_t)f * n;
+    float *vo = v ? v + (int64_t)f * n : nullptr;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float e = a[i] - b[i];
+        if (vo) vo[i] = 2.0f * e;
+        acc += (double)e * (double)e;
+    }
+    const double t = block_sum(acc, s_part);
+    if (threadIdx.x == 0) partial[(int64_t)f * gridDim.x + blockIdx.x] = t;
+}
+
+__global__ void k_loss_final(const double *__restrict__ partial, int nblk, double *__restrict__ loss) {
+    __shared__ double s_part[kEw / 64];
+    const int f = blockIdx.x;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) acc += partial[(int64_t)f * nblk + i];
+    const double t = block_sum(acc, s_part);
+    if (threadIdx.x == 0) loss[f] = t;
+}
+
+size_t residual_ws_bytes(int F) { return (size_t)F * kLossBlocks * sizeof(double); }
+
+int launch_residual_loss(double *partial, const float *ys, const float *yr, int64_t n, int F,
+                         float *v, double *loss, hipStream_t st) {
+    hipLaunchKernelGGL(k_residual, dim3(kLossBlocks, F), dim3(kEw), 0, st, ys, yr, n, v, partial);
+    SBP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_loss_final, dim3(F), dim3(kEw), 0, st, partial, kLossBlocks, loss);
+    SBP_HIP(hipGetLastError());
+    return SBP_OK;
+}
+
+// ------------------------------------------------------------------- Adam --
+
+struct AdamArgs {
+    float *param[5];
+    const float *grad[5];
+    float *m[5];
+    float *v[5];
+    float lr[5];
+    float beta1, beta2, eps;
+    int32_t step;
+    uint32_t mask;
+};
+
+// PyTorch's single-tensor Adam in FP32: m.lerp_(g, 1-b1); v = v*b2 + (1-b2) g g;
+// denom = sqrt(v) / sqrt(bc2) + eps; param += (-lr/bc1) * m / denom, where the
+// bias corrections are formed in FP64 and rounded once.
+__global__ void k_adam(AdamArgs a, const int64_t *__restrict__ ball_off, int F,
+                       const int32_t *__restrict__ step_dev) {
+    const int64_t count = ball_off[F];
+    const int step = step_dev ? *step_dev : a.step;
+    const double bc1 = 1.0 - pow((double)a.beta1, (double)step);
+    const double bc2 = 1.0 - pow((double)a.beta2, (double)step);
+    const float bc2_sqrt = (float)sqrt(bc2);
+    const float w1 = 1.0f - a.beta1;
+    const float w2 = 1.0f - a.beta2;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            if (!(a.mask & (1u << k))) continue;
+            const float g = a.grad[k][i];
+            float m = a.m[k][i];
+            float v = a.v[k][i];
+            m = m + w1 * (g - m);
+            v = v * a.beta2 + w2 * g * g;
+            const float denom = sqrtf(v) / bc2_sqrt + a.eps;
+            const float step_size = (float)(-(double)a.lr[k] / bc1);
+            a.param[k][i] = a.param[k][i] + step_size * (m / denom);
+            a.m[k][i] = m;
+            a.v[k][i] = v;
+        }
+    }
+}
+
+int launch_adam(const sbp_state *s, const sbp_adam_params *p, const int32_t *step_dev,
+                int a_softplus, hipStream_t st) {
+    (void)a_softplus;
+    AdamArgs a;
+    float *P[5] = {s->balls.x, s->balls.y, s->balls.z, s->balls.p0, s->balls.a};
+    float *Gr[5] = {s->grad.x, s->grad.y, s->grad.z, s->grad.p0, s->grad.a};
+    float *M[5] = {s->m.x, s->m.y, s->m.z, s->m.p0, s->m.a};
+    float *V[5] = {s->v.x, s->v.y, s->v.z, s->v.p0, s->v.a};
+    for (int k = 0; k < 5; ++k) {
+        a.param[k] = P[k];
+        a.grad[k] = Gr[k];
+        a.m[k] = M[k];
+        a.v[k] = V[k];
+        a.lr[k] = p->lr[k];
+    }
+    a.beta1 = p->beta1;
+    a.beta2 = p->beta2;
+    a.eps = p->eps;
+    a.step = p->step;
+    a.mask = p->mask;
+    if (s->B_cap == 0) return SBP_OK;
+    hipLaunchKernelGGL(k_adam, dim3(ew_grid(s->B_cap)), dim3(kEw), 0, st, a, s->ball_off, s->F,
+                       step_dev);
+    SBP_HIP(hipGetLastError());
+    return SBP_OK;
+}
+
+__global__ void k_incr(int32_t *p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p += 1;
+}
+
+int launch_incr(int32_t *p, hipStream_t st) {
+    hipLaunchKernelGGL(k_incr, dim3(1), dim3(64), 0, st, p);
+    SBP_HIP(hipGetLastError());
+    return SBP_OK;
+}
+
+// ------------------------------------------------------------- compaction --
+// Stable compaction of the balls whose filter gradient passes the keep test.
+// Blocks of kEw consecutive indices: count, exclusive scan of the counts in one
+// workgroup, then a scatter where each wave ranks its lanes with a ballot.
+
+__device__ inline bool keep_of(const float *g, int64_t i, int64_t count, int strict) {
+    if (i >= count) return false;
+    const float v = g[i];
+    return strict ? (v < 0.0f) : (v <= 0.0f);
+}
+
+__global__ void k_count_keep(const float *__restrict__ g, int strict,
+                             const int64_t *__restrict__ off_in, int F, int *__restrict__ cnt) {
+    const int64_t count = off_in[F];
+    const int64_t i = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    const int c = __syncthreads_count(keep_of(g, i, count, strict));
+    if (threadIdx.x == 0) cnt[blockIdx.x] = c;
+}
+
+__global__ void k_scan_counts(const int *__restrict__ cnt, int nblk, int64_t *__restrict__ pre) {
+    __shared__ int64_t s_carry;
+    __shared__ int64_t s_wave[1024 / 64];
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int base = 0; base < nblk; base += blockDim.x) {
+        const int i = base + threadIdx.x;
+        int64_t x = i < nblk ? cnt[i] : 0;
+        // inclusive wave scan
+        int64_t s = x;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t t = __shfl_up(s, o, 64);
+            if (lane >= o) s += t;
+        }
+        if (lane == 63) s_wave[wid] = s;
+        __syncthreads();
+        int64_t wpre = 0;
+        for (int w = 0; w < wid; ++w) wpre += s_wave[w];
+        const int64_t carry = s_carry;
+        if (i < nblk) pre[i] = carry + wpre + s - x;
+        __syncthreads();
+        if (threadIdx.x == blockDim.x - 1) s_carry = carry + wpre + s;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) pre[nblk] = s_carry;
+}
+
+struct CompactArgs {
+    const float *src[15];
+    float *dst[15];
+    int narr;
+};
+
+__global__ void k_scatter_keep(const float *__restrict__ g, int strict,
+                               const int64_t *__restrict__ off_in, int F,
+                               const int64_t *__restrict__ pre, CompactArgs ca) {
+    __shared__ int s_wave[kEw / 64];
+    const int64_t count = off_in[F];
+    const int64_t i = (int64_t)blockIdx.x * kEw + threadIdx.x;
+    const bool k = keep_of(g, i, count, strict);
+    const unsigned long long bal = __ballot(k);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int below = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0) s_wave[wid] = __popcll(bal);
+    __syncthreads();
+    int wpre = 0;
+    for (int w = 0; w < wid; ++w) wpre += s_wave[w];
+    if (k) {
+        const int64_t dst = pre[blockIdx.x] + wpre + below;
+        for (int a = 0; a < ca.narr; ++a) ca.dst[a][dst] = ca.src[a][i];
+    }
+}
+
+__global__ void k_frame_offsets(const float *__restrict__ g, int strict,
+                                const int64_t *__restrict__ off_in, int F, int nblk,
+                                const int64_t *__restrict__ pre, int64_t *__restrict__ off_out) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f > F) return;
+    const int64_t count = off_in[F];
+    const int64_t p = off_in[f];
+    const int64_t blk = p / kEw;
+    if (blk >= nblk) {
+        off_out[f] = pre[nblk];
+        return;
+    }
+    int64_t c = pre[blk];
+    for (int64_t i = blk * kEw; i < p; ++i) c += keep_of(g, i, count, strict) ? 1 : 0;
+    off_out[f] = c;
+}
+
+size_t compact_ws_bytes(int64_t B_cap) {
+    const int64_t nblk = (B_cap + kEw - 1) / kEw;
+    return (size_t)(nblk + 1) * sizeof(int) + 256 + (size_t)(nblk + 2) * sizeof(int64_t);
+}
+
+int launch_compact(void *ws, const float *g, int strict, const BallsP<float> &in,
+                   const int64_t *off_in, int F, int64_t B_cap, const BallsP<float> &out,
+                   int64_t *off_out, const BallsP<float> *m_in, const BallsP<float> *v_in,
+                   const BallsP<float> *m_out, const BallsP<float> *v_out, hipStream_t st) {
+    const int64_t nblk64 = (B_cap + kEw - 1) / kEw;
+    if (nblk64 > (int64_t)1 << 30) return fail(SBP_E_ARG, "B_cap too large");
+    const int nblk = (int)nblk64;
+    int *cnt = (int *)ws;
+    const size_t off_pre = ((size_t)(nblk + 1) * sizeof(int) + 255) & ~(size_t)255;
+    int64_t *pre = (int64_t *)((char *)ws + off_pre);
+    if (nblk > 0) {
+        hipLaunchKernelGGL(k_count_keep, dim3(nblk), dim3(kEw), 0, st, g, strict, off_in, F, cnt);
+        SBP_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, cnt, nblk, pre);
+    SBP_HIP(hipGetLastError());
+    CompactArgs ca;
+    int n = 0;
+    const BallsP<float> *srcs[3] = {&in, m_in, v_in};
+    const BallsP<float> *dsts[3] = {&out, m_out, v_out};
+    for (int s = 0; s < 3; ++s) {
+        if (!srcs[s] || !dsts[s]) continue;
+        const BallsP<float> &a = *srcs[s];
+        const BallsP<float> &b = *dsts[s];
+        const float *sa[5] = {a.x, a.y, a.z, a.p0, a.a};
+        float *da[5] = {b.x, b.y, b.z, b.p0, b.a};
+        for (int k = 0; k < 5; ++k) {
+            ca.src[n] = sa[k];
+            ca.dst[n] = da[k];
+            ++n;
+        }
+    }
+    ca.narr = n;
+    if (nblk > 0) {
+        hipLaunchKernelGGL(k_scatter_keep, dim3(nblk), dim3(kEw), 0, st, g, strict, off_in, F, pre,
+                           ca);
+        SBP_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_frame_offsets, dim3(1), dim3(SBP_MAX_FRAMES + 64), 0, st, g, strict,
+                       off_in, F, nblk, pre, off_out);
+    SBP_HIP(hipGetLastError());
+    return SBP_OK;
+}
+
+}  // namespace sbp

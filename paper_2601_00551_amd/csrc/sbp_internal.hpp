@@ -1,0 +1,208 @@
+// Internal declarations of the MI355X (gfx950) implementation behind sbp.h.
+//
+// Device-side physics of one (ball, transducer) pair.  A ball is a radially
+// symmetric initial pressure p0 * fhat(s) (section 4.1 of SlingBAG Pro); at
+// distance rho the pressure is p0 * u * fhat(u) / (2 rho), u = rho - c t, and
+// the mean over the time bin [tau_n, tau_{n+1}) is
+//     p0 * D * (psi(u_n) - psi(u_{n+1})) / (2 rho c dt_k),
+// psi being the antiderivative of u * fhat(u) that vanishes outside the
+// support.  Per profile (a = ball size, K = GAUSS truncation):
+//     UNIFORM: psi(u) = -(a^2 - u^2) / 2                   for |u| < a
+//     GAUSS:   psi(u) = -a^2 (exp(-u^2 / (2 a^2)) - e^{-K^2/2}) for |u| < K a
+// Both are written below as amp * max(q(u), 0) so that the support test is a
+// single max.  The distance rho and the offset rho - c t of the first edge are
+// formed in FP64 (a FP32 rho would move the pulse by up to 4e-6 mm at 70 mm,
+// several 1e-5 of its width); the per-edge work is FP32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sbp.h"
+
+namespace sbp {
+
+enum { UNIFORM = SBP_PROFILE_UNIFORM, GAUSS = SBP_PROFILE_GAUSS };
+enum { OMNI = SBP_DIR_OMNI, COS = SBP_DIR_COS };
+
+// Per-launch constants of one temporal level.
+struct Level {
+    double ct0;      // c * t0
+    double cdt;      // c * dt_k
+    double inv_cdt;  // 1 / (c dt_k)
+    double inv2cdt_d;  // 1 / (2 c dt_k)
+    double eK_d;     // exp(-K^2 / 2)
+    double K_d;      // GAUSS truncation, units of a
+    float cdt_f;     // the same, rounded to float
+    float inv2cdt;
+    float K;
+    float eK;
+    int T;           // samples at this level
+    int a_softplus;  // a arrays hold a~ with a = softplus(a~)
+};
+
+// Level constants in the precision R of the kernel instantiation.
+template <typename R> struct LevelR;
+template <> struct LevelR<float> {
+    __device__ static float cdt(const Level &l) { return l.cdt_f; }
+    __device__ static float inv2cdt(const Level &l) { return l.inv2cdt; }
+    __device__ static float eK(const Level &l) { return l.eK; }
+};
+template <> struct LevelR<double> {
+    __device__ static double cdt(const Level &l) { return l.cdt; }
+    __device__ static double inv2cdt(const Level &l) { return l.inv2cdt_d; }
+    __device__ static double eK(const Level &l) { return l.eK_d; }
+};
+
+Level make_level(const sbp_model *m);
+
+// ------------------------------------------------------------ device math --
+
+template <typename R> __device__ inline R ex2(R x);
+template <> __device__ inline float ex2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
+template <> __device__ inline double ex2<double>(double x) { return exp2(x); }
+
+template <typename R> __device__ inline R rcp(R x);
+template <> __device__ inline float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ inline double rcp<double>(double x) { return 1.0 / x; }
+
+// a = softplus(a~) (identity above 20, as PyTorch) and d a / d a~ = sigmoid(a~).
+template <typename R> __device__ inline R softplus_dev(R x) {
+    return x > R(20) ? x : log1p(exp(x));
+}
+template <typename R> __device__ inline R sigmoid_dev(R x) { return R(1) / (R(1) + exp(-x)); }
+
+// Per-ball constants.
+template <typename R, int PROF>
+struct BallK {
+    double x, y, z;   // centre, widened
+    double w;         // support half-width (a or K a)
+    R p, a;           // peak pressure, size
+    R q0;             // UNIFORM: a^2        GAUSS: -log2(e) / (2 a^2)
+    R ampk;           // UNIFORM: -p / 2     GAUSS: -p a^2
+    bool live;        // a > 0
+};
+
+template <typename R, int PROF>
+__device__ inline BallK<R, PROF> load_ball(R x, R y, R z, R p, R araw, const Level &lc) {
+    BallK<R, PROF> b;
+    R a = lc.a_softplus ? softplus_dev(araw) : araw;
+    b.x = (double)x;
+    b.y = (double)y;
+    b.z = (double)z;
+    b.p = p;
+    b.a = a;
+    b.live = a > R(0);
+    if (PROF == UNIFORM) {
+        b.w = (double)a;
+        b.q0 = a * a;
+        b.ampk = R(-0.5) * p;
+    } else {
+        b.w = lc.K_d * (double)a;
+        b.q0 = R(-1.4426950408889634) / (R(2) * a * a);
+        b.ampk = -p * a * a;
+    }
+    return b;
+}
+
+// q(u) such that psi(u) = amp * max(q(u), 0) with amp = ampk * D / (2 rho c dt).
+template <typename R, int PROF>
+__device__ inline R shape_q(R u, const BallK<R, PROF> &b, R eK) {
+    if (PROF == UNIFORM) return b.q0 - u * u;
+    return ex2(u * u * b.q0) - eK;
+}
+
+// Geometry of one pair, shared by the forward and the adjoint.
+template <typename R>
+struct PairG {
+    double s;    // rho - c t0
+    R rho;       // distance
+    R inv_rho;
+    R ex, ey, ez;  // unit vector transducer -> ball
+    R dir;       // directivity factor
+};
+
+// Returns false if the pair contributes nothing (near field, facing away).
+template <typename R, int DIR>
+__device__ inline bool pair_geometry(double bx, double by, double bz, double w, R qx, R qy, R qz,
+                                     R nx, R ny, R nz, const Level &lc, PairG<R> &g) {
+    const double dx = bx - (double)qx, dy = by - (double)qy, dz = bz - (double)qz;
+    const double rho = sqrt(dx * dx + dy * dy + dz * dz);
+    if (!(rho > w)) return false;
+    g.s = rho - lc.ct0;
+    g.rho = (R)rho;
+    g.inv_rho = rcp(g.rho);
+    g.ex = (R)dx * g.inv_rho;
+    g.ey = (R)dy * g.inv_rho;
+    g.ez = (R)dz * g.inv_rho;
+    if (DIR == COS) {
+        g.dir = nx * g.ex + ny * g.ey + nz * g.ez;
+        if (!(g.dir > R(0))) return false;
+    } else {
+        g.dir = R(1);
+    }
+    return true;
+}
+
+// ------------------------------------------------------------- host side --
+
+struct Ctx {
+    int device = 0;
+    int num_cus = 0;
+    size_t lds_max = 0;
+    sbp_tuning tuning{};
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+};
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+int ensure_scratch(Ctx *c, size_t bytes);
+
+#define SBP_HIP(call)                                          \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return ::sbp::hip_fail(e_, #call); \
+    } while (0)
+
+// Launchers (forward.hip, adjoint.hip, elementwise.hip).
+template <typename R>
+struct ArrayP {
+    const R *qx, *qy, *qz, *nx, *ny, *nz;
+    int D;
+};
+template <typename R>
+struct BallsP {
+    R *x, *y, *z, *p0, *a;
+};
+
+template <typename R>
+int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
+                   int F, int64_t B_cap, const sbp_model *m, R *y, int accumulate,
+                   hipStream_t st);
+
+// vscale multiplies v (the filter passes y_ref with vscale = -2).
+template <typename R>
+int launch_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
+                   int F, int64_t B_cap, const sbp_model *m, const R *v, R vscale,
+                   uint32_t mask, const BallsP<R> &grad, hipStream_t st);
+
+template <typename R>
+int launch_fill(R *p, int64_t n, R value, hipStream_t st);
+
+int launch_downsample(const float *y, int64_t R_, int T, int f, float *out, hipStream_t st);
+size_t residual_ws_bytes(int F);
+int launch_residual_loss(double *partial_ws, const float *ys, const float *yr, int64_t n, int F,
+                         float *v, double *loss, hipStream_t st);
+int launch_adam(const sbp_state *s, const sbp_adam_params *p, const int32_t *step_dev,
+                int a_softplus, hipStream_t st);
+size_t compact_ws_bytes(int64_t B_cap);
+int launch_compact(void *ws, const float *g, int strict, const BallsP<float> &in,
+                   const int64_t *off_in, int F, int64_t B_cap, const BallsP<float> &out,
+                   int64_t *off_out, const BallsP<float> *m_in, const BallsP<float> *v_in,
+                   const BallsP<float> *m_out, const BallsP<float> *v_out, hipStream_t st);
+int launch_incr(int32_t *p, hipStream_t st);
+int launch_grow(Ctx *c, const sbp_state *in, const sbp_growth_rule *rule, sbp_state *out,
+                int64_t *count, hipStream_t st);
+
+}  // namespace sbp

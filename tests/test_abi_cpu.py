@@ -1,0 +1,200 @@
+"""The C-ABI library loads, exports every entry point include/*.h declares, and
+rejects bad arguments on the host before touching a device (no GPU needed:
+validation runs before the context is looked at, so a NULL context is enough)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+from paper_2601_00551_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w \*]*?\b(sbp\w+)\s*\(", src, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("sbp_simulate_signals", "sbp_adjoint_gradients", "sbp_filter_zero_grad",
+                     "sbp_step", "sbp_downsample", "sbp_grow", "sbp_ctx_create", "sbp_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _abi.lib()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding knows the signature of each
+    assert set(declared_functions()) <= set(_abi.SIGNATURES)
+
+
+def _model(**kw):
+    m = _abi.SbpModel(1.5, 0.025, 0.0, 5.0, 512, 1, 1, 1, 0, 0)
+    for k, v in kw.items():
+        setattr(m, k, v)
+    return m
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+def _array(D=4):
+    return _abi.SbpArray(FAKE.value, FAKE.value, FAKE.value, FAKE.value, FAKE.value, FAKE.value, D, 0)
+
+
+def _balls():
+    return _abi.SbpBalls(FAKE.value, FAKE.value, FAKE.value, FAKE.value, FAKE.value)
+
+
+def _sim(ctx=None, arr=None, balls=None, off=FAKE, F=1, cap=10, model=None, y=FAKE, acc=0):
+    lib = _abi.lib()
+    return lib.sbp_simulate_signals(ctx, ctypes.byref(arr or _array()), ctypes.byref(balls or _balls()),
+                                    off, F, cap, ctypes.byref(model or _model()), y, acc, None)
+
+
+def last():
+    return _abi.lib().sbp_last_error().decode()
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(model=_model(c=0.0)), _abi.SBP_E_DOMAIN),
+    (dict(model=_model(c=-1.5)), _abi.SBP_E_DOMAIN),
+    (dict(model=_model(dt=0.0)), _abi.SBP_E_DOMAIN),
+    (dict(model=_model(f=0)), _abi.SBP_E_DOMAIN),
+    (dict(model=_model(T=0)), _abi.SBP_E_DOMAIN),
+    (dict(model=_model(profile=7)), _abi.SBP_E_DOMAIN),
+    (dict(model=_model(directivity=-1)), _abi.SBP_E_DOMAIN),
+    (dict(model=_model(gauss_K=0.0)), _abi.SBP_E_DOMAIN),
+    (dict(model=_model(a_softplus=2)), _abi.SBP_E_DOMAIN),
+    (dict(model=_model(t0=float("nan"))), _abi.SBP_E_DOMAIN),
+    (dict(F=0), _abi.SBP_E_ARG),
+    (dict(F=65), _abi.SBP_E_ARG),
+    (dict(cap=-1), _abi.SBP_E_ARG),
+    (dict(off=None), _abi.SBP_E_ARG),
+    (dict(y=None), _abi.SBP_E_ARG),
+    (dict(acc=3), _abi.SBP_E_ARG),
+    (dict(arr=_array(D=0)), _abi.SBP_E_ARG),
+    (dict(balls=_abi.SbpBalls(FAKE.value, None, FAKE.value, FAKE.value, FAKE.value)), _abi.SBP_E_ARG),
+    (dict(), _abi.SBP_E_ARG),          # everything valid but the NULL context
+])
+def test_simulate_validation(kw, code):
+    assert _sim(**kw) == code
+    assert last()
+
+
+def test_uniform_profile_ignores_gauss_K():
+    # gauss_K is only checked for the GAUSS profile; with the NULL context last
+    assert _sim(model=_model(profile=0, gauss_K=0.0)) == _abi.SBP_E_ARG
+    assert "ctx" in last()
+
+
+def test_adjoint_validation():
+    lib = _abi.lib()
+    g = _balls()
+    call = lambda mask, grad=g, v=FAKE, model=None: lib.sbp_adjoint_gradients(
+        None, ctypes.byref(_array()), ctypes.byref(_balls()), FAKE, 1, 10,
+        ctypes.byref(model or _model()), v, mask, ctypes.byref(grad), None)
+    assert call(0) == _abi.SBP_E_ARG
+    assert call(64) == _abi.SBP_E_ARG
+    assert call(_abi.ALL, v=None) == _abi.SBP_E_ARG
+    g2 = _abi.SbpBalls(None, None, None, FAKE.value, None)
+    assert call(_abi.P0, grad=g2) == _abi.SBP_E_ARG and "ctx" in last()   # p0-only with others NULL is fine
+    assert call(_abi.ALL, grad=g2) == _abi.SBP_E_ARG and "grad" in last()
+    assert call(_abi.ALL, model=_model(f=-2)) == _abi.SBP_E_DOMAIN
+
+
+def test_downsample_validation():
+    lib = _abi.lib()
+    assert lib.sbp_downsample(None, FAKE, 4, 100, 0, FAKE, None) == _abi.SBP_E_DOMAIN
+    assert lib.sbp_downsample(None, FAKE, 4, 3, 4, FAKE, None) == _abi.SBP_E_DOMAIN
+    assert lib.sbp_downsample(None, FAKE, 0, 100, 2, FAKE, None) == _abi.SBP_E_ARG
+    assert lib.sbp_downsample(None, None, 4, 100, 2, FAKE, None) == _abi.SBP_E_ARG
+    assert lib.sbp_downsample(None, FAKE, 4, 100, 2, FAKE, None) == _abi.SBP_E_ARG
+    assert "ctx" in last()
+
+
+def test_filter_validation():
+    lib = _abi.lib()
+    b = _balls()
+
+    def call(strict=1, m_in=None, y_ref=FAKE, off_out=FAKE):
+        return lib.sbp_filter_zero_grad(None, ctypes.byref(_array()), ctypes.byref(b), FAKE, 1, 10,
+                                        ctypes.byref(_model()), y_ref, strict, ctypes.byref(b), off_out,
+                                        None, m_in, None, None, None, None)
+    assert call(strict=2) == _abi.SBP_E_ARG
+    assert call(y_ref=None) == _abi.SBP_E_ARG
+    assert call(off_out=None) == _abi.SBP_E_ARG
+    assert call(m_in=ctypes.byref(b)) == _abi.SBP_E_ARG and "v_in" in last()  # moments all or none
+    assert call() == _abi.SBP_E_ARG and "ctx" in last()
+
+
+def test_adam_and_step_validation():
+    lib = _abi.lib()
+    st = _abi.SbpState(_balls(), _balls(), _balls(), _balls(), FAKE.value, 1, 0, 10)
+    p = _abi.SbpAdamParams((ctypes.c_float * 5)(0.1, 0.1, 0.1, 0.1, 0.1), 0.9, 0.999, 1e-8, 1, _abi.ALL)
+    assert lib.sbp_adam_update(None, ctypes.byref(st), ctypes.byref(p), None, None) == _abi.SBP_E_ARG
+    assert "ctx" in last()
+    bad = _abi.SbpAdamParams((ctypes.c_float * 5)(0.1, 0.1, 0.1, 0.1, 0.1), 1.0, 0.999, 1e-8, 1, _abi.ALL)
+    assert lib.sbp_adam_update(None, ctypes.byref(st), ctypes.byref(bad), None, None) == _abi.SBP_E_DOMAIN
+    zero_step = _abi.SbpAdamParams((ctypes.c_float * 5)(0.1, 0.1, 0.1, 0.1, 0.1), 0.9, 0.999, 1e-8, 0, _abi.ALL)
+    assert lib.sbp_adam_update(None, ctypes.byref(st), ctypes.byref(zero_step), None, None) == _abi.SBP_E_DOMAIN
+    # with a device step counter the host step is not used
+    assert lib.sbp_adam_update(None, ctypes.byref(st), ctypes.byref(zero_step), FAKE, None) == _abi.SBP_E_ARG
+    st_nog = _abi.SbpState(_balls(), _abi.SbpBalls(), _balls(), _balls(), FAKE.value, 1, 0, 10)
+    assert lib.sbp_adam_update(None, ctypes.byref(st_nog), ctypes.byref(p), None, None) == _abi.SBP_E_ARG
+    assert "grad" in last()
+    assert lib.sbp_step(None, ctypes.byref(_array()), ctypes.byref(st), ctypes.byref(_model()), FAKE, FAKE,
+                        ctypes.byref(p), None, None) == _abi.SBP_E_ARG
+    assert lib.sbp_step(None, ctypes.byref(_array()), ctypes.byref(st), ctypes.byref(_model(T=-1)), FAKE, FAKE,
+                        ctypes.byref(p), FAKE, None) == _abi.SBP_E_DOMAIN
+
+
+def test_grow_and_graph_validation():
+    lib = _abi.lib()
+    st = _abi.SbpState(_balls(), _balls(), _balls(), _balls(), FAKE.value, 1, 0, 10)
+    st2 = _abi.SbpState(_balls(), _balls(), _balls(), _balls(), FAKE.value, 2, 0, 10)
+    rule = _abi.SbpGrowthRule(0.02, 0.02, 0.3, 0.1, 0.5, 0)
+    cnt = ctypes.c_int64()
+    assert lib.sbp_grow(None, ctypes.byref(st), ctypes.byref(rule), ctypes.byref(st2), ctypes.byref(cnt), None) == _abi.SBP_E_ARG
+    assert "F" in last()
+    bad = _abi.SbpGrowthRule(0.02, 0.02, 0.3, 1.5, 0.5, 0)
+    assert lib.sbp_grow(None, ctypes.byref(st), ctypes.byref(bad), ctypes.byref(st), ctypes.byref(cnt), None) == _abi.SBP_E_DOMAIN
+    assert lib.sbp_grow(None, ctypes.byref(st), ctypes.byref(rule), ctypes.byref(st), ctypes.byref(cnt), None) == _abi.SBP_E_ARG
+    assert "ctx" in last()
+    p = _abi.SbpAdamParams((ctypes.c_float * 5)(0.1, 0.1, 0.1, 0.1, 0.1), 0.9, 0.999, 1e-8, 1, _abi.ALL)
+    g = ctypes.c_void_p()
+    assert lib.sbp_step_graph_create(None, ctypes.byref(_array()), ctypes.byref(st), ctypes.byref(_model()),
+                                     FAKE, FAKE, ctypes.byref(p), FAKE, FAKE, 0, ctypes.byref(g), FAKE) == _abi.SBP_E_ARG
+    assert lib.sbp_step_graph_create(None, ctypes.byref(_array()), ctypes.byref(st), ctypes.byref(_model()),
+                                     FAKE, FAKE, ctypes.byref(p), FAKE, FAKE, 2, ctypes.byref(g), None) == _abi.SBP_E_ARG
+    assert "stream" in last()
+    assert lib.sbp_graph_launch(None, None) == _abi.SBP_E_ARG
+    assert lib.sbp_graph_destroy(None) == _abi.SBP_OK
+    assert lib.sbp_ctx_destroy(None) == _abi.SBP_OK
+
+
+def test_tuning_validation():
+    lib = _abi.lib()
+    t = _abi.SbpTuning(4, 512, 2, 0, 4, 256, 2, 0)
+    assert lib.sbp_ctx_set_tuning(None, ctypes.byref(t)) == _abi.SBP_E_ARG and "ctx" in last()
+    for field, val in (("fwd_dets", 0), ("fwd_dets", 17), ("fwd_block", 100), ("adj_bpt", 5), ("adj_grid", -1)):
+        bad = _abi.SbpTuning(4, 512, 2, 0, 4, 256, 2, 0)
+        setattr(bad, field, val)
+        assert lib.sbp_ctx_set_tuning(None, ctypes.byref(bad)) == _abi.SBP_E_DOMAIN, field
+
+
+def test_context_create_rejects_bad_device():
+    lib = _abi.lib()
+    p = ctypes.c_void_p()
+    assert lib.sbp_ctx_create(ctypes.byref(p), -1) == _abi.SBP_E_ARG
+    assert lib.sbp_ctx_create(None, 0) == _abi.SBP_E_ARG
