@@ -1,0 +1,220 @@
+"""Throughput of the sliding-ball reconstruction hot path on one MI355X.
+
+One step is one pass of every step of the hot path over the large workload
+(1,024 transducers on a 45 mm hemispherical cap around a 30 mm cube holding
+2,000,000 balls; 4,096 samples at 40 MHz; Gaussian balls, cosine directivity):
+
+    downsample the measured signal to the level       (Downsample_f, section 4.3)
+    zero-gradient filter of the cloud                 (section 4.2, Algorithm 1)
+    simulate -> residual + loss -> adjoint -> Adam    (section 4.1 / 4.2)
+    plain growth rule (split / destroy / duplicate)   (section 4.1)
+
+value = (balls entering the step) x (transducers) / (seconds per step): every
+(ball, transducer) pair is carried through the whole pass once per step.
+Inputs are resident in HBM before the timed region; every kernel is timed with
+HIP events on the stream it runs on.  Prints ONE JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# --- algorithmic VALU lane-operations (FP32-equivalent issue slots; a
+# transcendental counts 4, the quarter rate of sqrt / rcp / exp on CDNA) -----
+OPS_GEOMETRY = 31        # per pair: offset, rho (sqrt), 1/rho, e_hat, cosine, window, amplitude
+OPS_FWD_EDGE = 12        # per edge: u, u^2 k, exp, support clamp, scale, bin difference, accumulate
+OPS_ADJ_EDGE = 13        # per edge: u, u^2 k, exp, support select, three weighted sums
+OPS_ADJ_PAIR = 26        # per pair: S0..S2, dL/dp0, dL/da, radial and directivity terms
+OPS_FLT_EDGE = 10        # per edge (p0 only): u, u^2 k, exp, select, one weighted sum
+OPS_FLT_PAIR = 3
+VALU_PEAK = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock = 3.93e13 lane-ops/s
+
+
+def edges_per_pair(a_sup, cdt):
+    """Expected edges of a pair: the support spans 2 a_sup / (c dt) bins, plus one."""
+    return 2.0 * a_sup / cdt + 1.0
+
+
+def cpu_baseline(wl, model_kw, n_balls_sample, rng_seed=0):
+    """The FP64 oracle on a bounded sample of the same workload: forward + VJP
+    of n_balls_sample balls against every transducer at the full record."""
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(rng_seed)
+    idx = np.sort(rng.choice(len(wl.init["x"]), size=n_balls_sample, replace=False))
+    balls = {k: v[idx] for k, v in wl.init.items()}
+    tm = oracle.Time(c=model_kw["c"], dt=model_kw["dt"], T=model_kw["T"], f=1,
+                     profile=oracle.GAUSS, directivity=oracle.COS)
+    D = len(wl.array["qx"])
+    t0 = time.perf_counter()
+    y = oracle.simulate(balls, wl.array, tm)
+    t1 = time.perf_counter()
+    v = rng.normal(size=y.shape)
+    oracle.vjp(balls, wl.array, tm, v)
+    t2 = time.perf_counter()
+    pairs = n_balls_sample * D
+    return {"value": pairs / (t2 - t0), "unit": "pairs/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n_balls_sample} of the {len(wl.init['x'])} balls x all {D} transducers, "
+                      f"T={model_kw['T']}: oracle forward {t1 - t0:.2f} s + VJP {t2 - t1:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--balls", type=int, default=2_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=12000, help="balls in the oracle sample (0 = skip)")
+    ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2601_00551_amd", "tuning.json"))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design only, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2601_00551_amd import api, synth
+    from paper_2601_00551_amd import autotune
+
+    dev = torch.device("cuda:0")
+    ctx = api.Context(0)
+    wl = synth.large_config(n_balls=args.balls)
+    T, dt, c = wl.T, wl.dt, 1.5
+    model = api.Model(c=c, dt=dt, T=T, f=1, profile=api.PROFILE_GAUSS, directivity=api.DIR_COS)
+    tuned = autotune.apply_cached(ctx, args.tuning, model, len(wl.array["qx"]), args.balls)
+    A = {k: torch.as_tensor(v, device=dev) for k, v in wl.array.items()}
+    B = args.balls
+    D = len(wl.array["qx"])
+
+    # measured signal: the cloud with p0 scaled up by 1.5 (so that the filter
+    # keeps it), plus 5 % noise; the estimate starts from p0 as drawn
+    rng = np.random.default_rng(3000)
+    gt = {k: torch.as_tensor(v, device=dev) for k, v in wl.init.items()}
+    gt["p0"] = gt["p0"] * 1.5
+    y_real = api.simulate_signals(ctx, A, gt, model)
+    sigma = 0.05 * float(y_real.abs().max())
+    y_real += sigma * torch.as_tensor(rng.normal(size=tuple(y_real.shape)).astype(np.float32), device=dev)
+    del gt
+    cap = B
+    st = [api.State(wl.init, capacity=cap, device=dev), api.State({k: np.zeros(0) for k in api.PARAMS},
+                                                                 ball_off=[0, 0], capacity=cap, device=dev)]
+    y_k = torch.empty_like(y_real)
+    y_work = torch.empty_like(y_real)
+    g_buf = torch.empty(cap, device=dev)
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    rule = api.GrowthRule(destroy_frac=0.02, a_min=0.02, a_split=0.3, dup_frac=0.0)
+    prm = api.AdamParams(lr=(0.005, 0.005, 0.005, 0.02, 0.002), step=1)
+    names = ("downsample", "filter", "forward", "residual", "adjoint", "adam", "grow")
+    times = {n: [] for n in names}
+    counts = {"in": [], "kept": []}
+    cur = 0
+
+    def one_step(record):
+        nonlocal cur
+        a, b = st[cur], st[1 - cur]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)]
+        ev[0].record()
+        api.downsample(ctx, y_real, 1, out=y_k)
+        ev[1].record()
+        # filter a -> b (balls and moments compacted, p0 kept)
+        out, off_out, _, _ = api.filter_zero_grad(
+            ctx, A, a.balls, model, y_k, ball_off=a.ball_off, strict=True, out=b.balls,
+            off_out=b.ball_off, g_out=g_buf, B_cap=a.B_cap, moments=(a.m, a.v),
+            moments_out=(b.m, b.v))
+        ev[2].record()
+        api.simulate_signals(ctx, A, b.balls, model, ball_off=b.ball_off, y=y_work, B_cap=b.B_cap)
+        ev[3].record()
+        api.residual_loss(ctx, y_work, y_k, v_out=y_work, loss=loss)
+        ev[4].record()
+        api.adjoint_gradients(ctx, A, b.balls, model, y_work, mask=api.ALL, ball_off=b.ball_off,
+                              grad=b.grad, B_cap=b.B_cap)
+        ev[5].record()
+        api.adam_update(ctx, b, prm)
+        ev[6].record()
+        new, cnt = api.grow(ctx, b, rule, capacity=cap)
+        ev[7].record()
+        # the grown cloud becomes the next step's input (moments carried by grow)
+        for k in api.PARAMS:
+            st[cur].balls[k], new.balls[k] = new.balls[k], st[cur].balls[k]
+            st[cur].m[k], new.m[k] = new.m[k], st[cur].m[k]
+            st[cur].v[k], new.v[k] = new.v[k], st[cur].v[k]
+        st[cur].ball_off.copy_(new.ball_off)
+        prm.step += 1
+        if record:
+            torch.cuda.synchronize()
+            for i, n in enumerate(names):
+                times[n].append(ev[i].elapsed_time(ev[i + 1]))
+            counts["kept"].append(int(b.ball_off[-1].item()))
+
+    for _ in range(args.warmup):
+        counts["in"].append(st[cur].count())
+        one_step(True)
+    for n in names:
+        times[n].clear()
+    counts["kept"].clear()
+    n_in = [st[cur].count()]
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step(True)
+        n_in.append(st[cur].count())
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = e0.elapsed_time(e1) / args.steps
+    pairs_in = float(np.mean(n_in[:-1])) * D
+    value = pairs_in / (ms_step * 1e-3)
+
+    avg = {n: float(np.mean(times[n])) for n in names}
+    kept = float(np.mean(counts["kept"]))
+    E = edges_per_pair(5.0 * 0.15, c * dt)
+    alg = {
+        "forward": kept * D * (OPS_GEOMETRY + E * OPS_FWD_EDGE),
+        "adjoint": kept * D * (OPS_GEOMETRY + OPS_ADJ_PAIR + (E + 1) * OPS_ADJ_EDGE),
+        "filter": float(np.mean(n_in[:-1])) * D * (OPS_GEOMETRY + OPS_FLT_PAIR + (E + 1) * OPS_FLT_EDGE),
+    }
+    dominant = max(("forward", "adjoint", "filter"), key=lambda n: avg[n])
+    achieved = alg[dominant] / (avg[dominant] * 1e-3)
+    fwd_adj = kept * D / ((avg["forward"] + avg["adjoint"]) * 1e-3)
+    line = {
+        "metric": "fwd+adjoint ball-detector pairs/s",
+        "value": value,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "balls": B, "transducers": D, "samples": T,
+                   "sampling_MHz": round(1.0 / dt), "profile": "gauss", "directivity": "cos",
+                   "step": "downsample+filter+simulate+residual+adjoint+adam+grow"},
+        "kernel_ms": {n: round(avg[n], 4) for n in names},
+        "fwd_adj_pairs_per_s": fwd_adj,
+        "balls_kept_by_filter": kept,
+        "roofline": {"bound": "alu", "kernel": dominant, "achieved": achieved / 1e12,
+                     "peak": VALU_PEAK / 1e12, "unit": "TOP/s", "frac": achieved / VALU_PEAK,
+                     "traffic": None},
+        "tuning": tuned,
+        "wall_s": wall,
+    }
+    if args.cpu_sample > 0:
+        line["cpu_baseline"] = cpu_baseline(wl, {"c": c, "dt": dt, "T": T}, args.cpu_sample)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -225,7 +225,8 @@ def downsample(ctx, y, f: int, out=None, stream=None):
 
 
 def filter_zero_grad(ctx, arr, balls, model: Model, y_ref, ball_off=None, strict=True,
-                     moments=None, out=None, off_out=None, g_out=None, B_cap=None, stream=None):
+                     moments=None, out=None, off_out=None, g_out=None, B_cap=None, stream=None,
+                     moments_out=None):
     """sbp_filter_zero_grad.  Returns (kept balls, off_out, g, out moments or None).
 
     The kept balls sit in the first off_out[F] entries of the returned arrays
@@ -244,8 +245,11 @@ def filter_zero_grad(ctx, arr, balls, model: Model, y_ref, ball_off=None, strict
     m_in = v_in = m_out = v_out = None
     if moments is not None:
         m_in, v_in = moments
-        m_out = {k: torch.empty_like(m_in[k]) for k in PARAMS}
-        v_out = {k: torch.empty_like(v_in[k]) for k in PARAMS}
+        if moments_out is not None:
+            m_out, v_out = moments_out
+        else:
+            m_out = {k: torch.empty_like(m_in[k]) for k in PARAMS}
+            v_out = {k: torch.empty_like(v_in[k]) for k in PARAMS}
     ref = lambda b: None if b is None else ctypes.byref(balls_struct(b))
     check(lib().sbp_filter_zero_grad(
         ctx.ptr, ctypes.byref(array_struct(arr)), ctypes.byref(balls_struct(balls)), _p(off), F, cap,

@@ -1,0 +1,159 @@
+"""Launch-shape autotuner for the forward and adjoint kernels.
+
+For a workload shape (profile, directivity, transducers D, samples T_k, balls
+B) it times candidate launch shapes of the two kernels on the real inputs,
+keeps the fastest of each, and caches the choice in a JSON file keyed by the
+device architecture and a bucketed shape.  apply_cached() looks a shape up
+(nearest bucket of the same profile / directivity if there is no exact entry)
+and installs it on a context.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+
+FWD_SPACE = {"fwd_dets": (1, 2, 4, 8), "fwd_block": (256, 512), "fwd_bpt": (1, 2, 4)}
+ADJ_SPACE = {"adj_dets": (2, 4, 8), "adj_block": (128, 256, 512), "adj_bpt": (1, 2, 4)}
+
+
+def _bucket(n: int) -> int:
+    return 1 << max(0, int(math.ceil(math.log2(max(1, n)))))
+
+
+def shape_key(arch: str, model, D: int, B: int) -> str:
+    return f"{arch}|p{model.profile}d{model.directivity}|D{_bucket(D)}|T{model.T}|B{_bucket(B)}"
+
+
+def _arch() -> str:
+    import torch
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def load(path: str) -> dict:
+    if path and os.path.exists(path):
+        with open(path) as fh:
+            return json.load(fh)
+    return {}
+
+
+def lookup(cache: dict, key: str):
+    if key in cache:
+        return cache[key]
+    arch, pd, Dk, Tk, Bk = key.split("|")
+    best, best_d = None, None
+    for k, v in cache.items():
+        a2, pd2, D2, T2, B2 = k.split("|")
+        if a2 != arch or pd2 != pd:
+            continue
+        d = sum(abs(math.log2(int(x[1:])) - math.log2(int(y[1:]))) for x, y in
+                ((Dk, D2), (Tk, T2), (Bk, B2)))
+        if best_d is None or d < best_d:
+            best, best_d = v, d
+    return best
+
+
+def apply_cached(ctx, path: str, model, D: int, B: int) -> dict:
+    """Install the cached launch shape for this workload; returns what is in use."""
+    cache = load(path)
+    entry = lookup(cache, shape_key(_arch(), model, D, B)) if cache else None
+    if entry:
+        ctx.tuning = {k: int(v) for k, v in entry.items() if k in ctx.tuning}
+    return ctx.tuning
+
+
+def _time(fn, reps: int) -> float:
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(ctx, arr, balls, model, v, reps: int = 3, path: str | None = None, log=print) -> dict:
+    """Sweep FWD_SPACE and ADJ_SPACE on (arr, balls, model) with cotangent v;
+    store the winners under the workload's key in `path` and install them."""
+    from . import api
+    D = arr["qx"].numel()
+    B = balls["x"].numel()
+    y = api.simulate_signals(ctx, arr, balls, model)
+    grad = {k: balls[k].new_empty(B) for k in api.PARAMS}
+    base = ctx.tuning
+    results = {}
+    best_f, best_a = None, None
+    for vals in itertools.product(*FWD_SPACE.values()):
+        t = dict(zip(FWD_SPACE, vals))
+        if t["fwd_dets"] * model.T * 8 > 150 * 1024 and t["fwd_dets"] > 1:   # FP64 rows
+            continue
+        ctx.tuning = t
+        ms = _time(lambda: api.simulate_signals(ctx, arr, balls, model, y=y), reps)
+        results[json.dumps(t)] = ms
+        log(f"forward {t}: {ms:.3f} ms")
+        if best_f is None or ms < best_f[1]:
+            best_f = (t, ms)
+    ctx.tuning = best_f[0]
+    for vals in itertools.product(*ADJ_SPACE.values()):
+        t = dict(zip(ADJ_SPACE, vals))
+        if t["adj_dets"] * (model.T + 1) * 4 > 150 * 1024:
+            continue
+        ctx.tuning = t
+        ms = _time(lambda: api.adjoint_gradients(ctx, arr, balls, model, v, grad=grad), reps)
+        results[json.dumps(t)] = ms
+        log(f"adjoint {t}: {ms:.3f} ms")
+        if best_a is None or ms < best_a[1]:
+            best_a = (t, ms)
+    chosen = dict(base)
+    chosen.update(best_f[0])
+    chosen.update(best_a[0])
+    ctx.tuning = chosen
+    if path:
+        cache = load(path)
+        cache[shape_key(_arch(), model, D, B)] = chosen
+        with open(path + ".tmp", "w") as fh:
+            json.dump(cache, fh, indent=1, sort_keys=True)
+        os.replace(path + ".tmp", path)
+    return {"chosen": chosen, "forward_ms": best_f[1], "adjoint_ms": best_a[1], "all": results}
+
+
+def main(argv=None):
+    """Tune the launch shapes for a named workload: python -m paper_2601_00551_amd.autotune."""
+    import argparse
+    import numpy as np
+    import torch
+    from . import api, synth
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", choices=("large", "conformal"), default="large")
+    ap.add_argument("--balls", type=int, default=2_000_000)
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json"))
+    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--levels", default="1")
+    args = ap.parse_args(argv)
+    dev = torch.device("cuda:0")
+    ctx = api.Context(0)
+    if args.workload == "large":
+        wl = synth.large_config(n_balls=args.balls)
+        balls = wl.init
+    else:
+        wl = synth.conformal_config()
+        balls = wl.init
+    A = {k: torch.as_tensor(v, device=dev) for k, v in wl.array.items()}
+    Bt = {k: torch.as_tensor(v, device=dev) for k, v in balls.items()}
+    rng = np.random.default_rng(7)
+    for f in (int(x) for x in args.levels.split(",")):
+        model = api.Model(c=1.5, dt=wl.dt, T=wl.T // f, f=f, profile=api.PROFILE_GAUSS,
+                          directivity=api.DIR_COS)
+        v = torch.as_tensor(rng.normal(size=(1, len(wl.array["qx"]), model.T)).astype(np.float32), device=dev)
+        res = tune(ctx, A, Bt, model, v, reps=args.reps, path=args.out, log=lambda s: print(s, flush=True))
+        print(json.dumps({"workload": wl.name, "f": f, "chosen": res["chosen"],
+                          "forward_ms": res["forward_ms"], "adjoint_ms": res["adjoint_ms"]}), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

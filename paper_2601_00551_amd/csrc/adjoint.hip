@@ -19,16 +19,20 @@ namespace sbp {
 
 constexpr int kMaxBpt = 4;
 
+// Accumulates the pair's edges in the staged tile [tlo, thi) (wr[m - tlo]).
+// Everything below is linear in (S0, S1, S2), so tiles simply add up.
 template <typename R, int PROF, int DIR, bool FULL>
 __device__ inline void adj_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx, R ny, R nz,
-                                const Level &lc, const R *__restrict__ wr, R acc[5]) {
+                                const Level &lc, int tlo, int thi, const R *__restrict__ wr,
+                                R acc[5]) {
     PairG<R> g;
     if (!pair_geometry<R, DIR>(b.x, b.y, b.z, b.w, qx, qy, qz, nx, ny, nz, lc, g)) return;
     const double lo = floor((g.s - b.w) * lc.inv_cdt);
     const double hi = floor((g.s + b.w) * lc.inv_cdt) + 1.0;
-    if (hi < 0.0 || lo > (double)lc.T) return;
-    const int mb = lo < 0.0 ? 0 : (int)lo;
-    const int me = hi > (double)lc.T ? lc.T : (int)hi;
+    if (hi < (double)tlo || lo > (double)(thi - 1)) return;
+    const int mb = lo < (double)tlo ? tlo : (int)lo;
+    const int me = hi > (double)(thi - 1) ? thi - 1 : (int)hi;
+    wr -= tlo;
     const R eK = LevelR<R>::eK(lc);
     const R cdt = LevelR<R>::cdt(lc);
     const R u0 = (R)(g.s - (double)mb * lc.cdt);
@@ -88,7 +92,7 @@ __device__ inline void adj_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx,
 template <typename R, int PROF, int DIR, bool FULL>
 __global__ __launch_bounds__(512) void k_adjoint(ArrayP<R> arr, BallsP<R> balls,
                                                  const int64_t *__restrict__ ball_off, int F,
-                                                 int ds, int bpt, Level lc,
+                                                 int ds, int TT, int bpt, Level lc,
                                                  const R *__restrict__ v, R vscale,
                                                  uint32_t mask, BallsP<R> grad) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -132,25 +136,28 @@ __global__ __launch_bounds__(512) void k_adjoint(ArrayP<R> arr, BallsP<R> balls,
         const R *vf = v + (int64_t)f * D * (int64_t)T;
         for (int d0 = 0; d0 < D; d0 += ds) {
             const int nd = min(ds, D - d0);
-            __syncthreads();
-            for (int dl = 0; dl < nd; ++dl) {
-                const R *vr = vf + (int64_t)(d0 + dl) * T;
-                R *wr = rows + (int64_t)dl * (T + 1);
-                for (int m = tid; m <= T; m += nth) {
-                    const R cur = m < T ? vr[m] : R(0);
-                    const R prv = m > 0 ? vr[m - 1] : R(0);
-                    wr[m] = vscale * (cur - prv);
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int jb = 0; jb < kMaxBpt; ++jb) {
-                if (!act[jb]) continue;
+            for (int tlo = 0; tlo <= T; tlo += TT) {
+                const int thi = min(tlo + TT, T + 1);
+                __syncthreads();
                 for (int dl = 0; dl < nd; ++dl) {
-                    const int d = __builtin_amdgcn_readfirstlane(d0 + dl);
-                    adj_pair<R, PROF, DIR, FULL>(b[jb], arr.qx[d], arr.qy[d], arr.qz[d], arr.nx[d],
-                                                 arr.ny[d], arr.nz[d], lc,
-                                                 rows + (int64_t)dl * (T + 1), acc[jb]);
+                    const R *vr = vf + (int64_t)(d0 + dl) * T;
+                    R *wr = rows + (int64_t)dl * TT;
+                    for (int m = tlo + tid; m < thi; m += nth) {
+                        const R cur = m < T ? vr[m] : R(0);
+                        const R prv = m > 0 ? vr[m - 1] : R(0);
+                        wr[m - tlo] = vscale * (cur - prv);
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int jb = 0; jb < kMaxBpt; ++jb) {
+                    if (!act[jb]) continue;
+                    for (int dl = 0; dl < nd; ++dl) {
+                        const int d = __builtin_amdgcn_readfirstlane(d0 + dl);
+                        adj_pair<R, PROF, DIR, FULL>(b[jb], arr.qx[d], arr.qy[d], arr.qz[d],
+                                                     arr.nx[d], arr.ny[d], arr.nz[d], lc, tlo, thi,
+                                                     rows + (int64_t)dl * TT, acc[jb]);
+                    }
                 }
             }
         }
@@ -178,15 +185,16 @@ static int run_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
                        R vscale, uint32_t mask, const BallsP<R> &grad, hipStream_t st) {
     auto kern = k_adjoint<R, PROF, DIR, FULL>;
     const size_t reserve = 2 * (SBP_MAX_FRAMES + 1) * sizeof(int64_t) + 256;
-    const size_t row_bytes = (size_t)(lc.T + 1) * sizeof(R);
+    const size_t avail = c->lds_max > reserve ? c->lds_max - reserve : 0;
     int ds = c->tuning.adj_dets;
-    while (ds > 1 && ds * row_bytes + reserve > c->lds_max) --ds;
-    if (ds * row_bytes + reserve > c->lds_max)
-        return fail(SBP_E_DOMAIN, "T = %d samples do not fit one LDS row", lc.T);
     if (ds > arr.D) ds = arr.D;
+    // edges 0..T staged per pass: the whole record if the ds rows fit
+    int64_t TT = (int64_t)(avail / ((size_t)ds * sizeof(R)));
+    if (TT > (int64_t)lc.T + 1) TT = (int64_t)lc.T + 1;
+    if (TT < (int64_t)lc.T + 1 && TT < 64) return fail(SBP_E_DOMAIN, "LDS too small for %d rows", ds);
     const int block = c->tuning.adj_block;
     const int bpt = c->tuning.adj_bpt;
-    const size_t lds = (size_t)ds * row_bytes;
+    const size_t lds = (size_t)ds * (size_t)TT * sizeof(R);
     SBP_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds));
     int grid = c->tuning.adj_grid;
@@ -200,8 +208,8 @@ static int run_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
     const int64_t max_items = (B_cap + CH - 1) / CH + F;
     if (grid > max_items) grid = (int)max_items;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, arr, balls, ball_off, F, ds, bpt,
-                       lc, v, vscale, mask, grad);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, arr, balls, ball_off, F, ds,
+                       (int)TT, bpt, lc, v, vscale, mask, grad);
     SBP_HIP(hipGetLastError());
     return SBP_OK;
 }

@@ -17,6 +17,8 @@
 //   5. per-block sums of (key > threshold, key == threshold) -> exclusive scan
 //   6. host reads the total (one synchronisation) and checks the capacity
 //   7. scatter: survivors and children in input order, then the clones
+#include <climits>
+
 #include "sbp_internal.hpp"
 
 namespace sbp {
@@ -93,12 +95,21 @@ __device__ inline Cls classify(const GrowIn &in, const sbp_growth_rule &r, const
     __syncthreads();                                       \
     const int64_t count = s_off[in.F];
 
+// Grid (slices, F): block (s, f) reduces a slice of frame f, then one atomic.
 __global__ void k_g_max(GrowIn in, int *pmax_key) {
-    LOAD_OFFSETS();
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int f = frame_of(s_off, in.F, i);
-        atomicMax(pmax_key + f, ordered_key(in.p0[i]));
+    __shared__ int s_red[kGb / 64];
+    const int f = blockIdx.y;
+    const int64_t lo = in.off[f], hi = in.off[f + 1];
+    int m = INT_MIN;
+    for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, ordered_key(in.p0[i]));
+    for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_down(m, o, 64));
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kGb / 64; ++w) m = max(m, s_red[w]);
+        if (m != INT_MIN) atomicMax(pmax_key + f, m);
     }
 }
 
@@ -203,28 +214,27 @@ __global__ void k_g_need(GrowIn in, sbp_growth_rule r, GrowWs ws, int nblk) {
     ws.prefix[f] = 0;
 }
 
+// Histogram of the current 8-bit digit of the candidates' keys whose higher
+// digits match the threshold prefix; LDS counts per frame, flushed once.
 __global__ void k_g_hist(GrowIn in, sbp_growth_rule r, GrowWs ws, int shift) {
     LOAD_OFFSETS();
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < count;
-         base += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = base + threadIdx.x;
-        bool ok = false;
-        int f = 0;
-        uint64_t key = 0;
-        if (i < count) {
-            f = frame_of(s_off, in.F, i);
-            if (ws.kneed[f] > 0) {
-                const Cls k = classify(in, r, ws.pmax_key, f, i);
-                if (k.cand) {
-                    key = (uint64_t)__double_as_longlong(dup_key(in, i));
-                    const uint64_t hi_mask = shift == 56 ? 0ull : (~0ull << (shift + 8));
-                    ok = (key & hi_mask) == (ws.prefix[f] & hi_mask);
-                }
-            }
-        }
-        if (ok) atomicAdd((unsigned long long *)(ws.hist + (int64_t)f * 256 + ((key >> shift) & 255)),
-                          1ull);
+    extern __shared__ unsigned s_hist[];   // [F][256]
+    for (int i = threadIdx.x; i < 256 * in.F; i += blockDim.x) s_hist[i] = 0u;
+    __syncthreads();
+    const uint64_t hi_mask = shift == 56 ? 0ull : (~0ull << (shift + 8));
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int f = frame_of(s_off, in.F, i);
+        if (ws.kneed[f] <= 0) continue;
+        const Cls k = classify(in, r, ws.pmax_key, f, i);
+        if (!k.cand) continue;
+        const uint64_t key = (uint64_t)__double_as_longlong(dup_key(in, i));
+        if ((key & hi_mask) == (ws.prefix[f] & hi_mask))
+            atomicAdd(&s_hist[f * 256 + (int)((key >> shift) & 255)], 1u);
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 256 * in.F; i += blockDim.x)
+        if (s_hist[i]) atomicAdd((unsigned long long *)(ws.hist + i), (unsigned long long)s_hist[i]);
 }
 
 // Choose the digit of the k-th largest key; kneed becomes the rank within it.
@@ -426,7 +436,7 @@ int launch_grow(Ctx *c, const sbp_state *in, const sbp_growth_rule *rule, sbp_st
     if (rc2) return rc2;
     rc2 = launch_fill<uint64_t>(ws.prefix, F, 0ull, st);
     if (rc2) return rc2;
-    hipLaunchKernelGGL(k_g_max, dim3(grid), dim3(kGb), 0, st, gi, ws.pmax_key);
+    hipLaunchKernelGGL(k_g_max, dim3(256, F), dim3(kGb), 0, st, gi, ws.pmax_key);
     SBP_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_g_blocksum, dim3(grid), dim3(kGb), 0, st, gi, *rule, ws, nblk, 1);
     SBP_HIP(hipGetLastError());
@@ -436,8 +446,8 @@ int launch_grow(Ctx *c, const sbp_state *in, const sbp_growth_rule *rule, sbp_st
     SBP_HIP(hipGetLastError());
     if (with_dup) {
         for (int shift = 56; shift >= 0; shift -= 8) {
-            hipLaunchKernelGGL(k_g_hist, dim3(grid < 2048 ? grid : 2048), dim3(kGb), 0, st, gi, *rule,
-                               ws, shift);
+            hipLaunchKernelGGL(k_g_hist, dim3(grid < 1024 ? grid : 1024), dim3(kGb),
+                               (size_t)256 * F * sizeof(unsigned), st, gi, *rule, ws, shift);
             SBP_HIP(hipGetLastError());
             hipLaunchKernelGGL(k_g_pick, dim3(1), dim3(SBP_MAX_FRAMES), 0, st, ws, F, shift);
             SBP_HIP(hipGetLastError());
