@@ -72,7 +72,19 @@ def main():
     ap.add_argument("--balls", type=int, default=2_000_000)
     ap.add_argument("--cpu-sample", type=int, default=12000, help="balls in the oracle sample (0 = skip)")
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2601_00551_amd", "tuning.json"))
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (the reference for HBM counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 28, device="cuda:0")     # 1 GiB of float32
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
+                          "launches": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design only, see DESIGN.md)", file=sys.stderr)

@@ -31,7 +31,9 @@
  *     validated on the host BEFORE anything is enqueued, in the order: pointers
  *     and sizes, model fields, then the context; so a failed call enqueues
  *     nothing.  NaN inputs propagate to NaN outputs; there are no device-side
- *     checks.  A context is used by one host thread at a time.
+ *     checks.  A context is used by one host thread and one stream at a time
+ *     (its scratch memory is shared by the calls made through it); a captured
+ *     graph owns its own workspace and may run on another stream.
  */
 #ifndef SBP_H
 #define SBP_H

@@ -7,9 +7,10 @@
 // differenced, w_m = v_m - v_{m-1} (v_{-1} = v_T = 0), so that by summation by
 // parts
 //     sum_n v_n (h(u_n) - h(u_{n+1})) = sum_m h(u_m) w_m
-// for any edge function h; one LDS read per edge then serves the three sums
-//     A0 = sum w max(q, 0)-part, A1 = sum w psi'(u), A2 = sum w d psi / d a
-// from which the pair's gradients follow in closed form:
+// for any edge function h; one LDS read per support edge then serves the sums
+// of w psi(u), w psi'(u) and w d psi / d a (psi, psi' = u fhat(u) and
+// d psi / d a are written out per profile in adj_pair), from which the pair's
+// gradients follow in closed form:
 //     G = D / (2 rho c dt),  dL/dp0 = G S0,  dL/da = p0 G S2,
 //     dL/dr = p0 G (S1 - S0 / rho) e_hat + p0 S0 / (2 rho c dt) (n_hat - D e_hat) / rho
 // (the last term only for COS directivity and D > 0).
@@ -19,57 +20,75 @@ namespace sbp {
 
 constexpr int kMaxBpt = 4;
 
-// Accumulates the pair's edges in the staged tile [tlo, thi) (wr[m - tlo]).
-// Everything below is linear in (S0, S1, S2), so tiles simply add up.
+// Edges per exact restart of the Gaussian recurrence below.
+constexpr int kRestart = 16;
+
+// Accumulates the pair's support edges in the staged tile [tlo, thi)
+// (wr[m - tlo]).  Everything is linear in (S0, S1, S2), so tiles add up.
+//
+// GAUSS: along the edges u_{m+1} = u_m - c, so e_m = exp(-u_m^2 / (2 a^2))
+// obeys e_{m+1} = e_m g_m with g_{m+1} = g_m h, h = exp(-c^2 / a^2): two
+// multiplies per edge instead of an exponential.  Both are recomputed
+// exactly every kRestart edges (relative drift below 1e-5 in between).
 template <typename R, int PROF, int DIR, bool FULL>
 __device__ inline void adj_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx, R ny, R nz,
                                 const Level &lc, int tlo, int thi, const R *__restrict__ wr,
                                 R acc[5]) {
     PairG<R> g;
     if (!pair_geometry<R, DIR>(b.x, b.y, b.z, b.w, qx, qy, qz, nx, ny, nz, lc, g)) return;
-    const double lo = floor((g.s - b.w) * lc.inv_cdt);
-    const double hi = floor((g.s + b.w) * lc.inv_cdt) + 1.0;
-    if (hi < (double)tlo || lo > (double)(thi - 1)) return;
+    // support edges: |u_m| < w  <=>  (s - w) / (c dt) < m < (s + w) / (c dt)
+    const double lo = floor((g.s - (double)b.w) * lc.inv_cdt) + 1.0;
+    const double hi = ceil((g.s + (double)b.w) * lc.inv_cdt) - 1.0;
+    if (hi < (double)tlo || lo > (double)(thi - 1) || hi < lo) return;
     const int mb = lo < (double)tlo ? tlo : (int)lo;
     const int me = hi > (double)(thi - 1) ? thi - 1 : (int)hi;
     wr -= tlo;
-    const R eK = LevelR<R>::eK(lc);
-    const R cdt = LevelR<R>::cdt(lc);
-    const R u0 = (R)(g.s - (double)mb * lc.cdt);
-    R A0 = R(0), A1 = R(0), A2 = R(0);
-    R j = R(0);
-    for (int m = mb; m <= me; ++m, j += R(1)) {
-        const R u = fma(-j, cdt, u0);
-        const R wv = wr[m];
-        const R t = u * u;
-        if (PROF == GAUSS) {
-            const R e = ex2(t * b.q0);
-            const R we = e > eK ? wv : R(0);
-            A0 = fma(we, e - eK, A0);
-            if (FULL) {
-                const R wee = we * e;
-                A1 = fma(wee, u, A1);
-                A2 = fma(wee, t, A2);
+    const R c = LevelR<R>::cdt(lc);
+    R P = R(0), W = R(0), A1 = R(0), A2 = R(0);
+    if (PROF == GAUSS) {
+        for (int m0 = mb; m0 <= me; m0 += kRestart) {
+            R u = (R)(g.s - (double)m0 * lc.cdt);
+            R e = ex2(u * u * b.q0);
+            R gq = ex2(b.q0 * c * (c - R(2) * u));
+            const int m1 = min(m0 + kRestart - 1, me);
+            for (int m = m0; m <= m1; ++m) {
+                const R w = wr[m];
+                W += w;
+                if (FULL) {
+                    const R we = w * e;
+                    P += we;
+                    const R wu = we * u;
+                    A1 += wu;
+                    A2 = fma(wu, u, A2);
+                    u -= c;
+                } else {
+                    P = fma(w, e, P);
+                }
+                e *= gq;
+                gq *= b.h;
             }
-        } else {
-            const R q = b.q0 - t;
-            const R we = q > R(0) ? wv : R(0);
-            A0 = fma(we, q, A0);
-            if (FULL) {
-                A1 = fma(we, u, A1);
-                A2 += we;
-            }
+        }
+    } else {
+        R u = (R)(g.s - (double)mb * lc.cdt);
+        for (int m = mb; m <= me; ++m) {
+            const R w = wr[m];
+            W += w;
+            const R wu = w * u;
+            A1 += wu;
+            P = fma(wu, u, P);     // sum w u^2
+            u -= c;
         }
     }
     R S0, S1, S2;
     if (PROF == GAUSS) {
+        const R A0 = P - LevelR<R>::eK(lc) * W;          // sum w (e - e^{-K^2/2})
         S0 = -(b.a * b.a) * A0;
         S1 = A1;
         S2 = R(-2) * b.a * A0 - A2 / b.a;
     } else {
-        S0 = R(-0.5) * A0;
+        S0 = R(-0.5) * (b.q0 * W - P);                   // -(1/2) sum w (a^2 - u^2)
         S1 = A1;
-        S2 = -b.a * A2;
+        S2 = -b.a * W;
     }
     const R G = g.dir * LevelR<R>::inv2cdt(lc) * g.inv_rho;
     acc[3] = fma(G, S0, acc[3]);
@@ -90,7 +109,7 @@ __device__ inline void adj_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx,
 }
 
 template <typename R, int PROF, int DIR, bool FULL>
-__global__ __launch_bounds__(512) void k_adjoint(ArrayP<R> arr, BallsP<R> balls,
+__global__ __launch_bounds__(512, 4) void k_adjoint(ArrayP<R> arr, BallsP<R> balls,
                                                  const int64_t *__restrict__ ball_off, int F,
                                                  int ds, int TT, int bpt, Level lc,
                                                  const R *__restrict__ v, R vscale,

@@ -15,7 +15,7 @@ struct sbp_ctx {
 struct sbp_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    void *ws = nullptr;  // residual partial sums owned by the graph
+    void *ws = nullptr;  // residual partial sums and the forward's bound, owned by the graph
     int device = 0;
 };
 
@@ -195,11 +195,12 @@ static int check_tuning(const sbp_tuning *t) {
 // One iteration, shared by sbp_step and the graph capture.
 static int step_body(Ctx *c, const sbp_array *arr, sbp_state *s, const sbp_model *model,
                      const float *y_ref, float *y_work, const sbp_adam_params *p,
-                     const int32_t *step_dev, double *loss, double *partial, hipStream_t st) {
+                     const int32_t *step_dev, double *loss, double *partial, unsigned *bound,
+                     hipStream_t st) {
     const ArrayP<float> a = arrp<float>(arr);
     const BallsP<float> b = ballsp<float>(&s->balls);
     const BallsP<float> g = ballsp<float>(&s->grad);
-    int rc = launch_forward<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 0, st);
+    int rc = launch_forward<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 0, bound, st);
     if (rc) return rc;
     const int64_t n = (int64_t)arr->D * model->T;
     rc = launch_residual_loss(partial, y_work, y_ref, n, s->F, y_work, loss, st);
@@ -234,7 +235,12 @@ int sbp_ctx_create(sbp_ctx **out, int device) {
     size_t lds = prop.sharedMemPerBlock;
     if (prop.maxSharedMemoryPerMultiProcessor > lds) lds = prop.maxSharedMemoryPerMultiProcessor;
     ctx->c.lds_max = lds;
-    ctx->c.tuning = sbp_tuning{4, 512, 2, 0, 4, 256, 2, 0};
+    ctx->c.tuning = sbp_tuning{4, 512, 4, 0, 4, 512, 4, 0};
+    if (hipMalloc((void **)&ctx->c.misc, 256) != hipSuccess) {
+        (void)hipGetLastError();
+        delete ctx;
+        return fail(SBP_E_NOMEM, "could not allocate the context's device words");
+    }
     *out = ctx;
     return SBP_OK;
 }
@@ -242,9 +248,12 @@ int sbp_ctx_create(sbp_ctx **out, int device) {
 int sbp_ctx_destroy(sbp_ctx *ctx) {
     if (!ctx) return SBP_OK;
     int rc = SBP_OK;
-    if (ctx->c.scratch) {
-        if (hipSetDevice(ctx->c.device) == hipSuccess && hipFree(ctx->c.scratch) != hipSuccess)
+    if (ctx->c.scratch || ctx->c.misc) {
+        if (hipSetDevice(ctx->c.device) != hipSuccess) rc = fail(SBP_E_HIP, "hipSetDevice failed");
+        if (ctx->c.scratch && hipFree(ctx->c.scratch) != hipSuccess)
             rc = fail(SBP_E_HIP, "hipFree(scratch) failed");
+        if (ctx->c.misc && hipFree(ctx->c.misc) != hipSuccess)
+            rc = fail(SBP_E_HIP, "hipFree(misc) failed");
     }
     delete ctx;
     return rc;
@@ -299,7 +308,7 @@ int sbp_simulate_signals(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *ba
     if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
     if ((rc = set_device(ctx->c))) return rc;
     return launch_forward<float>(&ctx->c, arrp<float>(arr), ballsp<float>(balls), ball_off, F,
-                                 B_cap, model, y, accumulate, (hipStream_t)stream);
+                                 B_cap, model, y, accumulate, ctx->c.misc, (hipStream_t)stream);
 }
 
 int sbp_simulate_signals_f64(sbp_ctx *ctx, const sbp_array_f64 *arr, const sbp_balls_f64 *balls,
@@ -314,7 +323,7 @@ int sbp_simulate_signals_f64(sbp_ctx *ctx, const sbp_array_f64 *arr, const sbp_b
     if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
     if ((rc = set_device(ctx->c))) return rc;
     return launch_forward<double>(&ctx->c, arrp<double>(arr), ballsp<double>(balls), ball_off, F,
-                                  B_cap, model, y, accumulate, (hipStream_t)stream);
+                                  B_cap, model, y, accumulate, nullptr, (hipStream_t)stream);
 }
 
 int sbp_residual_loss(sbp_ctx *ctx, const float *y_sim, const float *y_ref, int64_t n_per_frame,
@@ -425,7 +434,7 @@ int sbp_step(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state, const sbp_mod
     if ((rc = set_device(ctx->c))) return rc;
     if ((rc = ensure_scratch(&ctx->c, residual_ws_bytes(state->F)))) return rc;
     return step_body(&ctx->c, arr, state, model, y_ref, y_work, p, nullptr, loss,
-                     (double *)ctx->c.scratch, (hipStream_t)stream);
+                     (double *)ctx->c.scratch, ctx->c.misc, (hipStream_t)stream);
 }
 
 int sbp_step_graph_create(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state,
@@ -446,7 +455,8 @@ int sbp_step_graph_create(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state,
     hipStream_t st = (hipStream_t)stream;
     sbp_graph *g = new sbp_graph();
     g->device = ctx->c.device;
-    if (hipMalloc(&g->ws, residual_ws_bytes(state->F)) != hipSuccess) {
+    const size_t ws_res = (residual_ws_bytes(state->F) + 255) & ~(size_t)255;
+    if (hipMalloc(&g->ws, ws_res + 256) != hipSuccess) {
         delete g;
         (void)hipGetLastError();
         return fail(SBP_E_NOMEM, "could not allocate the graph workspace");
@@ -460,7 +470,8 @@ int sbp_step_graph_create(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state,
     int body = SBP_OK;
     for (int it = 0; it < iters && body == SBP_OK; ++it) {
         body = step_body(&ctx->c, arr, state, model, y_ref, y_work, p, step_dev,
-                         loss + (int64_t)it * state->F, (double *)g->ws, st);
+                         loss + (int64_t)it * state->F, (double *)g->ws,
+                         (unsigned *)((char *)g->ws + ws_res), st);
         if (body == SBP_OK) body = launch_incr(step_dev, st);
     }
     e = hipStreamEndCapture(st, &g->graph);

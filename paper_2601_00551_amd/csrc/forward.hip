@@ -1,55 +1,121 @@
 // Forward model (Simulate of section 4.2 / 4.3 of SlingBAG Pro) on gfx950.
 //
 // Scatter form: a lane owns a ball, loops over a group of `dg` transducers
-// whose traces it accumulates in LDS rows (full record length, so no ball is
-// culled against a time tile), and for each pair adds its bin values
+// whose traces it accumulates in LDS rows (the full record, or time tiles of
+// it), and for each pair adds its bin values
 //     amp * (max(q(u_n), 0) - max(q(u_{n+1}), 0))
-// into the row with LDS atomics.  The rows are FP64: on gfx950 an LDS FP64
-// atomic add sustains about ten times the rate of the FP32 one (which the
-// hardware serialises), and it makes the accumulation over up to ~10^5 balls
-// per sample exact to FP32 rounding.  Adding bin values (which sum to zero per
+// into the row with LDS atomics.  Adding bin values (which sum to zero per
 // pair) rather than edge values avoids the cancellation a running
 // antiderivative would suffer when many balls overlap in a bin.
 //
-// Work items are (frame, transducer group, chunk of block*bpt balls), ordered
-// frame-major, then group, then chunk.  A persistent workgroup takes one
-// contiguous range of items, so consecutive items share a transducer group and
-// the LDS rows are flushed to HBM (one global atomic per non-zero sample) only
-// when the group or frame changes.  Ball counts are read on the device, so the
-// launch is sized by capacity and can be captured in a graph.
+// LDS accumulation.  gfx950 serialises LDS FP32 atomic adds (about 0.3 lanes
+// per clock per CU, against ~7 for 64-bit integer adds), so the FP32 path
+// accumulates in exact 64-bit fixed point: each bin value is rounded to an
+// integer multiple of a power-of-two quantum q = 2^-k chosen per launch from
+// a bound on |bin value| over all balls (|p0| a / (2 K c dt) for GAUSS,
+// |p0| a / (4 c dt) for UNIFORM, using rho > support half-width), so that a
+// single value never exceeds 2^30 q; the int64 sums are exact and are turned
+// back into FP32 once per sample when the rows are flushed.  The per-value
+// rounding error is at most q / 2 <= 2^-31 of that bound.  The FP64 path keeps
+// FP64 rows (LDS FP64 adds are not serialised).
+//
+// Work items are (frame, transducer group, time tile, chunk of block*bpt
+// balls) in that order.  A persistent workgroup takes one contiguous range of
+// items, so consecutive items share a group and tile and the rows are flushed
+// (one global atomic per non-zero sample) only when those change.  Ball counts
+// are read on the device, so the launch is sized by capacity and can be
+// captured in a graph.
+#include <climits>
+
 #include "sbp_internal.hpp"
 
 namespace sbp {
 
-// Adds the pair's bins that fall in the time tile [tlo, thi) to row[n - tlo].
+// LDS row element and how bin values are added to it, per precision.
+template <typename R> struct FwdAcc;
+template <> struct FwdAcc<float> {
+    using T = unsigned long long;
+    __device__ static void add(T *p, float v_scaled) {
+        const int iv = (int)rintf(v_scaled);
+        atomicAdd(p, (unsigned long long)(long long)iv);
+    }
+    __device__ static float value(T s, float inv_scale) {
+        return (float)((double)(long long)s * (double)inv_scale);
+    }
+};
+template <> struct FwdAcc<double> {
+    using T = double;
+    __device__ static void add(T *p, double v) { atomicAdd(p, v); }
+    __device__ static double value(T s, double) { return s; }
+};
+
+// max over live balls of |p0| * a (a after softplus), as float bits in *slot
+// (zeroed before the launch; non-negative floats order like their bits).
+__global__ void k_amp_bound(BallsP<float> balls, const int64_t *__restrict__ ball_off, int F,
+                            int a_softplus, unsigned *slot) {
+    __shared__ float s_red[8];
+    const int64_t count = ball_off[F];
+    float m = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float a = balls.a[i];
+        if (a_softplus) a = softplus_dev(a);
+        if (a > 0.0f) m = fmaxf(m, fabsf(balls.p0[i]) * a);
+    }
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_down(m, o, 64));
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, s_red[w]);
+        atomicMax(slot, __float_as_uint(m));
+    }
+}
+
+// Adds the pair's bins that fall in the time tile [tlo, thi) to row[n - tlo];
+// `scale` multiplies the bin values (the fixed-point quantum's inverse).
 template <typename R, int PROF, int DIR>
 __device__ inline void fwd_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx, R ny, R nz,
-                                const Level &lc, int tlo, int thi, double *__restrict__ row) {
+                                const Level &lc, int tlo, int thi, R scale,
+                                typename FwdAcc<R>::T *__restrict__ row) {
     PairG<R> g;
     if (!pair_geometry<R, DIR>(b.x, b.y, b.z, b.w, qx, qy, qz, nx, ny, nz, lc, g)) return;
-    const double lo = floor((g.s - b.w) * lc.inv_cdt);
-    const double hi = floor((g.s + b.w) * lc.inv_cdt);
+    const double lo = floor((g.s - (double)b.w) * lc.inv_cdt);
+    const double hi = floor((g.s + (double)b.w) * lc.inv_cdt);
     if (hi < (double)tlo || lo > (double)(thi - 1)) return;
     const int nb = lo < (double)tlo ? tlo : (int)lo;
     const int ne = hi > (double)(thi - 1) ? thi - 1 : (int)hi;
-    const R amp = b.ampk * g.dir * LevelR<R>::inv2cdt(lc) * g.inv_rho;
-    const R eK = LevelR<R>::eK(lc);
-    const R cdt = LevelR<R>::cdt(lc);
-    const R u0 = (R)(g.s - (double)nb * lc.cdt);
-    R prev = amp * fmax(shape_q<R, PROF>(u0, b, eK), R(0));
-    R j = R(1);
-    double *out = row - tlo;
-    for (int n = nb; n <= ne; ++n, j += R(1)) {
-        const R u = fma(-j, cdt, u0);
-        const R cur = amp * fmax(shape_q<R, PROF>(u, b, eK), R(0));
-        atomicAdd(out + n, (double)(prev - cur));
-        prev = cur;
+    const R amp = b.ampk * g.dir * LevelR<R>::inv2cdt(lc) * g.inv_rho * scale;
+    const R c = LevelR<R>::cdt(lc);
+    typename FwdAcc<R>::T *out = row - tlo;
+    if (PROF == GAUSS) {
+        // one exponential per edge: a recurrence drifts by ~1e-7 per step, and
+        // bin differences amplify that by a / (c dt), up to ~10^2 here
+        const R eK = LevelR<R>::eK(lc);
+        const R u0 = (R)(g.s - (double)nb * lc.cdt);
+        R prev = fmax(ex2(u0 * u0 * b.q0), eK);
+        R j = R(1);
+        for (int n = nb; n <= ne; ++n, j += R(1)) {
+            const R u = fma(-j, c, u0);
+            const R cur = fmax(ex2(u * u * b.q0), eK);
+            FwdAcc<R>::add(out + n, amp * (prev - cur));
+            prev = cur;
+        }
+    } else {
+        R u = (R)(g.s - (double)nb * lc.cdt);
+        R prev = fmax(b.q0 - u * u, R(0));
+        for (int n = nb; n <= ne; ++n) {
+            u -= c;
+            const R cur = fmax(b.q0 - u * u, R(0));
+            FwdAcc<R>::add(out + n, amp * (prev - cur));
+            prev = cur;
+        }
     }
 }
 
 template <typename R>
-__device__ inline void flush_rows(double *__restrict__ rows, int dg, int TT, int T, int g, int tile,
-                                  int D, int f, R *__restrict__ y) {
+__device__ inline void flush_rows(typename FwdAcc<R>::T *__restrict__ rows, int dg, int TT, int T,
+                                  int g, int tile, int D, int f, R inv_scale, R *__restrict__ y) {
+    using A = typename FwdAcc<R>::T;
     __syncthreads();
     const int tlo = tile * TT;
     const int len = min(TT, T - tlo);
@@ -57,27 +123,40 @@ __device__ inline void flush_rows(double *__restrict__ rows, int dg, int TT, int
         const int d = g * dg + dl;
         if (d >= D) break;
         R *out = y + ((int64_t)f * D + d) * (int64_t)T + tlo;
-        double *row = rows + (int64_t)dl * TT;
+        A *row = rows + (int64_t)dl * TT;
         for (int n = threadIdx.x; n < len; n += blockDim.x) {
-            const double v = row[n];
-            if (v != 0.0) {
-                atomicAdd(out + n, (R)v);
-                row[n] = 0.0;
+            const A v = row[n];
+            if (v != A(0)) {
+                atomicAdd(out + n, FwdAcc<R>::value(v, inv_scale));
+                row[n] = A(0);
             }
         }
     }
     __syncthreads();
 }
 
-// Work items are (frame, transducer group g, time tile, ball chunk), in that
-// order; nt = number of time tiles of length TT.
+// Power-of-two scale with |bin value| * scale <= 2^30 (FP32 path).
+__device__ inline float fixed_scale(const unsigned *slot, int profile, const Level &lc) {
+    const float pa = __uint_as_float(*slot);
+    const float bound = pa * lc.inv2cdt * (profile == GAUSS ? 1.0f / lc.K : 0.5f);
+    if (!(bound > 0.0f) || !(bound < 3.0e38f)) return 1.0f;
+    int e = 0;
+    frexpf(bound, &e);              // bound < 2^e
+    int k = 30 - e;
+    if (k > 120) k = 120;
+    if (k < -120) k = -120;
+    return ldexpf(1.0f, k);
+}
+
 template <typename R, int PROF, int DIR>
-__global__ __launch_bounds__(512) void k_forward(ArrayP<R> arr, BallsP<R> balls,
-                                                 const int64_t *__restrict__ ball_off, int F,
-                                                 int G, int dg, int TT, int nt, int bpt, Level lc,
-                                                 R *__restrict__ y) {
+__global__ __launch_bounds__(512, 4) void k_forward(ArrayP<R> arr, BallsP<R> balls,
+                                                    const int64_t *__restrict__ ball_off, int F,
+                                                    int G, int dg, int TT, int nt, int bpt,
+                                                    Level lc, const unsigned *__restrict__ bound,
+                                                    R *__restrict__ y) {
+    using A = typename FwdAcc<R>::T;
     extern __shared__ __align__(16) unsigned char lds_raw[];
-    double *rows = reinterpret_cast<double *>(lds_raw);
+    A *rows = reinterpret_cast<A *>(lds_raw);
     __shared__ int64_t s_off[SBP_MAX_FRAMES + 1];
     __shared__ int64_t s_ipre[SBP_MAX_FRAMES + 1];
     const int tid = threadIdx.x;
@@ -85,8 +164,10 @@ __global__ __launch_bounds__(512) void k_forward(ArrayP<R> arr, BallsP<R> balls,
     const int T = lc.T;
     const int64_t CH = (int64_t)nth * bpt;
     const int64_t GT = (int64_t)G * nt;
+    const R scale = bound ? (R)fixed_scale(bound, PROF, lc) : R(1);
+    const R inv_scale = R(1) / scale;
     for (int i = tid; i <= F; i += nth) s_off[i] = ball_off[i];
-    for (int i = tid; i < dg * TT; i += nth) rows[i] = 0.0;
+    for (int i = tid; i < dg * TT; i += nth) rows[i] = A(0);
     __syncthreads();
     if (tid == 0) {
         s_ipre[0] = 0;
@@ -108,7 +189,8 @@ __global__ __launch_bounds__(512) void k_forward(ArrayP<R> arr, BallsP<R> balls,
         const int gt = __builtin_amdgcn_readfirstlane((int)(local / nch));
         const int64_t ck = local - (int64_t)gt * nch;
         if (f != cur_f || gt != cur_gt) {
-            if (cur_f >= 0) flush_rows(rows, dg, TT, T, cur_gt / nt, cur_gt % nt, D, cur_f, y);
+            if (cur_f >= 0)
+                flush_rows<R>(rows, dg, TT, T, cur_gt / nt, cur_gt % nt, D, cur_f, inv_scale, y);
             cur_f = f;
             cur_gt = gt;
         }
@@ -127,31 +209,32 @@ __global__ __launch_bounds__(512) void k_forward(ArrayP<R> arr, BallsP<R> balls,
                 const int d = __builtin_amdgcn_readfirstlane(g * dg + dl);
                 if (d >= D) break;
                 fwd_pair<R, PROF, DIR>(b, arr.qx[d], arr.qy[d], arr.qz[d], arr.nx[d], arr.ny[d],
-                                       arr.nz[d], lc, tlo, thi, rows + (int64_t)dl * TT);
+                                       arr.nz[d], lc, tlo, thi, scale, rows + (int64_t)dl * TT);
             }
         }
     }
-    if (cur_f >= 0) flush_rows(rows, dg, TT, T, cur_gt / nt, cur_gt % nt, D, cur_f, y);
+    if (cur_f >= 0) flush_rows<R>(rows, dg, TT, T, cur_gt / nt, cur_gt % nt, D, cur_f, inv_scale, y);
 }
 
 template <typename R, int PROF, int DIR>
 static int run_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
-                       const int64_t *ball_off, int F, int64_t B_cap, const Level &lc, R *y,
-                       hipStream_t st) {
+                       const int64_t *ball_off, int F, int64_t B_cap, const Level &lc,
+                       const unsigned *bound, R *y, hipStream_t st) {
+    using A = typename FwdAcc<R>::T;
     auto kern = k_forward<R, PROF, DIR>;
     const size_t reserve = 2 * (SBP_MAX_FRAMES + 1) * sizeof(int64_t) + 256;
     const size_t avail = c->lds_max > reserve ? c->lds_max - reserve : 0;
     int dg = c->tuning.fwd_dets;
     if (dg > arr.D) dg = arr.D;
     // time tile: the whole record if the dg rows fit, else the longest that does
-    int64_t TT = (int64_t)(avail / ((size_t)dg * sizeof(double)));
+    int64_t TT = (int64_t)(avail / ((size_t)dg * sizeof(A)));
     if (TT > lc.T) TT = lc.T;
     if (TT < lc.T && TT < 64) return fail(SBP_E_DOMAIN, "LDS too small for %d rows", dg);
     const int nt = (int)((lc.T + TT - 1) / TT);
     const int G = (arr.D + dg - 1) / dg;
     const int block = c->tuning.fwd_block;
     const int bpt = c->tuning.fwd_bpt;
-    const size_t lds = (size_t)dg * (size_t)TT * sizeof(double);
+    const size_t lds = (size_t)dg * (size_t)TT * sizeof(A);
     SBP_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds));
     int grid = c->tuning.fwd_grid;
@@ -166,7 +249,7 @@ static int run_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
     if (grid > max_items) grid = (int)max_items;
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, arr, balls, ball_off, F, G, dg,
-                       (int)TT, nt, bpt, lc, y);
+                       (int)TT, nt, bpt, lc, bound, y);
     SBP_HIP(hipGetLastError());
     return SBP_OK;
 }
@@ -174,28 +257,41 @@ static int run_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
 template <typename R>
 int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
                    int F, int64_t B_cap, const sbp_model *m, R *y, int accumulate,
-                   hipStream_t st) {
+                   unsigned *bound_slot, hipStream_t st) {
     const Level lc = make_level(m);
     if (!accumulate) {
         int rc = launch_fill<R>(y, (int64_t)F * arr.D * m->T, R(0), st);
         if (rc) return rc;
     }
     if (B_cap == 0) return SBP_OK;
+    const unsigned *bound = nullptr;
+    if (sizeof(R) == sizeof(float)) {
+        int rc = launch_fill<int32_t>((int32_t *)bound_slot, 1, 0, st);
+        if (rc) return rc;
+        int64_t nb = (B_cap + 255) / 256;
+        if (nb > 1024) nb = 1024;
+        hipLaunchKernelGGL(k_amp_bound, dim3((int)nb), dim3(256), 0, st,
+                           BallsP<float>{(float *)balls.x, (float *)balls.y, (float *)balls.z,
+                                         (float *)balls.p0, (float *)balls.a},
+                           ball_off, F, m->a_softplus, bound_slot);
+        SBP_HIP(hipGetLastError());
+        bound = bound_slot;
+    }
     if (m->profile == SBP_PROFILE_GAUSS) {
         if (m->directivity == SBP_DIR_COS)
-            return run_forward<R, GAUSS, COS>(c, arr, balls, ball_off, F, B_cap, lc, y, st);
-        return run_forward<R, GAUSS, OMNI>(c, arr, balls, ball_off, F, B_cap, lc, y, st);
+            return run_forward<R, GAUSS, COS>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, st);
+        return run_forward<R, GAUSS, OMNI>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, st);
     }
     if (m->directivity == SBP_DIR_COS)
-        return run_forward<R, UNIFORM, COS>(c, arr, balls, ball_off, F, B_cap, lc, y, st);
-    return run_forward<R, UNIFORM, OMNI>(c, arr, balls, ball_off, F, B_cap, lc, y, st);
+        return run_forward<R, UNIFORM, COS>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, st);
+    return run_forward<R, UNIFORM, OMNI>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, st);
 }
 
 template int launch_forward<float>(Ctx *, const ArrayP<float> &, const BallsP<float> &,
                                    const int64_t *, int, int64_t, const sbp_model *, float *, int,
-                                   hipStream_t);
+                                   unsigned *, hipStream_t);
 template int launch_forward<double>(Ctx *, const ArrayP<double> &, const BallsP<double> &,
                                     const int64_t *, int, int64_t, const sbp_model *, double *,
-                                    int, hipStream_t);
+                                    int, unsigned *, hipStream_t);
 
 }  // namespace sbp

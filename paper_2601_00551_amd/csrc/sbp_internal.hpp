@@ -75,11 +75,12 @@ template <typename R> __device__ inline R sigmoid_dev(R x) { return R(1) / (R(1)
 // Per-ball constants.
 template <typename R, int PROF>
 struct BallK {
-    double x, y, z;   // centre, widened
-    double w;         // support half-width (a or K a)
+    R x, y, z;        // centre (widened to FP64 per pair: the difference is exact)
+    R w;              // support half-width (a or K a)
     R p, a;           // peak pressure, size
     R q0;             // UNIFORM: a^2        GAUSS: -log2(e) / (2 a^2)
     R ampk;           // UNIFORM: -p / 2     GAUSS: -p a^2
+    R h;              // GAUSS: 2^(2 q0 (c dt)^2), the ratio of successive edge ratios
     bool live;        // a > 0
 };
 
@@ -87,20 +88,22 @@ template <typename R, int PROF>
 __device__ inline BallK<R, PROF> load_ball(R x, R y, R z, R p, R araw, const Level &lc) {
     BallK<R, PROF> b;
     R a = lc.a_softplus ? softplus_dev(araw) : araw;
-    b.x = (double)x;
-    b.y = (double)y;
-    b.z = (double)z;
+    b.x = x;
+    b.y = y;
+    b.z = z;
     b.p = p;
     b.a = a;
     b.live = a > R(0);
     if (PROF == UNIFORM) {
-        b.w = (double)a;
+        b.w = a;
         b.q0 = a * a;
         b.ampk = R(-0.5) * p;
     } else {
-        b.w = lc.K_d * (double)a;
+        b.w = (R)(lc.K_d * (double)a);
         b.q0 = R(-1.4426950408889634) / (R(2) * a * a);
         b.ampk = -p * a * a;
+        const R c = LevelR<R>::cdt(lc);
+        b.h = ex2(R(2) * b.q0 * c * c);
     }
     return b;
 }
@@ -124,11 +127,12 @@ struct PairG {
 
 // Returns false if the pair contributes nothing (near field, facing away).
 template <typename R, int DIR>
-__device__ inline bool pair_geometry(double bx, double by, double bz, double w, R qx, R qy, R qz,
+__device__ inline bool pair_geometry(R bx, R by, R bz, R w, R qx, R qy, R qz,
                                      R nx, R ny, R nz, const Level &lc, PairG<R> &g) {
-    const double dx = bx - (double)qx, dy = by - (double)qy, dz = bz - (double)qz;
+    const double dx = (double)bx - (double)qx, dy = (double)by - (double)qy,
+                 dz = (double)bz - (double)qz;
     const double rho = sqrt(dx * dx + dy * dy + dz * dz);
-    if (!(rho > w)) return false;
+    if (!(rho > (double)w)) return false;
     g.s = rho - lc.ct0;
     g.rho = (R)rho;
     g.inv_rho = rcp(g.rho);
@@ -153,6 +157,7 @@ struct Ctx {
     sbp_tuning tuning{};
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
+    unsigned *misc = nullptr;  // 256 persistent bytes: the forward's per-launch bound
 };
 
 int fail(int code, const char *fmt, ...);
@@ -176,10 +181,11 @@ struct BallsP {
     R *x, *y, *z, *p0, *a;
 };
 
+// bound_slot: one device word the FP32 path uses for its fixed-point quantum.
 template <typename R>
 int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
                    int F, int64_t B_cap, const sbp_model *m, R *y, int accumulate,
-                   hipStream_t st);
+                   unsigned *bound_slot, hipStream_t st);
 
 // vscale multiplies v (the filter passes y_ref with vscale = -2).
 template <typename R>
