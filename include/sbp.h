@@ -283,6 +283,15 @@ int sbp_step_graph_create(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state,
 int sbp_graph_launch(sbp_graph *g, void *stream);
 int sbp_graph_destroy(sbp_graph *g);
 
+/* Switch the size parameterisation of the positivity-constrained refinement
+ * (section 4.3): to_softplus = 1 replaces every a in state->balls.a (balls
+ * [0, ball_off[F])) by a~ = log(e^a - 1), so that a = softplus(a~) (a <= 0
+ * becomes a~ = -88); to_softplus = 0 replaces a~ by softplus(a~).  Calls that
+ * follow must set model->a_softplus to match.  state->m.a and state->v.a, if
+ * not NULL, are reset to zero (the optimised variable changes).
+ * Errors: SBP_E_ARG. */
+int sbp_softplus_reparam(sbp_ctx *ctx, sbp_state *state, int32_t to_softplus, void *stream);
+
 /* Plain growth rule (see sbp_growth_rule) applied to `in` (uses in->grad for
  * the split axis and the duplication ranking) and written to `out`
  * (balls, zeroed-or-copied moments, ball_off); out->B_cap is its capacity.

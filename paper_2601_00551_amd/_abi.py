@@ -94,6 +94,7 @@ SIGNATURES = {
     "sbp_graph_launch": (ctypes.c_int, [P, P]),
     "sbp_graph_destroy": (ctypes.c_int, [P]),
     "sbp_grow": (ctypes.c_int, [P, PS, PG, PS, ctypes.POINTER(I64), P]),
+    "sbp_softplus_reparam": (ctypes.c_int, [P, PS, I32, P]),
     "sbp_simulate_signals_f64": (ctypes.c_int, [P, PA, PB, P, I32, I64, PM, P, I32, P]),
     "sbp_adjoint_gradients_f64": (ctypes.c_int, [P, PA, PB, P, I32, I64, PM, P, U32, PB, P]),
 }

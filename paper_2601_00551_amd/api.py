@@ -346,6 +346,12 @@ class StepGraph:
             pass
 
 
+def softplus_reparam(ctx, state: State, to_softplus: bool, stream=None):
+    """sbp_softplus_reparam: a <-> a~ in place (a = softplus(a~)); resets a's moments."""
+    check(lib().sbp_softplus_reparam(ctx.ptr, ctypes.byref(state.struct()), int(bool(to_softplus)),
+                                     _stream(stream)))
+
+
 def grow(ctx, state: State, rule: GrowthRule, capacity=None, stream=None):
     """sbp_grow: returns (new State, total count)."""
     cap = int(capacity or state.B_cap)

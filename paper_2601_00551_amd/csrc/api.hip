@@ -513,6 +513,18 @@ int sbp_graph_destroy(sbp_graph *g) {
     return rc;
 }
 
+int sbp_softplus_reparam(sbp_ctx *ctx, sbp_state *state, int32_t to_softplus, void *stream) {
+    int rc;
+    if (!state) return fail(SBP_E_ARG, "state is NULL");
+    if ((rc = check_frames(state->ball_off, state->F, state->B_cap))) return rc;
+    if (state->B_cap > 0 && !state->balls.a) return fail(SBP_E_ARG, "state.balls.a is NULL");
+    if (to_softplus != 0 && to_softplus != 1) return fail(SBP_E_ARG, "to_softplus must be 0 or 1");
+    if ((rc = check_ctx(ctx))) return rc;
+    if ((rc = set_device(ctx->c))) return rc;
+    return launch_reparam(state->balls.a, state->m.a, state->v.a, state->ball_off, state->F,
+                          state->B_cap, to_softplus, (hipStream_t)stream);
+}
+
 int sbp_grow(sbp_ctx *ctx, const sbp_state *in, const sbp_growth_rule *rule, sbp_state *out,
              int64_t *count, void *stream) {
     int rc;

@@ -182,6 +182,37 @@ int launch_adam(const sbp_state *s, const sbp_adam_params *p, const int32_t *ste
     return SBP_OK;
 }
 
+// a <-> a~ for balls [0, count): to_softplus = 1 stores a~ = log(expm1(a))
+// (a <= 0 becomes a~ = -88, i.e. a ~ 1e-38), to_softplus = 0 stores
+// a = softplus(a~).  The size's Adam moments restart at zero when given.
+__global__ void k_reparam(float *a, float *m, float *v, const int64_t *__restrict__ ball_off, int F,
+                          int to_softplus) {
+    const int64_t count = ball_off[F];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float x = a[i];
+        float r;
+        if (to_softplus) {
+            const double xd = (double)x;
+            r = x > 0.0f ? (float)(xd > 30.0 ? xd : log(expm1(xd))) : -88.0f;
+        } else {
+            r = softplus_dev(x);
+        }
+        a[i] = r;
+        if (m) m[i] = 0.0f;
+        if (v) v[i] = 0.0f;
+    }
+}
+
+int launch_reparam(float *a, float *m, float *v, const int64_t *ball_off, int F, int64_t B_cap,
+                   int to_softplus, hipStream_t st) {
+    if (B_cap == 0) return SBP_OK;
+    hipLaunchKernelGGL(k_reparam, dim3(ew_grid(B_cap)), dim3(kEw), 0, st, a, m, v, ball_off, F,
+                       to_softplus);
+    SBP_HIP(hipGetLastError());
+    return SBP_OK;
+}
+
 __global__ void k_incr(int32_t *p) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p += 1;
 }

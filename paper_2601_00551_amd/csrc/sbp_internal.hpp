@@ -208,6 +208,8 @@ int launch_compact(void *ws, const float *g, int strict, const BallsP<float> &in
                    int64_t *off_out, const BallsP<float> *m_in, const BallsP<float> *v_in,
                    const BallsP<float> *m_out, const BallsP<float> *v_out, hipStream_t st);
 int launch_incr(int32_t *p, hipStream_t st);
+int launch_reparam(float *a, float *m, float *v, const int64_t *ball_off, int F, int64_t B_cap,
+                   int to_softplus, hipStream_t st);
 int launch_grow(Ctx *c, const sbp_state *in, const sbp_growth_rule *rule, sbp_state *out,
                 int64_t *count, hipStream_t st);
 
