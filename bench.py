@@ -40,6 +40,35 @@ def edges_per_pair(a_sup, cdt):
     return 2.0 * a_sup / cdt + 1.0
 
 
+KERNEL_SOURCES = {"k_forward": ("paper_2601_00551_amd/csrc/forward.hip", "paper_2601_00551_amd/csrc/sbp_internal.hpp"),
+                  "k_adjoint": ("paper_2601_00551_amd/csrc/adjoint.hip", "paper_2601_00551_amd/csrc/sbp_internal.hpp")}
+KERNEL_NAMES = {"forward": "k_forward<float, 1, 1>", "adjoint": "k_adjoint<float, 1, 1, true>",
+                "filter": "k_adjoint<float, 1, 1, false>"}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel's source changed since it was taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_large.md")
+    if not os.path.exists(path):
+        return None
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), flags=re.S)
+    if not m:
+        return None
+    entry = json.loads(m.group(1)).get(KERNEL_NAMES[kernel])
+    if not entry:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[KERNEL_NAMES[kernel].split("<")[0]]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != entry["source_hash"]:
+        return None
+    return entry["read_bytes"] + entry["write_bytes"]
+
+
 def cpu_baseline(wl, model_kw, n_balls_sample, rng_seed=0):
     """The FP64 oracle on a bounded sample of the same workload: forward + VJP
     of n_balls_sample balls against every transducer at the full record."""
@@ -218,7 +247,7 @@ def main():
         "balls_kept_by_filter": kept,
         "roofline": {"bound": "alu", "kernel": dominant, "achieved": achieved / 1e12,
                      "peak": VALU_PEAK / 1e12, "unit": "TOP/s", "frac": achieved / VALU_PEAK,
-                     "traffic": None},
+                     "traffic": measured_traffic(dominant), "traffic_unit": "bytes/launch"},
         "tuning": tuned,
         "wall_s": wall,
     }
