@@ -73,6 +73,17 @@ PM, PA, PB = ctypes.POINTER(SbpModel), ctypes.POINTER(SbpArray), ctypes.POINTER(
 PS, PAd, PG = ctypes.POINTER(SbpState), ctypes.POINTER(SbpAdamParams), ctypes.POINTER(SbpGrowthRule)
 PT = ctypes.POINTER(SbpTuning)
 
+
+class SbpGrid(ctypes.Structure):
+    _fields_ = [("ox", ctypes.c_float), ("oy", ctypes.c_float), ("oz", ctypes.c_float),
+                ("h", ctypes.c_float), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+PGr = ctypes.POINTER(SbpGrid)
+F32 = ctypes.c_float
+MLP_IN, MLP_HID, MLP_OUT, MLP_NPARAM, MLP_NWORK = 31, 256, 2, 140546, 278528
+
 # name -> (restype, argtypes); the names are the C-ABI's entry points.
 SIGNATURES = {
     "sbp_last_error": (ctypes.c_char_p, []),
@@ -97,6 +108,16 @@ SIGNATURES = {
     "sbp_softplus_reparam": (ctypes.c_int, [P, PS, I32, P]),
     "sbp_simulate_signals_f64": (ctypes.c_int, [P, PA, PB, P, I32, I64, PM, P, I32, P]),
     "sbp_adjoint_gradients_f64": (ctypes.c_int, [P, PA, PB, P, I32, I64, PM, P, U32, PB, P]),
+    # sbp_mlp.h
+    "sbp_mlp_sync": (ctypes.c_int, [P, P, P, P]),
+    "sbp_mlp_forward": (ctypes.c_int, [P, P, P, P, I64, P, P, P]),
+    "sbp_mlp_loss": (ctypes.c_int, [P, P, P, P, I64, F32, P, P, P, P]),
+    "sbp_mlp_backward": (ctypes.c_int, [P, P, P, P, P, I64, P, P, P]),
+    "sbp_mlp_adam": (ctypes.c_int, [P, P, P, P, P, PAd, P, P]),
+    "sbp_grid_mass": (ctypes.c_int, [P, PB, P, I64, PGr, P, P]),
+    "sbp_candidates": (ctypes.c_int, [P, PGr, P, F32, F32, PB, I64, ctypes.POINTER(I64), P]),
+    "sbp_features": (ctypes.c_int, [P, PGr, P, PB, I64, PB, F32, P, P]),
+    "sbp_append_proposals": (ctypes.c_int, [P, PS, PB, P, I64, F32, F32, ctypes.POINTER(I64), P]),
 }
 
 _LIB = None

@@ -8,10 +8,6 @@
 
 #include "sbp_internal.hpp"
 
-struct sbp_ctx {
-    sbp::Ctx c;
-};
-
 struct sbp_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;

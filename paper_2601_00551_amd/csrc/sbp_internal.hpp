@@ -214,3 +214,8 @@ int launch_grow(Ctx *c, const sbp_state *in, const sbp_growth_rule *rule, sbp_st
                 int64_t *count, hipStream_t st);
 
 }  // namespace sbp
+
+// The opaque context of the C-ABI.
+struct sbp_ctx {
+    sbp::Ctx c;
+};

@@ -1,0 +1,477 @@
+"""Learned growth proposal: a BF16 MLP on the matrix cores that decides where
+new balls appear and with which p0 (declared in include/sbp_mlp.h).
+
+Section 4.1 of SlingBAG Pro grows the cloud by splitting, destroying and
+duplicating balls from pressure / size thresholds.  The network adds a second
+source of new balls at the same growth points: candidate sites are the empty
+cells of a regular grid that touch an occupied cell; each gets a feature row
+(the residual back-projected onto a unit probe ball at the site, the probe's
+gradient norm, the 26 neighbour masses and the position) and the network
+returns a growth logit and an initial p0.  The accepted sites are appended as
+balls.  The data-fidelity loss is the judge: if the appended balls do not
+lower the loss, they are removed again and only the plain rule has acted.
+
+Training data come from reconstructions the plain method itself runs: the
+features of the candidate sites at its growth points, labelled by the mass the
+plain reconstruction ends up with in the candidate's cell (grow if above a
+threshold; the regression target is that mass).
+
+Every step runs in libsbp.so (feature kernels, MLP forward / loss / backward /
+Adam kernels); this module marshals arguments, sequences calls and prepares
+training sets.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import dataclasses
+import json
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import _abi, api, recon, synth
+from ._abi import MLP_HID, MLP_IN, MLP_NPARAM, MLP_NWORK, check, lib
+from .api import P0, PARAMS, XYZ, _need, _p, _stream, balls_struct
+
+# flat FP32 parameter layout of the network (row-major [in][out], then bias)
+LAYOUT = [("W1", (32, MLP_HID)), ("b1", (MLP_HID,)), ("W2", (MLP_HID, MLP_HID)), ("b2", (MLP_HID,)),
+          ("W3", (MLP_HID, MLP_HID)), ("b3", (MLP_HID,)), ("W4", (MLP_HID, 2)), ("b4", (2,))]
+
+
+def padded(M: int) -> int:
+    return (int(M) + 63) // 64 * 64
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-normal weights (the zero-padding input row 31 stays zero), zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, shape in LAYOUT:
+        if name.startswith("b"):
+            parts.append(np.zeros(shape))
+            continue
+        fan_in = MLP_IN if name == "W1" else shape[0]
+        gain = 1.0 if name == "W4" else 2.0
+        w = rng.normal(0.0, np.sqrt(gain / fan_in), size=shape)
+        if name == "W1":
+            w[MLP_IN:, :] = 0.0
+        parts.append(w)
+    p = np.concatenate([x.ravel() for x in parts]).astype(np.float32)
+    assert p.size == MLP_NPARAM
+    return p
+
+
+class ProposalMLP:
+    """Parameters (FP32), their BF16 working copies and Adam moments, on one device."""
+
+    def __init__(self, ctx, device="cuda:0", seed=0, params=None):
+        self.ctx = ctx
+        self.dev = torch.device(device)
+        p = init_params(seed) if params is None else np.asarray(params, np.float32)
+        if p.size != MLP_NPARAM:
+            raise ValueError(f"expected {MLP_NPARAM} parameters, got {p.size}")
+        self.params = torch.as_tensor(p, device=self.dev).contiguous()
+        self.work = torch.empty(MLP_NWORK, dtype=torch.int16, device=self.dev)
+        self.grad = torch.zeros(MLP_NPARAM, dtype=torch.float32, device=self.dev)
+        self.m = torch.zeros(MLP_NPARAM, dtype=torch.float32, device=self.dev)
+        self.v = torch.zeros(MLP_NPARAM, dtype=torch.float32, device=self.dev)
+        self.t = 0
+        self._bufs = {}
+        self.sync()
+
+    def sync(self, stream=None):
+        check(lib().sbp_mlp_sync(self.ctx.ptr, _p(self.params), _p(self.work), _stream(stream)))
+
+    def forward(self, X, out=None, acts=None, stream=None):
+        """out [M][2] = (growth logit, initial p0) for feature rows X [M][31]."""
+        _need(X, name="X")
+        M = X.shape[0]
+        if X.dim() != 2 or X.shape[1] != MLP_IN:
+            raise ValueError("X must be [M][31]")
+        if out is None:
+            out = torch.empty((M, 2), dtype=torch.float32, device=X.device)
+        check(lib().sbp_mlp_forward(self.ctx.ptr, _p(self.params), _p(self.work), _p(X), M,
+                                    _p(_need(out, name="out")), _p(acts), _stream(stream)))
+        return out
+
+    def _buffers(self, M):
+        Mp = padded(M)
+        b = self._bufs.get(Mp)
+        if b is None:
+            d = self.dev
+            b = dict(acts=torch.empty((32 + 3 * MLP_HID) * Mp, dtype=torch.int16, device=d),
+                     dacts=torch.empty(3 * MLP_HID * Mp, dtype=torch.int16, device=d),
+                     dout=torch.empty(2 * Mp, dtype=torch.float32, device=d),
+                     dout_t=torch.empty(16 * Mp, dtype=torch.int16, device=d),
+                     loss=torch.zeros(1, dtype=torch.float64, device=d))
+            self._bufs = {Mp: b}
+        return b
+
+    def loss_and_grad(self, X, yg, yp, pos_weight=1.0, stream=None):
+        """Mean loss (device double) and self.grad = d loss / d params."""
+        M = X.shape[0]
+        b = self._buffers(M)
+        out = torch.empty((M, 2), dtype=torch.float32, device=X.device)
+        self.forward(X, out=out, acts=b["acts"], stream=stream)
+        check(lib().sbp_mlp_loss(self.ctx.ptr, _p(out), _p(_need(yg, name="yg")), _p(_need(yp, name="yp")),
+                                 M, float(pos_weight), _p(b["loss"]), _p(b["dout"]), _p(b["dout_t"]),
+                                 _stream(stream)))
+        check(lib().sbp_mlp_backward(self.ctx.ptr, _p(self.work), _p(b["acts"]), _p(b["dout"]),
+                                     _p(b["dout_t"]), M, _p(b["dacts"]), _p(self.grad), _stream(stream)))
+        return b["loss"], out
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        self.t += 1
+        prm = api.AdamParams(lr=(lr,) * 5, beta1=beta1, beta2=beta2, eps=eps, step=self.t)
+        check(lib().sbp_mlp_adam(self.ctx.ptr, _p(self.params), _p(self.grad), _p(self.m), _p(self.v),
+                                 ctypes.byref(prm.struct()), _p(self.work), _stream(stream)))
+
+    def train_step(self, X, yg, yp, pos_weight=1.0, lr=1e-3, stream=None):
+        loss, _ = self.loss_and_grad(X, yg, yp, pos_weight, stream)
+        self.adam(lr=lr, stream=stream)
+        return loss
+
+    def save(self, path):
+        np.savez(path, params=self.params.cpu().numpy())
+
+    @classmethod
+    def load(cls, ctx, path, device="cuda:0"):
+        with np.load(path) as z:
+            return cls(ctx, device=device, params=z["params"])
+
+
+# ------------------------------------------------------ candidate sites --
+
+@dataclasses.dataclass
+class Grid:
+    ox: float
+    oy: float
+    oz: float
+    h: float
+    nx: int
+    ny: int
+    nz: int
+
+    @classmethod
+    def cube(cls, half, h):
+        n = int(round(2 * half / h))
+        return cls(-half, -half, -half, h, n, n, n)
+
+    @property
+    def ncell(self):
+        return self.nx * self.ny * self.nz
+
+    def struct(self):
+        return _abi.SbpGrid(self.ox, self.oy, self.oz, self.h, self.nx, self.ny, self.nz, 0)
+
+
+def grid_mass(ctx, balls, ball_off, grid: Grid, B_cap=None, mass=None, stream=None):
+    """sbp_grid_mass: p0 summed per cell over frame 0."""
+    dev = balls["x"].device
+    if mass is None:
+        mass = torch.empty(grid.ncell, dtype=torch.float32, device=dev)
+    cap = balls["x"].numel() if B_cap is None else int(B_cap)
+    check(lib().sbp_grid_mass(ctx.ptr, ctypes.byref(balls_struct(balls)), _p(_need(ball_off, torch.int64, "ball_off")),
+                              cap, ctypes.byref(grid.struct()), _p(_need(mass, name="mass")), _stream(stream)))
+    return mass
+
+
+def candidates(ctx, grid: Grid, mass, occ, a_probe, sites=None, stream=None):
+    """sbp_candidates: (sites as a probe-ball SoA of capacity ncell, count)."""
+    dev = mass.device
+    if sites is None:
+        sites = {k: torch.empty(grid.ncell, dtype=torch.float32, device=dev) for k in PARAMS}
+    cap = sites["x"].numel()
+    cnt = ctypes.c_int64()
+    check(lib().sbp_candidates(ctx.ptr, ctypes.byref(grid.struct()), _p(_need(mass, name="mass")), float(occ),
+                               float(a_probe), ctypes.byref(balls_struct(sites)), cap, ctypes.byref(cnt),
+                               _stream(stream)))
+    return sites, cnt.value
+
+
+def features(ctx, grid: Grid, mass, sites, M, g, half, X=None, stream=None):
+    """sbp_features: feature rows [M][31]."""
+    dev = mass.device
+    if X is None:
+        X = torch.empty((M, MLP_IN), dtype=torch.float32, device=dev)
+    gb = _abi.SbpBalls(_p(g["x"]), _p(g["y"]), _p(g["z"]), _p(g["p0"]), None)
+    check(lib().sbp_features(ctx.ptr, ctypes.byref(grid.struct()), _p(mass), ctypes.byref(balls_struct(sites)),
+                             int(M), ctypes.byref(gb), float(half), _p(_need(X, name="X")), _stream(stream)))
+    return X
+
+
+def append_proposals(ctx, state: api.State, sites, out, M, a_init, p0_scale=1.0, stream=None):
+    """sbp_append_proposals: returns the new ball count of frame 0."""
+    cnt = ctypes.c_int64()
+    check(lib().sbp_append_proposals(ctx.ptr, ctypes.byref(state.struct()), ctypes.byref(balls_struct(sites)),
+                                     _p(_need(out, name="out")), int(M), float(a_init), float(p0_scale),
+                                     ctypes.byref(cnt), _stream(stream)))
+    return cnt.value
+
+
+class FeatureBuilder:
+    """Candidate sites and their features for one state, reusing its buffers."""
+
+    def __init__(self, ctx, grid: Grid, occ=0.1, a_probe=0.1, half=10.0, device="cuda:0"):
+        self.ctx, self.grid, self.occ, self.a_probe, self.half = ctx, grid, occ, a_probe, half
+        dev = torch.device(device)
+        self.mass = torch.empty(grid.ncell, dtype=torch.float32, device=dev)
+        self.sites = {k: torch.empty(grid.ncell, dtype=torch.float32, device=dev) for k in PARAMS}
+        self.g = {k: torch.empty(grid.ncell, dtype=torch.float32, device=dev) for k in PARAMS}
+        self.off = torch.zeros(2, dtype=torch.int64, device=dev)
+
+    def build(self, A, state: api.State, model: api.Model, v):
+        """(M, X [M][31], sites) given v = dL/dy_sim of the current state."""
+        grid_mass(self.ctx, state.balls, state.ball_off, self.grid, B_cap=state.B_cap, mass=self.mass)
+        _, M = candidates(self.ctx, self.grid, self.mass, self.occ, self.a_probe, sites=self.sites)
+        if M == 0:
+            return 0, None, self.sites
+        self.off[1] = M
+        probe_model = dataclasses.replace(model, a_softplus=0)
+        api.adjoint_gradients(self.ctx, A, self.sites, probe_model, v, mask=P0 | XYZ, ball_off=self.off,
+                              grad=self.g, B_cap=M)
+        X = features(self.ctx, self.grid, self.mass, self.sites, M, self.g, self.half)
+        return M, X, self.sites
+
+
+def _residual(r: recon.Recon, model, y_k, yw):
+    st = r.state
+    api.simulate_signals(r.ctx, r.A, st.balls, model, ball_off=st.ball_off, y=yw, B_cap=st.B_cap)
+    return float(api.residual_loss(r.ctx, yw, y_k, v_out=yw).sum().item())
+
+
+class Recorder:
+    """Growth-point hook for plain runs: keeps the candidates' features."""
+
+    def __init__(self, builder: FeatureBuilder):
+        self.builder = builder
+        self.events = []
+
+    def __call__(self, r: recon.Recon, si, model, y_k, yw):
+        _residual(r, model, y_k, yw)
+        M, X, sites = self.builder.build(r.A, r.state, model, yw)
+        if M == 0:
+            return
+        xyz = torch.stack([sites["x"][:M], sites["y"][:M], sites["z"][:M]], dim=1).cpu().numpy()
+        self.events.append(dict(stage=si, X=X.cpu().numpy(), xyz=xyz))
+
+
+class LearnedProposer:
+    """Growth-point hook that appends the sites the network accepts.
+
+    The accepted balls enter along one direction of the parameter space (their
+    predicted p0 values); their common scale is the exact minimiser of the
+    quadratic loss along it, alpha* = -<e, s> / <s, s> (e the current
+    residual, s the signal of the appended balls at the predicted p0), taken
+    from three loss evaluations: ||e||^2, ||s||^2 and ||e + s||^2.  If
+    alpha* <= 0, or the loss at alpha* is not below ||e||^2 (the judge), the
+    balls are removed again.
+    """
+
+    def __init__(self, mlp: ProposalMLP, builder: FeatureBuilder, a_init=0.1, judge=True,
+                 max_scale=4.0):
+        self.mlp, self.builder, self.a_init, self.judge = mlp, builder, a_init, judge
+        self.max_scale = max_scale
+        self.events = []
+        self._zero = None
+        self._ys = None
+        self._off = None
+
+    def __call__(self, r: recon.Recon, si, model, y_k, yw):
+        st = r.state
+        if st.F != 1:
+            raise ValueError("the learned proposal works on single-frame states")
+        L0 = _residual(r, model, y_k, yw)
+        M, X, sites = self.builder.build(r.A, st, model, yw)
+        ev = dict(stage=si, candidates=M, accepted=0, kept=False, loss_before=L0, loss_after=L0, scale=0.0)
+        self.events.append(ev)
+        if M == 0:
+            return
+        out = self.mlp.forward(X)
+        n_old = st.count()
+        try:
+            n_new = append_proposals(r.ctx, st, sites, out, M, self.a_init)
+        except _abi.SbpError as e:
+            if e.code != _abi.SBP_E_CAPACITY:
+                raise
+            return
+        ev["accepted"] = n_new - n_old
+        if n_new == n_old:
+            return
+        dev = yw.device
+        if self._zero is None or self._zero.shape != yw.shape:
+            self._zero = torch.zeros_like(yw)
+            self._ys = torch.empty_like(yw)
+            self._off = torch.zeros(2, dtype=torch.int64, device=dev)
+        self._off[0], self._off[1] = n_old, n_new
+        api.simulate_signals(r.ctx, r.A, st.balls, model, ball_off=self._off, y=self._ys, B_cap=st.B_cap)
+        Ls = float(api.residual_loss(r.ctx, self._ys, self._zero).sum().item())
+        L1 = _residual(r, model, y_k, yw)
+        st.ball_off[1:2].fill_(n_old)
+        es = 0.5 * (L1 - L0 - Ls)
+        if not (Ls > 0.0 and es < 0.0):
+            return
+        alpha = min(-es / Ls, self.max_scale)
+        append_proposals(r.ctx, st, sites, out, M, self.a_init, p0_scale=alpha)
+        L2 = _residual(r, model, y_k, yw)
+        ev.update(scale=alpha, loss_after=L2)
+        if self.judge and not L2 < L0:
+            st.ball_off[1:2].fill_(n_old)
+        else:
+            ev["kept"] = True
+
+
+# ---------------------------------------------------------- data & A/B --
+
+def proposal_workload(index, n_init=200_000, n_det=512):
+    """A conformal-array workload (the 512-element jittered ellipsoid, a
+    branching-tree phantom, 2048 samples at 40 MHz) from seed stream 5."""
+    rng = synth.rng_for(5, index)
+    arr = synth.ellipsoid_array(n_det, (20.0, 15.0, 10.0), rng, jitter=1.0)
+    region = synth.Region(10.0, (18.0, 13.0, 8.0))
+    gt = synth.drop_near(synth.tree_phantom(rng, region), arr, 1.5)
+    init = synth.drop_near(synth.region_init(rng, region, n_init), arr, 1.5)
+    return synth.Workload(f"proposal-{index}", arr, gt, init, 2048, 0.025, (4, 2, 1), 0.1)
+
+
+def synthetic_measurement(ctx, wl, noise=0.05, seed=0, device="cuda:0"):
+    dev = torch.device(device)
+    A = {k: torch.as_tensor(v, device=dev) for k, v in wl.array.items()}
+    gt = {k: torch.as_tensor(v, device=dev) for k, v in wl.gt.items()}
+    y = api.simulate_signals(ctx, A, gt, api.Model(c=synth.C, dt=wl.dt, T=wl.T, f=1))
+    if noise > 0:
+        rng = np.random.default_rng(seed)
+        sigma = noise * float(y.abs().max())
+        y = y + sigma * torch.as_tensor(rng.normal(size=tuple(y.shape)).astype(np.float32), device=dev)
+    return y.contiguous()
+
+
+def default_schedule(levels, iters=60, grow_every=20):
+    return recon.plain_schedule(levels, iters=iters, coarse_grow_every=grow_every,
+                                fine_grow_every=grow_every, softplus_frac=0.2, tol=1e-3)
+
+
+def label_events(events, grid: Grid, final_mass, threshold=0.1):
+    """(X, grow label, p0 target) from recorded events and the final cell masses."""
+    fm = np.asarray(final_mass, np.float64).reshape(grid.nx, grid.ny, grid.nz)
+    Xs, ys, ps = [], [], []
+    for ev in events:
+        xyz = ev["xyz"]
+        idx = np.rint((xyz - np.array([grid.ox, grid.oy, grid.oz])) / grid.h - 0.5).astype(np.int64)
+        idx = np.clip(idx, 0, np.array([grid.nx, grid.ny, grid.nz]) - 1)
+        m = fm[idx[:, 0], idx[:, 1], idx[:, 2]]
+        Xs.append(ev["X"])
+        ys.append((m > threshold).astype(np.float32))
+        ps.append(np.where(m > threshold, m, 0.0).astype(np.float32))
+    return np.concatenate(Xs), np.concatenate(ys), np.concatenate(ps)
+
+
+def plain_run(ctx, wl, y, stages, builder=None, capacity=0, graph_iters=0, stop_below=None, proposer=None):
+    cfg = recon.ReconConfig(stages=stages, T=wl.T, dt=wl.dt, dup_frac=0.05, capacity=capacity,
+                            graph_iters=graph_iters)
+    r = recon.Recon(wl.array, y, wl.init, cfg, ctx=ctx)
+    r.proposer = proposer
+    return r, r.run(stop_below=stop_below)
+
+
+def generate(ctx, indices, grid: Grid, stages, workload=proposal_workload, log=print, **wl_kw):
+    """Training set from plain reconstructions of the given workload indices."""
+    builder = FeatureBuilder(ctx, grid, a_probe=0.1, half=-grid.ox)
+    Xs, ys, ps = [], [], []
+    for i in indices:
+        wl = workload(i, **wl_kw)
+        y = synthetic_measurement(ctx, wl, seed=50_000 + i)
+        rec = Recorder(builder)
+        r, out = plain_run(ctx, wl, y, stages, proposer=rec, capacity=4 * len(wl.init["x"]))
+        st = out["state"]
+        fm = grid_mass(ctx, st.balls, st.ball_off, grid, B_cap=st.B_cap).cpu().numpy()
+        if rec.events:
+            X, yg, yp = label_events(rec.events, grid, fm)
+            Xs.append(X), ys.append(yg), ps.append(yp)
+        log(json.dumps(dict(event="plain-run", index=i, wall_s=round(out["wall_s"], 3),
+                            final_loss=out["final_loss"], growth_points=len(rec.events),
+                            samples=int(sum(len(e["X"]) for e in rec.events)))), flush=True)
+    return np.concatenate(Xs), np.concatenate(ys), np.concatenate(ps)
+
+
+def train(mlp: ProposalMLP, X, yg, yp, epochs=4, batch=8192, lr=1e-3, seed=0, log=print):
+    """Minibatch Adam on the GPU; returns the per-epoch mean losses.  Classes are
+    not re-weighted: a site is accepted where the network's P(grow) > 1/2."""
+    rng = np.random.default_rng(seed)
+    n = len(X)
+    pos_weight = 1.0
+    order = rng.permutation(n)
+    dev = mlp.dev
+    Xd = torch.as_tensor(np.ascontiguousarray(X[order], np.float32), device=dev)
+    gd = torch.as_tensor(np.ascontiguousarray(yg[order], np.float32), device=dev)
+    pd = torch.as_tensor(np.ascontiguousarray(yp[order], np.float32), device=dev)
+    hist = []
+    for ep in range(epochs):
+        start = int(rng.integers(0, min(batch, n - batch + 1))) if n > batch else 0
+        losses = []
+        for s in range(start, n - batch + 1 if n >= batch else 1, batch):
+            e = min(s + batch, n)
+            losses.append(mlp.train_step(Xd[s:e], gd[s:e], pd[s:e], pos_weight=pos_weight, lr=lr))
+        L = float(torch.stack(losses).mean().item())
+        hist.append(L)
+        log(json.dumps(dict(event="epoch", epoch=ep, loss=L, batches=len(losses), pos_weight=pos_weight)),
+            flush=True)
+    return hist
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="Train the growth-proposal network on plain runs and "
+                                             "compare wall time to the plain final residual.")
+    ap.add_argument("--train", type=int, default=16, help="plain reconstructions for training")
+    ap.add_argument("--eval", type=int, default=4, help="held-out phantoms for the comparison")
+    ap.add_argument("--iters", type=int, default=60)
+    ap.add_argument("--epochs", type=int, default=6)
+    ap.add_argument("--n-init", type=int, default=200_000)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    ctx = api.context(0)
+    grid = Grid.cube(10.0, 0.2)
+    stages = default_schedule((4, 2, 1), iters=args.iters)
+    t0 = time.perf_counter()
+    X, yg, yp = generate(ctx, range(args.train), grid, stages, n_init=args.n_init)
+    t_gen = time.perf_counter() - t0
+    mlp = ProposalMLP(ctx, seed=0)
+    t0 = time.perf_counter()
+    hist = train(mlp, X, yg, yp, epochs=args.epochs)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    rows = []
+    for j in range(args.eval):
+        i = 10_000 + j
+        wl = proposal_workload(i, n_init=args.n_init)
+        y = synthetic_measurement(ctx, wl, seed=60_000 + j)
+        _, plain = plain_run(ctx, wl, y, stages, capacity=4 * len(wl.init["x"]))
+        target = plain["final_loss"]
+        lp = LearnedProposer(mlp, FeatureBuilder(ctx, grid, a_probe=0.1, half=10.0), a_init=wl.a_init)
+        r, learned = plain_run(ctx, wl, y, stages, capacity=4 * len(wl.init["x"]), stop_below=target,
+                               proposer=lp)
+        row = dict(event="compare", index=i, plain_wall_s=plain["wall_s"], plain_final_loss=target,
+                   learned_wall_s=learned.get("t_target") or learned["wall_s"],
+                   learned_reached=learned.get("t_target") is not None,
+                   learned_final_loss=learned["final_loss"],
+                   proposals_kept=sum(e["kept"] for e in lp.events),
+                   proposals_tried=len(lp.events))
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    summary = dict(event="summary", train_runs=args.train, samples=len(X), positives=float(np.mean(yg)),
+                   generate_s=t_gen, train_s=t_train, epoch_losses=hist,
+                   plain_wall_s=float(np.mean([r["plain_wall_s"] for r in rows])) if rows else None,
+                   learned_wall_s=float(np.mean([r["learned_wall_s"] for r in rows])) if rows else None,
+                   reached=sum(r["learned_reached"] for r in rows))
+    print(json.dumps(summary), flush=True)
+    if args.out:
+        with open(args.out, "w") as fh:
+            json.dump(dict(rows=rows, summary=summary), fh, indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

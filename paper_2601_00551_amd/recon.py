@@ -112,6 +112,9 @@ class Recon:
         self.log = []
         self.t_start = None
         self.last_loss = None
+        # optional growth-point hook proposer(recon, stage_index, model, y_k, y_work),
+        # called after each split / destroy / duplicate (the learned proposal)
+        self.proposer = None
 
     # ------------------------------------------------------------ helpers --
     def model(self, f, a_softplus=0):
@@ -139,9 +142,11 @@ class Recon:
         api.adjoint_gradients(self.ctx, self.A, s.balls, model, y_work, mask=ALL, ball_off=s.ball_off,
                               grad=s.grad, B_cap=s.B_cap)
 
-    def _grow(self, dup_frac):
+    def _grow(self, dup_frac, si=None, model=None, y_k=None, y_work=None):
         new, _ = api.grow(self.ctx, self.state, self._rule(dup_frac), capacity=self.cap)
         self.state = new
+        if self.proposer is not None and model is not None:
+            self.proposer(self, si, model, y_k, y_work)
 
     def _reset_adam(self):
         for k in PARAMS:
@@ -183,8 +188,11 @@ class Recon:
         return meta
 
     # --------------------------------------------------------------- run --
-    def run(self, resume=False, fail_at=None, on_iter=None):
+    def run(self, resume=False, fail_at=None, on_iter=None, stop_below=None):
+        """Run the schedule.  stop_below: end as soon as the last stage's loss
+        is at or below this value (the time is reported as t_target)."""
         cfg = self.cfg
+        t_target = None
         start_stage, start_it, step, softplus_on = 0, 0, 1, False
         if resume:
             meta = self.load_checkpoint()
@@ -205,7 +213,7 @@ class Recon:
                     self._filter(model, y_k)
                 if stg.duplicate and cfg.dup_frac > 0:
                     self._gradients(model, y_k, yw)
-                    self._grow(cfg.dup_frac)
+                    self._grow(cfg.dup_frac, si, model, y_k, yw)
                 self._reset_adam()
                 step, it0 = 1, 0
                 self._log(si, -1, stg, None, "stage-entry")
@@ -251,8 +259,14 @@ class Recon:
                         on_iter(self, si, it, L)
                     step += 1
                     it += 1
-                if stg.grow_every and it % stg.grow_every == 0 and it < stg.iters:
-                    self._grow(0.0)
+                    if (stop_below is not None and t_target is None and si == len(cfg.stages) - 1
+                            and L <= stop_below):
+                        t_target = time.perf_counter() - self.t_start
+                if t_target is not None:
+                    break
+                # no growth in the softplus refinement: the arrays hold a~ there
+                if stg.grow_every and it % stg.grow_every == 0 and it < stg.iters and not softplus_on:
+                    self._grow(0.0, si, model, y_k, yw)
                     graph = None
                 if cfg.checkpoint_every and it % cfg.checkpoint_every == 0:
                     self.save_checkpoint(si, it, step, softplus_on)
@@ -273,7 +287,7 @@ class Recon:
             self.save_checkpoint(si + 1, 0, 1, False)
         torch.cuda.synchronize(self.dev)
         return {"state": self.state, "log": self.log, "final_loss": self.last_loss,
-                "wall_s": time.perf_counter() - self.t_start}
+                "wall_s": time.perf_counter() - self.t_start, "t_target": t_target}
 
     def _log(self, si, it, stg, L, kind):
         rec = {"stage": si, "it": it, "f": stg.f, "kind": kind, "loss": L,
