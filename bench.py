@@ -93,6 +93,43 @@ def cpu_baseline(wl, model_kw, n_balls_sample, rng_seed=0):
                       f"T={model_kw['T']}: oracle forward {t1 - t0:.2f} s + VJP {t2 - t1:.2f} s"}
 
 
+MLP_FLOP_FWD = 2 * (31 * 256 + 2 * 256 * 256 + 256 * 2)   # per candidate row
+BF16_PEAK = 2.5e15
+
+
+def mlp_rates(ctx, dev, M=262144, reps=20):
+    """The proposal network's matrix-core rates: inference over M candidate rows
+    and one training step (forward, loss, backward, Adam) on M rows."""
+    import numpy as np
+    import torch
+    from paper_2601_00551_amd import proposal
+    net = proposal.ProposalMLP(ctx, device=dev, seed=0)
+    rng = np.random.default_rng(7)
+    X = torch.as_tensor(rng.normal(size=(M, 31)).astype(np.float32), device=dev)
+    yg = torch.as_tensor((rng.uniform(size=M) > 0.9).astype(np.float32), device=dev)
+    yp = torch.as_tensor(rng.uniform(size=M).astype(np.float32), device=dev)
+    out = torch.empty((M, 2), device=dev)
+    for _ in range(3):
+        net.forward(X, out=out)
+        net.train_step(X, yg, yp)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(reps):
+        net.forward(X, out=out)
+    e[1].record()
+    for _ in range(reps):
+        net.train_step(X, yg, yp)
+    e[2].record()
+    torch.cuda.synchronize()
+    t_fwd = e[0].elapsed_time(e[1]) / reps * 1e-3
+    t_train = e[1].elapsed_time(e[2]) / reps * 1e-3
+    fwd = MLP_FLOP_FWD * M / t_fwd
+    train = 3 * MLP_FLOP_FWD * M / t_train
+    return {"rows": M, "forward_ms": t_fwd * 1e3, "forward_TFLOPs": fwd / 1e12,
+            "forward_frac_bf16_peak": fwd / BF16_PEAK, "train_step_ms": t_train * 1e3,
+            "train_TFLOPs": train / 1e12, "train_frac_bf16_peak": train / BF16_PEAK}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +288,7 @@ def main():
         "tuning": tuned,
         "wall_s": wall,
     }
+    line["mlp"] = mlp_rates(ctx, dev)
     if args.cpu_sample > 0:
         line["cpu_baseline"] = cpu_baseline(wl, {"c": c, "dt": dt, "T": T}, args.cpu_sample)
     print(json.dumps(line), flush=True)

@@ -1,15 +1,19 @@
-"""The learned growth proposal end to end on small conformal workloads:
-training data from plain reconstructions, training on the GPU, then the
-comparison with the plain method on a held-out phantom (wall time to the
-plain method's final residual).  The loss judge guarantees that every kept
-proposal lowered the data-fidelity loss at its growth point."""
+"""The learned growth proposal end to end: training data from plain
+reconstructions, training on the GPU, then the comparison with the plain
+method on held-out phantoms (wall time to the plain method's final residual).
+
+Workload: the conformal array (512 elements on the jittered ellipsoid), a
+branching-tree phantom, 2048 samples at 40 MHz with 5% noise, and a sparse
+initial cloud of 20,000 lattice balls, where growth decides how fast the
+phantom is covered.  The loss judge guarantees that every kept proposal
+lowered the data-fidelity loss at its growth point."""
 import json
 
 import numpy as np
 import pytest
 import torch
 
-from paper_2601_00551_amd import api, proposal, synth
+from paper_2601_00551_amd import api, proposal
 
 pytestmark = pytest.mark.gpu
 
@@ -21,41 +25,37 @@ def ctx(gpu):
     c.close()
 
 
-def small_workload(index, n_init=20000, n_det=128):
-    rng = synth.rng_for(5, 500 + index)
-    arr = synth.ellipsoid_array(n_det, (20.0, 15.0, 10.0), rng, jitter=1.0)
-    region = synth.Region(10.0, (18.0, 13.0, 8.0))
-    gt = synth.drop_near(synth.tree_phantom(rng, region, max_depth=4), arr, 1.5)
-    init = synth.drop_near(synth.region_init(rng, region, n_init), arr, 1.5)
-    return synth.Workload(f"small-proposal-{index}", arr, gt, init, 1024, 0.025, (4, 2, 1), 0.1)
-
-
-def test_learned_proposal_against_plain(ctx):
+def test_learned_proposal_gains_over_plain(ctx):
     grid = proposal.Grid.cube(10.0, 0.2)
-    stages = proposal.default_schedule((4, 2, 1), iters=30, grow_every=10)
+    stages = proposal.default_schedule((4, 2, 1), iters=60)
     logs = []
-    X, yg, yp = proposal.generate(ctx, range(3), grid, stages, workload=small_workload,
+    X, yg, yp = proposal.generate(ctx, range(6), grid, stages, n_init=20000,
                                   log=lambda s, **k: logs.append(s))
     assert len(X) == len(yg) == len(yp) > 0 and X.shape[1] == 31
-    assert 0.0 < yg.mean() < 1.0
-    net = proposal.ProposalMLP(ctx, seed=1)
-    hist = proposal.train(net, X, yg, yp, epochs=4, batch=4096, lr=1e-3, log=lambda s, **k: logs.append(s))
+    assert 0.0 < yg.mean() < 0.1
+    net = proposal.ProposalMLP(ctx, seed=0)
+    hist = proposal.train(net, X, yg, yp, epochs=6, log=lambda s, **k: logs.append(s))
     assert hist[-1] < hist[0]
-    wl = small_workload(100)
-    y = proposal.synthetic_measurement(ctx, wl, seed=7)
-    cap = 4 * len(wl.init["x"])
-    _, plain = proposal.plain_run(ctx, wl, y, stages, capacity=cap)
-    lp = proposal.LearnedProposer(net, proposal.FeatureBuilder(ctx, grid, a_probe=0.1, half=10.0),
-                                  a_init=wl.a_init)
-    _, learned = proposal.plain_run(ctx, wl, y, stages, capacity=cap, stop_below=plain["final_loss"],
-                                    proposer=lp)
-    assert lp.events, "no growth point was reached"
-    for ev in lp.events:
-        if ev["kept"]:
-            assert ev["loss_after"] < ev["loss_before"], ev
-    row = dict(plain_wall_s=plain["wall_s"], plain_final_loss=plain["final_loss"],
-               learned_t_target=learned["t_target"], learned_wall_s=learned["wall_s"],
-               learned_final_loss=learned["final_loss"], kept=sum(e["kept"] for e in lp.events),
-               tried=len(lp.events), accepted=[e["accepted"] for e in lp.events])
-    print(json.dumps(row))
-    assert np.isfinite(learned["final_loss"])
+    rows = []
+    for j in range(2):
+        wl = proposal.proposal_workload(10_000 + j, n_init=20000)
+        y = proposal.synthetic_measurement(ctx, wl, seed=60_000 + j)
+        cap = 4 * len(wl.init["x"])
+        _, plain = proposal.plain_run(ctx, wl, y, stages, capacity=cap)
+        target = plain["final_loss"] * (1.0 + 1e-3)
+        t_plain = proposal.first_below(plain["log"], target)
+        lp = proposal.LearnedProposer(net, proposal.FeatureBuilder(ctx, grid, a_probe=0.1, half=10.0),
+                                      a_init=wl.a_init)
+        _, learned = proposal.plain_run(ctx, wl, y, stages, capacity=cap, stop_below=target, proposer=lp,
+                                        graph_iters=10)
+        for ev in lp.events:
+            if ev["kept"]:
+                assert ev["loss_after"] < ev["loss_before"], ev
+        row = dict(phantom=10_000 + j, plain_s=t_plain, learned_s=learned["t_target"],
+                   plain_final_loss=plain["final_loss"], kept=sum(e["kept"] for e in lp.events),
+                   tried=len(lp.events))
+        rows.append(row)
+        print(json.dumps(row))
+    for row in rows:
+        assert row["learned_s"] is not None, row        # reached the plain final residual
+        assert row["learned_s"] < row["plain_s"], row   # and sooner
