@@ -130,6 +130,149 @@ def mlp_rates(ctx, dev, M=262144, reps=20):
             "train_TFLOPs": train / 1e12, "train_frac_bf16_peak": train / BF16_PEAK}
 
 
+def _timed(fn, reps):
+    """Average milliseconds of fn() over reps calls, bracketed by events on the current stream."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def suite(args):
+    """The other workloads, one JSON line each: per-iteration latency of the tiny
+    workload (eager vs graph), per-level rates of the conformal workload, the
+    16-frame batched iteration (graph-captured), and the large workload with
+    uniform balls."""
+    import numpy as np
+    import torch
+    from paper_2601_00551_amd import api, autotune, synth
+
+    dev = torch.device("cuda:0")
+    ctx = api.Context(0)
+    c = 1.5
+
+    def measured(wl, noise=0.05, seed=0):
+        A = {k: torch.as_tensor(v, device=dev) for k, v in wl.array.items()}
+        gt = {k: torch.as_tensor(v, device=dev) for k, v in wl.gt.items()}
+        y = api.simulate_signals(ctx, A, gt, api.Model(c=c, dt=wl.dt, T=wl.T, f=1))
+        if noise > 0:
+            rng = np.random.default_rng(seed)
+            y = y + noise * float(y.abs().max()) * torch.as_tensor(
+                rng.normal(size=tuple(y.shape)).astype(np.float32), device=dev)
+        return A, y.contiguous()
+
+    def fwd_adj(A, st, model, y_k, reps=5):
+        yw = torch.empty_like(y_k)
+        f = lambda: api.simulate_signals(ctx, A, st.balls, model, ball_off=st.ball_off, y=yw, B_cap=st.B_cap)
+        b = lambda: api.adjoint_gradients(ctx, A, st.balls, model, y_k, mask=api.ALL, ball_off=st.ball_off,
+                                          grad=st.grad, B_cap=st.B_cap)
+        f(), b()
+        return _timed(f, reps), _timed(b, reps)
+
+    def iteration_rates(A, st, model, y_k, iters=10, reps=3):
+        yw = torch.empty_like(y_k)
+        prm = api.AdamParams(step=1)
+        loss = torch.empty(st.F, dtype=torch.float64, device=dev)
+        eager = lambda: api.step(ctx, A, st, model, y_k, yw, prm, loss=loss)
+        eager()
+        t_eager = _timed(eager, iters * reps)
+        g = api.StepGraph(ctx, A, st, model, y_k, yw, prm, iters=iters, step0=1)
+        cur = torch.cuda.current_stream(dev)
+        launch = lambda: g.launch(stream=cur)
+        launch()
+        t_graph = _timed(launch, reps) / iters
+        g.close()
+        return t_eager, t_graph
+
+    def filtered(A, init, model, y_k, off=None):
+        n = len(init["x"])
+        st = api.State(init, ball_off=off, capacity=n, device=dev)
+        out = api.State({k: np.zeros(0) for k in api.PARAMS}, ball_off=[0] * (st.F + 1), capacity=n, device=dev)
+        run = lambda: api.filter_zero_grad(ctx, A, st.balls, model, y_k, ball_off=st.ball_off, out=out.balls,
+                                           off_out=out.ball_off, B_cap=n)
+        run()
+        return out, _timed(run, 3)
+
+    # tiny: launch-latency bound
+    wl = synth.tiny_config()
+    A, y = measured(wl, noise=0.0)
+    model = api.Model(c=c, dt=wl.dt, T=wl.T, f=1)
+    st = api.State(wl.init, device=dev)
+    te, tg = iteration_rates(A, st, model, y, iters=10, reps=20)
+    print(json.dumps({"workload": wl.name, "balls": len(wl.init["x"]), "transducers": len(wl.array["qx"]),
+                      "us_per_iteration_eager": te * 1e3, "us_per_iteration_graph": tg * 1e3,
+                      "graph_speedup": te / tg}), flush=True)
+
+    # conformal: per level, filter then forward + adjoint on the kept balls
+    wl = synth.conformal_config()
+    A, y = measured(wl)
+    D = len(wl.array["qx"])
+    for f in wl.levels:
+        model = api.Model(c=c, dt=wl.dt, T=wl.T // f, f=f)
+        autotune.apply_cached(ctx, args.tuning, model, D, len(wl.init["x"]))
+        y_k = api.downsample(ctx, y, f)
+        st, t_filter = filtered(A, wl.init, model, y_k)
+        kept = st.count()
+        tf, tb = fwd_adj(A, st, model, y_k)
+        te, tg = iteration_rates(A, st, model, y_k, iters=10, reps=2)
+        print(json.dumps({"workload": wl.name, "level_f": f, "samples": wl.T // f,
+                          "balls_in": len(wl.init["x"]), "balls_kept": kept, "transducers": D,
+                          "filter_ms": t_filter, "filter_pairs_per_s": len(wl.init["x"]) * D / (t_filter * 1e-3),
+                          "forward_ms": tf, "adjoint_ms": tb,
+                          "fwd_adj_pairs_per_s": kept * D / ((tf + tb) * 1e-3),
+                          "iteration_ms_eager": te, "iteration_ms_graph": tg}), flush=True)
+
+    # batched: 16 uneven frames in one graph-captured iteration at 40 MHz
+    base = wl
+    gts, inits = synth.batched_frames(base)
+    F = len(inits)
+    ys = []
+    for g_ in gts:
+        gt = {k: torch.as_tensor(v, device=dev) for k, v in g_.items()}
+        ys.append(api.simulate_signals(ctx, A, gt, api.Model(c=c, dt=base.dt, T=base.T, f=1))[0])
+    y = torch.stack(ys)
+    rng = np.random.default_rng(4000)
+    y += 0.05 * float(y.abs().max()) * torch.as_tensor(rng.normal(size=tuple(y.shape)).astype(np.float32),
+                                                       device=dev)
+    balls = synth.concat_balls(inits)
+    off = np.cumsum([0] + [len(b["x"]) for b in inits]).tolist()
+    model = api.Model(c=c, dt=base.dt, T=base.T, f=1)
+    autotune.apply_cached(ctx, args.tuning, model, D, max(np.diff(off)))
+    st, t_filter = filtered(A, balls, model, y.contiguous(), off=off)
+    kept_off = st.ball_off.cpu().numpy()
+    kept = int(kept_off[-1])
+    tf, tb = fwd_adj(A, st, model, y.contiguous())
+    te, tg = iteration_rates(A, st, model, y.contiguous(), iters=5, reps=2)
+    print(json.dumps({"workload": "batched-16-frames-ell512-T2048-40MHz", "frames": F,
+                      "balls_in": off[-1], "balls_kept": kept,
+                      "kept_per_frame_min": int(np.min(np.diff(kept_off))),
+                      "kept_per_frame_max": int(np.max(np.diff(kept_off))), "transducers": D,
+                      "filter_ms": t_filter, "forward_ms": tf, "adjoint_ms": tb,
+                      "fwd_adj_pairs_per_s": kept * D / ((tf + tb) * 1e-3),
+                      "iteration_ms_eager": te, "iteration_ms_graph": tg,
+                      "iteration_pairs_per_s_graph": kept * D / (tg * 1e-3)}), flush=True)
+
+    # large, uniform balls
+    wl = synth.large_config()
+    A = {k: torch.as_tensor(v, device=dev) for k, v in wl.array.items()}
+    model = api.Model(c=c, dt=wl.dt, T=wl.T, f=1, profile=api.PROFILE_UNIFORM)
+    autotune.apply_cached(ctx, args.tuning, model, len(wl.array["qx"]), len(wl.init["x"]))
+    st = api.State(wl.init, device=dev)
+    y = api.simulate_signals(ctx, A, st.balls, model)
+    tf, tb = fwd_adj(A, st, model, y)
+    B, D = len(wl.init["x"]), len(wl.array["qx"])
+    E = edges_per_pair(0.15, c * wl.dt)
+    ops_f = B * D * (OPS_GEOMETRY + E * OPS_FWD_EDGE)
+    print(json.dumps({"workload": wl.name.replace("uniform2M", "uniform2M-uniformballs"), "profile": "uniform",
+                      "forward_ms": tf, "adjoint_ms": tb, "fwd_adj_pairs_per_s": B * D / ((tf + tb) * 1e-3),
+                      "forward_frac_alu": ops_f / (tf * 1e-3) / VALU_PEAK}), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,7 +283,12 @@ def main():
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2601_00551_amd", "tuning.json"))
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (the reference for HBM counters)")
+    ap.add_argument("--suite", action="store_true",
+                    help="measure the other workloads instead (one JSON line each)")
     args = ap.parse_args()
+    if args.suite:
+        suite(args)
+        return
     if args.copy_calibration:
         import torch
         src = torch.ones(1 << 28, device="cuda:0")     # 1 GiB of float32

@@ -209,8 +209,12 @@ int sbp_downsample(sbp_ctx *ctx, const float *y, int64_t R, int32_t T, int32_t f
  * (psi is the antiderivative of u * fhat(u), zero outside the support;
  * rho_id = |r_i - q_d|; D_id is the directivity).  Pairs with
  * rho_id <= support half-width and balls with a <= 0 contribute nothing.
- * y is [F][D][model->T]; it is overwritten unless accumulate = 1.
- * Errors: SBP_E_ARG, SBP_E_DOMAIN, SBP_E_HIP. */
+ * y is [F][D][model->T]; it is overwritten unless accumulate = 1.  Every bin
+ * value is rounded to a multiple of a per-call power-of-two quantum (at most
+ * 2^-31 of the largest possible bin value) and the multiples are summed
+ * exactly, so the result is bitwise reproducible however the work is split.
+ * The context's scratch holds 8 bytes per output sample during the call.
+ * Errors: SBP_E_ARG, SBP_E_DOMAIN, SBP_E_HIP, SBP_E_NOMEM. */
 int sbp_simulate_signals(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *balls,
                          const int64_t *ball_off, int32_t F, int64_t B_cap,
                          const sbp_model *model, float *y, int32_t accumulate, void *stream);
@@ -228,8 +232,11 @@ int sbp_residual_loss(sbp_ctx *ctx, const float *y_sim, const float *y_ref, int6
  * parameter theta in `mask` (SBP_* bits).  v = dL/dy; for the L2 loss the
  * caller passes v = 2 (y_sim - y_ref) (the factor 2 is not applied here).
  * Gradient arrays outside `mask` may be NULL and are not touched; those in
- * the mask are overwritten for balls [0, ball_off[F]).
- * Errors: SBP_E_ARG (mask 0 or a needed pointer NULL), SBP_E_DOMAIN, SBP_E_HIP. */
+ * the mask are overwritten for balls [0, ball_off[F]).  Small clouds are split
+ * over transducer slices whose partial sums (in the context's scratch) are
+ * added in a fixed order: results are reproducible run to run.
+ * Errors: SBP_E_ARG (mask 0 or a needed pointer NULL), SBP_E_DOMAIN, SBP_E_HIP,
+ * SBP_E_NOMEM. */
 int sbp_adjoint_gradients(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *balls,
                           const int64_t *ball_off, int32_t F, int64_t B_cap,
                           const sbp_model *model, const float *v, uint32_t mask,

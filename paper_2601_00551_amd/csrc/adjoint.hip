@@ -108,12 +108,18 @@ __device__ inline void adj_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx,
     }
 }
 
+// Work items are (frame, ball chunk, transducer slice).  With one slice the
+// kernel writes the gradients; with nsl > 1 each item writes its slice's
+// partial sums to part[(slice * NF + field) * pstride + ball] (NF = 5, or 1
+// for the p0-only variant) and k_adj_reduce adds the slices in a fixed order,
+// so results do not depend on scheduling.
 template <typename R, int PROF, int DIR, bool FULL>
 __global__ __launch_bounds__(512, 4) void k_adjoint(ArrayP<R> arr, BallsP<R> balls,
                                                  const int64_t *__restrict__ ball_off, int F,
-                                                 int ds, int TT, int bpt, Level lc,
-                                                 const R *__restrict__ v, R vscale,
-                                                 uint32_t mask, BallsP<R> grad) {
+                                                 int ds, int TT, int bpt, int nsl, int dsl,
+                                                 Level lc, const R *__restrict__ v, R vscale,
+                                                 uint32_t mask, BallsP<R> grad,
+                                                 R *__restrict__ part, int64_t pstride) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     R *rows = reinterpret_cast<R *>(lds_raw);
     __shared__ int64_t s_off[SBP_MAX_FRAMES + 1];
@@ -131,11 +137,13 @@ __global__ __launch_bounds__(512, 4) void k_adjoint(ArrayP<R> arr, BallsP<R> bal
             s_cpre[f + 1] = s_cpre[f] + (s_off[f + 1] - s_off[f] + CH - 1) / CH;
     }
     __syncthreads();
-    const int64_t I = s_cpre[F];
+    const int64_t I = s_cpre[F] * nsl;
     for (int64_t it = blockIdx.x; it < I; it += gridDim.x) {
+        const int64_t ci = it / nsl;
+        const int sl = (int)(it - ci * nsl);
         int f = 0;
-        while (it >= s_cpre[f + 1]) ++f;
-        const int64_t base = s_off[f] + (it - s_cpre[f]) * CH;
+        while (ci >= s_cpre[f + 1]) ++f;
+        const int64_t base = s_off[f] + (ci - s_cpre[f]) * CH;
         const int64_t end = min(base + CH, s_off[f + 1]);
         BallK<R, PROF> b[kMaxBpt];
         R acc[kMaxBpt][5];
@@ -153,8 +161,10 @@ __global__ __launch_bounds__(512, 4) void k_adjoint(ArrayP<R> arr, BallsP<R> bal
             }
         }
         const R *vf = v + (int64_t)f * D * (int64_t)T;
-        for (int d0 = 0; d0 < D; d0 += ds) {
-            const int nd = min(ds, D - d0);
+        const int dbeg = sl * dsl;
+        const int dend = min(D, dbeg + dsl);
+        for (int d0 = dbeg; d0 < dend; d0 += ds) {
+            const int nd = min(ds, dend - d0);
             for (int tlo = 0; tlo <= T; tlo += TT) {
                 const int thi = min(tlo + TT, T + 1);
                 __syncthreads();
@@ -185,6 +195,15 @@ __global__ __launch_bounds__(512, 4) void k_adjoint(ArrayP<R> arr, BallsP<R> bal
             const int64_t i = base + (int64_t)jb * nth + tid;
             if (!(jb < bpt && i < end)) continue;
             // dead balls (a <= 0) get exact zeros
+            if (part) {
+                if (FULL) {
+#pragma unroll
+                    for (int k = 0; k < 5; ++k) part[((int64_t)sl * 5 + k) * pstride + i] = acc[jb][k];
+                } else {
+                    part[(int64_t)sl * pstride + i] = acc[jb][3];
+                }
+                continue;
+            }
             if (mask & SBP_X) grad.x[i] = acc[jb][0];
             if (mask & SBP_Y) grad.y[i] = acc[jb][1];
             if (mask & SBP_Z) grad.z[i] = acc[jb][2];
@@ -198,10 +217,79 @@ __global__ __launch_bounds__(512, 4) void k_adjoint(ArrayP<R> arr, BallsP<R> bal
     }
 }
 
+// Sums the transducer slices of the partial gradients, slice 0 first.
+template <typename R, bool FULL>
+__global__ void k_adj_reduce(const R *__restrict__ part, int nsl, int64_t pstride,
+                             const int64_t *__restrict__ ball_off, int F, uint32_t mask,
+                             int a_softplus, const R *__restrict__ a_arr, BallsP<R> grad) {
+    const int64_t lo = ball_off[0], hi = ball_off[F];
+    R *out[5] = {grad.x, grad.y, grad.z, grad.p0, grad.a};
+    for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (FULL) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                if (!(mask & (1u << k))) continue;
+                R s = R(0);
+                for (int sl = 0; sl < nsl; ++sl) s += part[((int64_t)sl * 5 + k) * pstride + i];
+                if (k == 4 && a_softplus) s *= sigmoid_dev(a_arr[i]);
+                out[k][i] = s;
+            }
+        } else {
+            R s = R(0);
+            for (int sl = 0; sl < nsl; ++sl) s += part[(int64_t)sl * pstride + i];
+            grad.p0[i] = s;
+        }
+    }
+}
+
+// Launch plan shared by the launcher and the workspace query: ball chunks of
+// block * bpt balls (shrunk for small clouds), and as many transducer slices
+// as it takes to give the chip about four work items per resident workgroup.
+struct AdjPlan {
+    int block, bpt, nsl, dsl;
+};
+
+// Workspace ceiling of the partial sums; plans that need more use fewer slices.
+constexpr size_t kMaxAdjWs = size_t(512) << 20;
+
+static AdjPlan adjoint_plan(const Ctx *c, int D, int64_t B_cap, int F, size_t slice_bytes) {
+    AdjPlan p;
+    p.block = c->tuning.adj_block;
+    p.bpt = c->tuning.adj_bpt;
+    int ds = c->tuning.adj_dets;
+    if (ds > D) ds = D;
+    const int64_t maxs = (D + ds - 1) / ds;
+    const int64_t want = 4 * (int64_t)c->num_cus * (1024 / p.block > 0 ? 1024 / p.block : 1);
+    auto chunks = [&](int blk, int bpt) {
+        const int64_t ch = (int64_t)blk * bpt;
+        return (B_cap + ch - 1) / ch + F;
+    };
+    while (p.bpt > 1 && chunks(p.block, p.bpt) * maxs < want) --p.bpt;
+    while (p.block > 128 && chunks(p.block, p.bpt) * maxs < want) p.block /= 2;
+    int64_t nsl = (want + chunks(p.block, p.bpt) - 1) / chunks(p.block, p.bpt);
+    if (nsl > maxs) nsl = maxs;
+    if (slice_bytes > 0 && (size_t)nsl * slice_bytes > kMaxAdjWs) nsl = (int64_t)(kMaxAdjWs / slice_bytes);
+    if (nsl < 1) nsl = 1;
+    int64_t dsl = ((D + nsl - 1) / nsl + ds - 1) / ds * ds;
+    p.dsl = (int)dsl;
+    p.nsl = (int)((D + dsl - 1) / dsl);
+    return p;
+}
+
+size_t adjoint_ws_bytes(const Ctx *c, int D, int64_t B_cap, int F, uint32_t mask, size_t elem) {
+    const int nf = (mask & ~SBP_P0) ? 5 : 1;
+    const size_t slice = (size_t)nf * (size_t)B_cap * elem;
+    const AdjPlan p = adjoint_plan(c, D, B_cap, F, slice);
+    if (p.nsl <= 1) return 0;
+    return ((size_t)p.nsl * slice + 255) & ~(size_t)255;
+}
+
 template <typename R, int PROF, int DIR, bool FULL>
 static int run_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
                        const int64_t *ball_off, int F, int64_t B_cap, const Level &lc, const R *v,
-                       R vscale, uint32_t mask, const BallsP<R> &grad, hipStream_t st) {
+                       R vscale, uint32_t mask, const BallsP<R> &grad, void *ws, size_t ws_bytes,
+                       hipStream_t st) {
     auto kern = k_adjoint<R, PROF, DIR, FULL>;
     const size_t reserve = 2 * (SBP_MAX_FRAMES + 1) * sizeof(int64_t) + 256;
     const size_t avail = c->lds_max > reserve ? c->lds_max - reserve : 0;
@@ -211,8 +299,14 @@ static int run_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
     int64_t TT = (int64_t)(avail / ((size_t)ds * sizeof(R)));
     if (TT > (int64_t)lc.T + 1) TT = (int64_t)lc.T + 1;
     if (TT < (int64_t)lc.T + 1 && TT < 64) return fail(SBP_E_DOMAIN, "LDS too small for %d rows", ds);
-    const int block = c->tuning.adj_block;
-    const int bpt = c->tuning.adj_bpt;
+    const int nf = FULL ? 5 : 1;
+    AdjPlan pl = adjoint_plan(c, arr.D, B_cap, F, (size_t)nf * (size_t)B_cap * sizeof(R));
+    if (pl.nsl > 1 && ws_bytes < (size_t)pl.nsl * nf * (size_t)B_cap * sizeof(R)) {
+        pl.nsl = 1;
+        pl.dsl = arr.D;
+    }
+    R *part = pl.nsl > 1 ? (R *)ws : nullptr;
+    const int block = pl.block;
     const size_t lds = (size_t)ds * (size_t)TT * sizeof(R);
     SBP_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds));
@@ -223,54 +317,62 @@ static int run_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
         if (per_cu < 1) per_cu = 1;
         grid = per_cu * c->num_cus;
     }
-    const int64_t CH = (int64_t)block * bpt;
-    const int64_t max_items = (B_cap + CH - 1) / CH + F;
+    const int64_t CH = (int64_t)block * pl.bpt;
+    const int64_t max_items = ((B_cap + CH - 1) / CH + F) * pl.nsl;
     if (grid > max_items) grid = (int)max_items;
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, arr, balls, ball_off, F, ds,
-                       (int)TT, bpt, lc, v, vscale, mask, grad);
+                       (int)TT, pl.bpt, pl.nsl, pl.dsl, lc, v, vscale, mask, grad, part, B_cap);
     SBP_HIP(hipGetLastError());
+    if (part) {
+        int64_t nb = (B_cap + 255) / 256;
+        if (nb > 2048) nb = 2048;
+        hipLaunchKernelGGL((k_adj_reduce<R, FULL>), dim3((int)nb), dim3(256), 0, st, (const R *)part,
+                           pl.nsl, B_cap, ball_off, F, mask, lc.a_softplus, (const R *)balls.a, grad);
+        SBP_HIP(hipGetLastError());
+    }
     return SBP_OK;
 }
 
 template <typename R, bool FULL>
 static int dispatch_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
                             const int64_t *ball_off, int F, int64_t B_cap, const sbp_model *m,
-                            const R *v, R vscale, uint32_t mask, const BallsP<R> &grad,
-                            hipStream_t st) {
+                            const R *v, R vscale, uint32_t mask, const BallsP<R> &grad, void *ws,
+                            size_t ws_bytes, hipStream_t st) {
     const Level lc = make_level(m);
     if (m->profile == SBP_PROFILE_GAUSS) {
         if (m->directivity == SBP_DIR_COS)
             return run_adjoint<R, GAUSS, COS, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v,
-                                                    vscale, mask, grad, st);
+                                                    vscale, mask, grad, ws, ws_bytes, st);
         return run_adjoint<R, GAUSS, OMNI, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v, vscale,
-                                                 mask, grad, st);
+                                                 mask, grad, ws, ws_bytes, st);
     }
     if (m->directivity == SBP_DIR_COS)
         return run_adjoint<R, UNIFORM, COS, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v, vscale,
-                                                  mask, grad, st);
+                                                  mask, grad, ws, ws_bytes, st);
     return run_adjoint<R, UNIFORM, OMNI, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v, vscale,
-                                               mask, grad, st);
+                                               mask, grad, ws, ws_bytes, st);
 }
 
 template <typename R>
 int launch_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
                    int F, int64_t B_cap, const sbp_model *m, const R *v, R vscale,
-                   uint32_t mask, const BallsP<R> &grad, hipStream_t st) {
+                   uint32_t mask, const BallsP<R> &grad, void *ws, size_t ws_bytes, hipStream_t st) {
     if (B_cap == 0) return SBP_OK;
     if ((mask & ~SBP_P0) == 0)
         return dispatch_adjoint<R, false>(c, arr, balls, ball_off, F, B_cap, m, v, vscale, mask,
-                                          grad, st);
+                                          grad, ws, ws_bytes, st);
     return dispatch_adjoint<R, true>(c, arr, balls, ball_off, F, B_cap, m, v, vscale, mask, grad,
-                                     st);
+                                     ws, ws_bytes, st);
 }
 
 template int launch_adjoint<float>(Ctx *, const ArrayP<float> &, const BallsP<float> &,
                                    const int64_t *, int, int64_t, const sbp_model *, const float *,
-                                   float, uint32_t, const BallsP<float> &, hipStream_t);
+                                   float, uint32_t, const BallsP<float> &, void *, size_t,
+                                   hipStream_t);
 template int launch_adjoint<double>(Ctx *, const ArrayP<double> &, const BallsP<double> &,
                                     const int64_t *, int, int64_t, const sbp_model *,
                                     const double *, double, uint32_t, const BallsP<double> &,
-                                    hipStream_t);
+                                    void *, size_t, hipStream_t);
 
 }  // namespace sbp

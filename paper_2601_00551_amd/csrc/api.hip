@@ -11,7 +11,7 @@
 struct sbp_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    void *ws = nullptr;  // residual partial sums and the forward's bound, owned by the graph
+    void *ws = nullptr;  // residual partial sums, forward bound and integer sums, adjoint slices (owned)
     int device = 0;
 };
 
@@ -192,16 +192,19 @@ static int check_tuning(const sbp_tuning *t) {
 static int step_body(Ctx *c, const sbp_array *arr, sbp_state *s, const sbp_model *model,
                      const float *y_ref, float *y_work, const sbp_adam_params *p,
                      const int32_t *step_dev, double *loss, double *partial, unsigned *bound,
+                     void *fwd_ws, size_t fwd_ws_bytes, void *adj_ws, size_t adj_ws_bytes,
                      hipStream_t st) {
     const ArrayP<float> a = arrp<float>(arr);
     const BallsP<float> b = ballsp<float>(&s->balls);
     const BallsP<float> g = ballsp<float>(&s->grad);
-    int rc = launch_forward<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 0, bound, st);
+    int rc = launch_forward<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 0, bound,
+                                   fwd_ws, fwd_ws_bytes, st);
     if (rc) return rc;
     const int64_t n = (int64_t)arr->D * model->T;
     rc = launch_residual_loss(partial, y_work, y_ref, n, s->F, y_work, loss, st);
     if (rc) return rc;
-    rc = launch_adjoint<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 1.0f, p->mask, g, st);
+    rc = launch_adjoint<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 1.0f, p->mask, g,
+                               adj_ws, adj_ws_bytes, st);
     if (rc) return rc;
     return launch_adam(s, p, step_dev, model->a_softplus, st);
 }
@@ -303,8 +306,11 @@ int sbp_simulate_signals(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *ba
     if (accumulate != 0 && accumulate != 1) return fail(SBP_E_ARG, "accumulate must be 0 or 1");
     if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
     if ((rc = set_device(ctx->c))) return rc;
+    const size_t wsb = forward_ws_bytes(F, arr->D, model->T, sizeof(float));
+    if ((rc = ensure_scratch(&ctx->c, wsb))) return rc;
     return launch_forward<float>(&ctx->c, arrp<float>(arr), ballsp<float>(balls), ball_off, F,
-                                 B_cap, model, y, accumulate, ctx->c.misc, (hipStream_t)stream);
+                                 B_cap, model, y, accumulate, ctx->c.misc, ctx->c.scratch, wsb,
+                                 (hipStream_t)stream);
 }
 
 int sbp_simulate_signals_f64(sbp_ctx *ctx, const sbp_array_f64 *arr, const sbp_balls_f64 *balls,
@@ -319,7 +325,7 @@ int sbp_simulate_signals_f64(sbp_ctx *ctx, const sbp_array_f64 *arr, const sbp_b
     if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
     if ((rc = set_device(ctx->c))) return rc;
     return launch_forward<double>(&ctx->c, arrp<double>(arr), ballsp<double>(balls), ball_off, F,
-                                  B_cap, model, y, accumulate, nullptr, (hipStream_t)stream);
+                                  B_cap, model, y, accumulate, nullptr, nullptr, 0, (hipStream_t)stream);
 }
 
 int sbp_residual_loss(sbp_ctx *ctx, const float *y_sim, const float *y_ref, int64_t n_per_frame,
@@ -346,9 +352,11 @@ int sbp_adjoint_gradients(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *b
     if (!v) return fail(SBP_E_ARG, "v is NULL");
     if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
     if ((rc = set_device(ctx->c))) return rc;
+    const size_t wsb = adjoint_ws_bytes(&ctx->c, arr->D, B_cap, F, mask, sizeof(float));
+    if ((rc = ensure_scratch(&ctx->c, wsb))) return rc;
     return launch_adjoint<float>(&ctx->c, arrp<float>(arr), ballsp<float>(balls), ball_off, F,
-                                 B_cap, model, v, 1.0f, mask, ballsp<float>(grad),
-                                 (hipStream_t)stream);
+                                 B_cap, model, v, 1.0f, mask, ballsp<float>(grad), ctx->c.scratch,
+                                 wsb, (hipStream_t)stream);
 }
 
 int sbp_adjoint_gradients_f64(sbp_ctx *ctx, const sbp_array_f64 *arr, const sbp_balls_f64 *balls,
@@ -362,9 +370,11 @@ int sbp_adjoint_gradients_f64(sbp_ctx *ctx, const sbp_array_f64 *arr, const sbp_
     if (!v) return fail(SBP_E_ARG, "v is NULL");
     if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
     if ((rc = set_device(ctx->c))) return rc;
+    const size_t wsb = adjoint_ws_bytes(&ctx->c, arr->D, B_cap, F, mask, sizeof(double));
+    if ((rc = ensure_scratch(&ctx->c, wsb))) return rc;
     return launch_adjoint<double>(&ctx->c, arrp<double>(arr), ballsp<double>(balls), ball_off, F,
-                                  B_cap, model, v, 1.0, mask, ballsp<double>(grad),
-                                  (hipStream_t)stream);
+                                  B_cap, model, v, 1.0, mask, ballsp<double>(grad), ctx->c.scratch,
+                                  wsb, (hipStream_t)stream);
 }
 
 int sbp_filter_zero_grad(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *in,
@@ -386,15 +396,17 @@ int sbp_filter_zero_grad(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *in
     }
     if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
     if ((rc = set_device(ctx->c))) return rc;
-    // scratch: [filter gradient (if g_out is NULL)][compaction workspace]
+    // scratch: [filter gradient (if g_out is NULL)][compaction workspace][adjoint slices]
     const size_t g_bytes = g_out ? 0 : (((size_t)B_cap * sizeof(float) + 255) & ~(size_t)255);
-    if ((rc = ensure_scratch(&ctx->c, g_bytes + compact_ws_bytes(B_cap)))) return rc;
+    const size_t c_bytes = (compact_ws_bytes(B_cap) + 255) & ~(size_t)255;
+    const size_t a_bytes = adjoint_ws_bytes(&ctx->c, arr->D, B_cap, F, SBP_P0, sizeof(float));
+    if ((rc = ensure_scratch(&ctx->c, g_bytes + c_bytes + a_bytes))) return rc;
     float *g = g_out ? g_out : (float *)ctx->c.scratch;
     void *ws = (char *)ctx->c.scratch + g_bytes;
     hipStream_t st = (hipStream_t)stream;
     BallsP<float> gp{nullptr, nullptr, nullptr, g, nullptr};
     rc = launch_adjoint<float>(&ctx->c, arrp<float>(arr), ballsp<float>(in), off_in, F, B_cap, model,
-                               y_ref, -2.0f, SBP_P0, gp, st);
+                               y_ref, -2.0f, SBP_P0, gp, (char *)ws + c_bytes, a_bytes, st);
     if (rc) return rc;
     BallsP<float> mi, vi, mo, vo;
     if (any_mom) {
@@ -428,9 +440,15 @@ int sbp_step(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state, const sbp_mod
     if (!y_ref || !y_work || !loss) return fail(SBP_E_ARG, "y_ref, y_work or loss is NULL");
     if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
     if ((rc = set_device(ctx->c))) return rc;
-    if ((rc = ensure_scratch(&ctx->c, residual_ws_bytes(state->F)))) return rc;
-    return step_body(&ctx->c, arr, state, model, y_ref, y_work, p, nullptr, loss,
-                     (double *)ctx->c.scratch, ctx->c.misc, (hipStream_t)stream);
+    // scratch: [residual partial sums][forward integer sums][adjoint slices]
+    const size_t r_bytes = (residual_ws_bytes(state->F) + 255) & ~(size_t)255;
+    const size_t f_bytes = forward_ws_bytes(state->F, arr->D, model->T, sizeof(float));
+    const size_t a_bytes = adjoint_ws_bytes(&ctx->c, arr->D, state->B_cap, state->F, p->mask, sizeof(float));
+    if ((rc = ensure_scratch(&ctx->c, r_bytes + f_bytes + a_bytes))) return rc;
+    char *sc = (char *)ctx->c.scratch;
+    return step_body(&ctx->c, arr, state, model, y_ref, y_work, p, nullptr, loss, (double *)sc,
+                     ctx->c.misc, sc + r_bytes, f_bytes, sc + r_bytes + f_bytes, a_bytes,
+                     (hipStream_t)stream);
 }
 
 int sbp_step_graph_create(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state,
@@ -451,8 +469,11 @@ int sbp_step_graph_create(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state,
     hipStream_t st = (hipStream_t)stream;
     sbp_graph *g = new sbp_graph();
     g->device = ctx->c.device;
+    // graph workspace: [residual partial sums][bound word][forward integer sums][adjoint slices]
     const size_t ws_res = (residual_ws_bytes(state->F) + 255) & ~(size_t)255;
-    if (hipMalloc(&g->ws, ws_res + 256) != hipSuccess) {
+    const size_t ws_fwd = forward_ws_bytes(state->F, arr->D, model->T, sizeof(float));
+    const size_t ws_adj = adjoint_ws_bytes(&ctx->c, arr->D, state->B_cap, state->F, p->mask, sizeof(float));
+    if (hipMalloc(&g->ws, ws_res + 256 + ws_fwd + ws_adj) != hipSuccess) {
         delete g;
         (void)hipGetLastError();
         return fail(SBP_E_NOMEM, "could not allocate the graph workspace");
@@ -467,7 +488,8 @@ int sbp_step_graph_create(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state,
     for (int it = 0; it < iters && body == SBP_OK; ++it) {
         body = step_body(&ctx->c, arr, state, model, y_ref, y_work, p, step_dev,
                          loss + (int64_t)it * state->F, (double *)g->ws,
-                         (unsigned *)((char *)g->ws + ws_res), st);
+                         (unsigned *)((char *)g->ws + ws_res), (char *)g->ws + ws_res + 256, ws_fwd,
+                         (char *)g->ws + ws_res + 256 + ws_fwd, ws_adj, st);
         if (body == SBP_OK) body = launch_incr(step_dev, st);
     }
     e = hipStreamEndCapture(st, &g->graph);

@@ -14,10 +14,12 @@
 // integer multiple of a power-of-two quantum q = 2^-k chosen per launch from
 // a bound on |bin value| over all balls (|p0| a / (2 K c dt) for GAUSS,
 // |p0| a / (4 c dt) for UNIFORM, using rho > support half-width), so that a
-// single value never exceeds 2^30 q; the int64 sums are exact and are turned
-// back into FP32 once per sample when the rows are flushed.  The per-value
+// single value never exceeds 2^30 q.  Flushed rows are added, still as
+// integers, to a global int64 accumulator per sample, which one pass turns
+// into FP32 at the end: every sum is exact, so the signals do not depend on
+// how the work was split or scheduled (bitwise reproducible).  The per-value
 // rounding error is at most q / 2 <= 2^-31 of that bound.  The FP64 path keeps
-// FP64 rows (LDS FP64 adds are not serialised).
+// FP64 rows (LDS FP64 adds are not serialised) and flushes with FP64 atomics.
 //
 // Work items are (frame, transducer group, time tile, chunk of block*bpt
 // balls) in that order.  A persistent workgroup takes one contiguous range of
@@ -112,9 +114,12 @@ __device__ inline void fwd_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx,
     }
 }
 
+// Adds the rows to the global sums (gacc, integer, FP32 path) or to y (FP64
+// path) and clears them.
 template <typename R>
 __device__ inline void flush_rows(typename FwdAcc<R>::T *__restrict__ rows, int dg, int TT, int T,
-                                  int g, int tile, int D, int f, R inv_scale, R *__restrict__ y) {
+                                  int g, int tile, int D, int f, R *__restrict__ y,
+                                  unsigned long long *__restrict__ gacc) {
     using A = typename FwdAcc<R>::T;
     __syncthreads();
     const int tlo = tile * TT;
@@ -122,12 +127,15 @@ __device__ inline void flush_rows(typename FwdAcc<R>::T *__restrict__ rows, int 
     for (int dl = 0; dl < dg; ++dl) {
         const int d = g * dg + dl;
         if (d >= D) break;
-        R *out = y + ((int64_t)f * D + d) * (int64_t)T + tlo;
+        const int64_t o = ((int64_t)f * D + d) * (int64_t)T + tlo;
         A *row = rows + (int64_t)dl * TT;
         for (int n = threadIdx.x; n < len; n += blockDim.x) {
             const A v = row[n];
             if (v != A(0)) {
-                atomicAdd(out + n, FwdAcc<R>::value(v, inv_scale));
+                if constexpr (sizeof(A) == sizeof(unsigned long long) && sizeof(R) == sizeof(float))
+                    atomicAdd(gacc + o + n, (unsigned long long)v);
+                else
+                    atomicAdd(y + o + n, (R)v);
                 row[n] = A(0);
             }
         }
@@ -148,12 +156,25 @@ __device__ inline float fixed_scale(const unsigned *slot, int profile, const Lev
     return ldexpf(1.0f, k);
 }
 
+// y = (accumulate ? y : 0) + q * sum, for every sample of the launch.
+__global__ void k_fwd_convert(const unsigned long long *__restrict__ gacc, int64_t n,
+                              const unsigned *__restrict__ bound, int profile, Level lc,
+                              int accumulate, float *__restrict__ y) {
+    const float inv_scale = 1.0f / fixed_scale(bound, profile, lc);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = FwdAcc<float>::value(gacc[i], inv_scale);
+        y[i] = accumulate ? y[i] + v : v;
+    }
+}
+
 template <typename R, int PROF, int DIR>
 __global__ __launch_bounds__(512, 4) void k_forward(ArrayP<R> arr, BallsP<R> balls,
                                                     const int64_t *__restrict__ ball_off, int F,
                                                     int G, int dg, int TT, int nt, int bpt,
                                                     Level lc, const unsigned *__restrict__ bound,
-                                                    R *__restrict__ y) {
+                                                    R *__restrict__ y,
+                                                    unsigned long long *__restrict__ gacc) {
     using A = typename FwdAcc<R>::T;
     extern __shared__ __align__(16) unsigned char lds_raw[];
     A *rows = reinterpret_cast<A *>(lds_raw);
@@ -165,7 +186,6 @@ __global__ __launch_bounds__(512, 4) void k_forward(ArrayP<R> arr, BallsP<R> bal
     const int64_t CH = (int64_t)nth * bpt;
     const int64_t GT = (int64_t)G * nt;
     const R scale = bound ? (R)fixed_scale(bound, PROF, lc) : R(1);
-    const R inv_scale = R(1) / scale;
     for (int i = tid; i <= F; i += nth) s_off[i] = ball_off[i];
     for (int i = tid; i < dg * TT; i += nth) rows[i] = A(0);
     __syncthreads();
@@ -190,7 +210,7 @@ __global__ __launch_bounds__(512, 4) void k_forward(ArrayP<R> arr, BallsP<R> bal
         const int64_t ck = local - (int64_t)gt * nch;
         if (f != cur_f || gt != cur_gt) {
             if (cur_f >= 0)
-                flush_rows<R>(rows, dg, TT, T, cur_gt / nt, cur_gt % nt, D, cur_f, inv_scale, y);
+                flush_rows<R>(rows, dg, TT, T, cur_gt / nt, cur_gt % nt, D, cur_f, y, gacc);
             cur_f = f;
             cur_gt = gt;
         }
@@ -213,13 +233,13 @@ __global__ __launch_bounds__(512, 4) void k_forward(ArrayP<R> arr, BallsP<R> bal
             }
         }
     }
-    if (cur_f >= 0) flush_rows<R>(rows, dg, TT, T, cur_gt / nt, cur_gt % nt, D, cur_f, inv_scale, y);
+    if (cur_f >= 0) flush_rows<R>(rows, dg, TT, T, cur_gt / nt, cur_gt % nt, D, cur_f, y, gacc);
 }
 
 template <typename R, int PROF, int DIR>
 static int run_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
                        const int64_t *ball_off, int F, int64_t B_cap, const Level &lc,
-                       const unsigned *bound, R *y, hipStream_t st) {
+                       const unsigned *bound, R *y, unsigned long long *gacc, hipStream_t st) {
     using A = typename FwdAcc<R>::T;
     auto kern = k_forward<R, PROF, DIR>;
     const size_t reserve = 2 * (SBP_MAX_FRAMES + 1) * sizeof(int64_t) + 256;
@@ -232,8 +252,19 @@ static int run_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
     if (TT < lc.T && TT < 64) return fail(SBP_E_DOMAIN, "LDS too small for %d rows", dg);
     const int nt = (int)((lc.T + TT - 1) / TT);
     const int G = (arr.D + dg - 1) / dg;
-    const int block = c->tuning.fwd_block;
-    const int bpt = c->tuning.fwd_bpt;
+    // small clouds: fewer balls per item (bpt, then the block) until the chip
+    // has about two work items per resident workgroup
+    int block = c->tuning.fwd_block;
+    int bpt = c->tuning.fwd_bpt;
+    {
+        const int64_t want = 2 * (int64_t)c->num_cus * (1024 / block > 0 ? 1024 / block : 1);
+        auto items = [&](int blk, int b) {
+            const int64_t ch = (int64_t)blk * b;
+            return ((B_cap + ch - 1) / ch + F) * (int64_t)G * nt;
+        };
+        while (bpt > 1 && items(block, bpt) < want) --bpt;
+        while (block > 128 && items(block, bpt) < want) block /= 2;
+    }
     const size_t lds = (size_t)dg * (size_t)TT * sizeof(A);
     SBP_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds));
@@ -249,24 +280,38 @@ static int run_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
     if (grid > max_items) grid = (int)max_items;
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, arr, balls, ball_off, F, G, dg,
-                       (int)TT, nt, bpt, lc, bound, y);
+                       (int)TT, nt, bpt, lc, bound, y, gacc);
     SBP_HIP(hipGetLastError());
     return SBP_OK;
+}
+
+size_t forward_ws_bytes(int F, int D, int T, size_t elem) {
+    if (elem != sizeof(float)) return 0;
+    return ((size_t)F * (size_t)D * (size_t)T * sizeof(unsigned long long) + 255) & ~(size_t)255;
 }
 
 template <typename R>
 int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
                    int F, int64_t B_cap, const sbp_model *m, R *y, int accumulate,
-                   unsigned *bound_slot, hipStream_t st) {
+                   unsigned *bound_slot, void *ws, size_t ws_bytes, hipStream_t st) {
     const Level lc = make_level(m);
-    if (!accumulate) {
-        int rc = launch_fill<R>(y, (int64_t)F * arr.D * m->T, R(0), st);
-        if (rc) return rc;
+    const int64_t ns = (int64_t)F * arr.D * m->T;
+    if (B_cap == 0 || sizeof(R) != sizeof(float)) {
+        if (!accumulate) {
+            int rc = launch_fill<R>(y, ns, R(0), st);
+            if (rc) return rc;
+        }
+        if (B_cap == 0) return SBP_OK;
     }
-    if (B_cap == 0) return SBP_OK;
+    unsigned long long *gacc = nullptr;
     const unsigned *bound = nullptr;
     if (sizeof(R) == sizeof(float)) {
-        int rc = launch_fill<int32_t>((int32_t *)bound_slot, 1, 0, st);
+        if (!ws || ws_bytes < (size_t)ns * sizeof(unsigned long long))
+            return fail(SBP_E_NOMEM, "forward workspace too small");
+        gacc = (unsigned long long *)ws;
+        int rc = launch_fill<uint64_t>((uint64_t *)gacc, ns, 0, st);
+        if (rc) return rc;
+        rc = launch_fill<int32_t>((int32_t *)bound_slot, 1, 0, st);
         if (rc) return rc;
         int64_t nb = (B_cap + 255) / 256;
         if (nb > 1024) nb = 1024;
@@ -277,21 +322,32 @@ int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const i
         SBP_HIP(hipGetLastError());
         bound = bound_slot;
     }
+    int rc;
     if (m->profile == SBP_PROFILE_GAUSS) {
         if (m->directivity == SBP_DIR_COS)
-            return run_forward<R, GAUSS, COS>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, st);
-        return run_forward<R, GAUSS, OMNI>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, st);
+            rc = run_forward<R, GAUSS, COS>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, gacc, st);
+        else
+            rc = run_forward<R, GAUSS, OMNI>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, gacc, st);
+    } else {
+        if (m->directivity == SBP_DIR_COS)
+            rc = run_forward<R, UNIFORM, COS>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, gacc, st);
+        else
+            rc = run_forward<R, UNIFORM, OMNI>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, gacc, st);
     }
-    if (m->directivity == SBP_DIR_COS)
-        return run_forward<R, UNIFORM, COS>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, st);
-    return run_forward<R, UNIFORM, OMNI>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, st);
+    if (rc || !gacc) return rc;
+    int64_t nb = (ns + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_fwd_convert, dim3((int)nb), dim3(256), 0, st, (const unsigned long long *)gacc,
+                       ns, bound, m->profile, lc, accumulate, (float *)y);
+    SBP_HIP(hipGetLastError());
+    return SBP_OK;
 }
 
 template int launch_forward<float>(Ctx *, const ArrayP<float> &, const BallsP<float> &,
                                    const int64_t *, int, int64_t, const sbp_model *, float *, int,
-                                   unsigned *, hipStream_t);
+                                   unsigned *, void *, size_t, hipStream_t);
 template int launch_forward<double>(Ctx *, const ArrayP<double> &, const BallsP<double> &,
                                     const int64_t *, int, int64_t, const sbp_model *, double *,
-                                    int, unsigned *, hipStream_t);
+                                    int, unsigned *, void *, size_t, hipStream_t);
 
 }  // namespace sbp

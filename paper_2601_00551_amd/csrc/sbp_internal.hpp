@@ -181,17 +181,22 @@ struct BallsP {
     R *x, *y, *z, *p0, *a;
 };
 
-// bound_slot: one device word the FP32 path uses for its fixed-point quantum.
+// bound_slot: one device word the FP32 path uses for its fixed-point quantum;
+// ws: its per-sample integer sums (forward_ws_bytes; none for FP64).
+size_t forward_ws_bytes(int F, int D, int T, size_t elem);
 template <typename R>
 int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
                    int F, int64_t B_cap, const sbp_model *m, R *y, int accumulate,
-                   unsigned *bound_slot, hipStream_t st);
+                   unsigned *bound_slot, void *ws, size_t ws_bytes, hipStream_t st);
 
-// vscale multiplies v (the filter passes y_ref with vscale = -2).
+// vscale multiplies v (the filter passes y_ref with vscale = -2).  ws holds the
+// per-slice partial gradients when the launch splits the transducers into
+// slices (adjoint_ws_bytes of them; with less, the launch does not split).
+size_t adjoint_ws_bytes(const Ctx *c, int D, int64_t B_cap, int F, uint32_t mask, size_t elem);
 template <typename R>
 int launch_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
                    int F, int64_t B_cap, const sbp_model *m, const R *v, R vscale,
-                   uint32_t mask, const BallsP<R> &grad, hipStream_t st);
+                   uint32_t mask, const BallsP<R> &grad, void *ws, size_t ws_bytes, hipStream_t st);
 
 template <typename R>
 int launch_fill(R *p, int64_t n, R value, hipStream_t st);

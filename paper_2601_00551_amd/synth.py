@@ -207,13 +207,15 @@ def region_init(rng, region: Region, n, spacing=0.2, a=0.1, p_lo=0.0, p_hi=0.2, 
 
 
 def drop_near(balls, array, min_dist):
-    """Remove balls closer than min_dist to any transducer."""
+    """Remove balls closer than min_dist to any transducer (nearest-neighbour
+    distances from a k-d tree over the transducer positions, FP64)."""
+    from scipy.spatial import cKDTree
     p = np.stack([balls["x"], balls["y"], balls["z"]], axis=1).astype(np.float64)
     q = np.stack([array["qx"], array["qy"], array["qz"]], axis=1).astype(np.float64)
-    keep = np.ones(len(p), dtype=bool)
-    for s in range(0, len(p), 8192):
-        d2 = ((p[s:s + 8192, None, :] - q[None, :, :]) ** 2).sum(-1)
-        keep[s:s + 8192] = d2.min(axis=1) >= min_dist * min_dist
+    if len(p) == 0:
+        return dict(balls)
+    d, _ = cKDTree(q).query(p, k=1)
+    keep = d >= min_dist
     return {k: v[keep] for k, v in balls.items()}
 
 

@@ -91,6 +91,33 @@ def test_launch_shapes_all_agree(ctx, tuning):
         assert rel_l2(g[k], ref[k]) <= GRAD_TOL, k
 
 
+def test_forward_bitwise_reproducible(ctx):
+    """The FP32 forward sums integer multiples of one quantum exactly: the same
+    bits for any launch shape (without time tiling) and on every repetition;
+    the adjoint repeats bit for bit for a given shape."""
+    arr, balls = small_scene(23, nb=5000, nd=23)
+    T = 700
+    rng = np.random.default_rng(5)
+    v = rng.normal(size=(23, T)).astype(np.float32)
+    ys, gs = [], []
+    old = ctx.tuning
+    try:
+        for t in (dict(fwd_dets=4, fwd_block=512, fwd_bpt=4, adj_dets=4, adj_block=512, adj_bpt=4),
+                  dict(fwd_dets=1, fwd_block=256, fwd_bpt=1, adj_dets=2, adj_block=128, adj_bpt=1),
+                  dict(fwd_dets=8, fwd_block=128, fwd_bpt=2, fwd_grid=7)):
+            ctx.tuning = t
+            for _ in range(2):
+                ys.append(run_fwd(ctx, arr, balls, gmodel(T))[0].cpu().numpy())
+                gs.append(run_adj(ctx, arr, balls, gmodel(T), v))
+    finally:
+        ctx.tuning = old
+    for y in ys[1:]:
+        assert np.array_equal(y, ys[0])
+    for i in range(0, len(gs), 2):
+        for k in PARAMS:
+            assert np.array_equal(gs[i][k], gs[i + 1][k]), (i, k)
+
+
 # ------------------------------------------------------------------ adjoint --
 
 @pytest.mark.parametrize("profile,directivity", COMBOS)
