@@ -168,6 +168,8 @@ typedef struct sbp_tuning {
     int32_t adj_block;    /* threads per workgroup: 64, 128, 256 or 512 */
     int32_t adj_bpt;      /* balls per thread, 1..4 */
     int32_t adj_grid;     /* persistent workgroups, 0 = as many as fit on the device */
+    int32_t fwd_tile;     /* samples per LDS time tile, 0 = as many as fit, else >= 64 */
+    int32_t adj_tile;     /* edges per LDS time tile, 0 = as many as fit, else >= 64 */
 } sbp_tuning;
 
 typedef struct sbp_ctx sbp_ctx;

@@ -65,7 +65,8 @@ class SbpGrowthRule(ctypes.Structure):
 
 class SbpTuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("fwd_dets", "fwd_block", "fwd_bpt", "fwd_grid",
-                                               "adj_dets", "adj_block", "adj_bpt", "adj_grid")]
+                                               "adj_dets", "adj_block", "adj_bpt", "adj_grid",
+                                               "fwd_tile", "adj_tile")]
 
 
 I32, I64, U32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32

@@ -14,8 +14,12 @@ import json
 import math
 import os
 
-FWD_SPACE = {"fwd_dets": (1, 2, 4, 8), "fwd_block": (256, 512), "fwd_bpt": (1, 2, 4)}
-ADJ_SPACE = {"adj_dets": (2, 4, 8), "adj_block": (128, 256, 512), "adj_bpt": (1, 2, 4)}
+FWD_SPACE = {"fwd_dets": (1, 2, 4, 8), "fwd_block": (256, 512), "fwd_bpt": (1, 2, 4),
+             "fwd_tile": (0, 2048, 1024)}
+ADJ_SPACE = {"adj_dets": (2, 4, 8), "adj_block": (128, 256, 512), "adj_bpt": (1, 2, 4),
+             "adj_tile": (0, 2048)}
+DEFAULTS = {"fwd_dets": 4, "fwd_block": 512, "fwd_bpt": 4, "fwd_grid": 0, "adj_dets": 4,
+            "adj_block": 512, "adj_bpt": 4, "adj_grid": 0, "fwd_tile": 0, "adj_tile": 0}
 
 
 def _bucket(n: int) -> int:
@@ -59,7 +63,9 @@ def apply_cached(ctx, path: str, model, D: int, B: int) -> dict:
     cache = load(path)
     entry = lookup(cache, shape_key(_arch(), model, D, B)) if cache else None
     if entry:
-        ctx.tuning = {k: int(v) for k, v in entry.items() if k in ctx.tuning}
+        t = dict(DEFAULTS)
+        t.update({k: int(v) for k, v in entry.items() if k in DEFAULTS})
+        ctx.tuning = t
     return ctx.tuning
 
 
@@ -89,7 +95,10 @@ def tune(ctx, arr, balls, model, v, reps: int = 3, path: str | None = None, log=
     best_f, best_a = None, None
     for vals in itertools.product(*FWD_SPACE.values()):
         t = dict(zip(FWD_SPACE, vals))
-        if t["fwd_dets"] * model.T * 8 > 150 * 1024 and t["fwd_dets"] > 1:   # FP64 rows
+        if t["fwd_tile"] and t["fwd_tile"] >= model.T:
+            continue                                   # the same as no tiling
+        rows = min(model.T, t["fwd_tile"] or model.T)
+        if t["fwd_dets"] * rows * 8 > 150 * 1024 and t["fwd_dets"] > 1:   # int64 rows
             continue
         ctx.tuning = t
         ms = _time(lambda: api.simulate_signals(ctx, arr, balls, model, y=y), reps)
@@ -100,7 +109,9 @@ def tune(ctx, arr, balls, model, v, reps: int = 3, path: str | None = None, log=
     ctx.tuning = best_f[0]
     for vals in itertools.product(*ADJ_SPACE.values()):
         t = dict(zip(ADJ_SPACE, vals))
-        if t["adj_dets"] * (model.T + 1) * 4 > 150 * 1024:
+        if t["adj_tile"] and t["adj_tile"] >= model.T + 1:
+            continue
+        if t["adj_dets"] * min(model.T + 1, t["adj_tile"] or model.T + 1) * 4 > 150 * 1024:
             continue
         ctx.tuning = t
         ms = _time(lambda: api.adjoint_gradients(ctx, arr, balls, model, v, grad=grad), reps)

@@ -22,6 +22,11 @@ constexpr int kMaxBpt = 4;
 
 // Edges per exact restart of the Gaussian recurrence below.
 constexpr int kRestart = 16;
+// Edges whose staged values are loaded together in FP32 (eight measured
+// faster than sixteen); the FP64 twin, which already spills at this register
+// budget, keeps one edge per trip.
+template <typename R> struct EdgeGroup { static constexpr int gauss = 8, uniform = 8; };
+template <> struct EdgeGroup<double> { static constexpr int gauss = 1, uniform = 1; };
 
 // Accumulates the pair's support edges in the staged tile [tlo, thi)
 // (wr[m - tlo]).  Everything is linear in (S0, S1, S2), so tiles add up.
@@ -44,15 +49,17 @@ __device__ inline void adj_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx,
     const int me = hi > (double)(thi - 1) ? thi - 1 : (int)hi;
     wr -= tlo;
     const R c = LevelR<R>::cdt(lc);
+    constexpr int kUnroll = PROF == GAUSS ? EdgeGroup<R>::gauss : EdgeGroup<R>::uniform;
     R P = R(0), W = R(0), A1 = R(0), A2 = R(0);
+    // The staged rows are read kUnroll edges at a time, all loads issued before
+    // the arithmetic, so that one LDS latency is paid per group, not per edge.
     if (PROF == GAUSS) {
         for (int m0 = mb; m0 <= me; m0 += kRestart) {
             R u = (R)(g.s - (double)m0 * lc.cdt);
             R e = ex2(u * u * b.q0);
             R gq = ex2(b.q0 * c * (c - R(2) * u));
             const int m1 = min(m0 + kRestart - 1, me);
-            for (int m = m0; m <= m1; ++m) {
-                const R w = wr[m];
+            auto edge = [&](R w) {
                 W += w;
                 if (FULL) {
                     const R we = w * e;
@@ -66,18 +73,35 @@ __device__ inline void adj_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx,
                 }
                 e *= gq;
                 gq *= b.h;
+            };
+            int m = m0;
+            for (; m + kUnroll - 1 <= m1; m += kUnroll) {
+                R w[kUnroll];
+#pragma unroll
+                for (int k = 0; k < kUnroll; ++k) w[k] = wr[m + k];
+#pragma unroll
+                for (int k = 0; k < kUnroll; ++k) edge(w[k]);
             }
+            for (; m <= m1; ++m) edge(wr[m]);
         }
     } else {
         R u = (R)(g.s - (double)mb * lc.cdt);
-        for (int m = mb; m <= me; ++m) {
-            const R w = wr[m];
+        auto edge = [&](R w) {
             W += w;
             const R wu = w * u;
             A1 += wu;
             P = fma(wu, u, P);     // sum w u^2
             u -= c;
+        };
+        int m = mb;
+        for (; m + kUnroll - 1 <= me; m += kUnroll) {
+            R w[kUnroll];
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) w[k] = wr[m + k];
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) edge(w[k]);
         }
+        for (; m <= me; ++m) edge(wr[m]);
     }
     R S0, S1, S2;
     if (PROF == GAUSS) {
@@ -299,6 +323,7 @@ static int run_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
     int64_t TT = (int64_t)(avail / ((size_t)ds * sizeof(R)));
     if (TT > (int64_t)lc.T + 1) TT = (int64_t)lc.T + 1;
     if (TT < (int64_t)lc.T + 1 && TT < 64) return fail(SBP_E_DOMAIN, "LDS too small for %d rows", ds);
+    if (c->tuning.adj_tile > 0 && TT > c->tuning.adj_tile) TT = c->tuning.adj_tile;
     const int nf = FULL ? 5 : 1;
     AdjPlan pl = adjoint_plan(c, arr.D, B_cap, F, (size_t)nf * (size_t)B_cap * sizeof(R));
     if (pl.nsl > 1 && ws_bytes < (size_t)pl.nsl * nf * (size_t)B_cap * sizeof(R)) {

@@ -185,6 +185,8 @@ static int check_tuning(const sbp_tuning *t) {
     if (t->fwd_bpt < 1 || t->fwd_bpt > 16) return fail(SBP_E_DOMAIN, "fwd_bpt must be in [1, 16]");
     if (t->adj_bpt < 1 || t->adj_bpt > 4) return fail(SBP_E_DOMAIN, "adj_bpt must be in [1, 4]");
     if (t->fwd_grid < 0 || t->adj_grid < 0) return fail(SBP_E_DOMAIN, "grid must be >= 0");
+    if ((t->fwd_tile != 0 && t->fwd_tile < 64) || (t->adj_tile != 0 && t->adj_tile < 64))
+        return fail(SBP_E_DOMAIN, "tile must be 0 or >= 64");
     return SBP_OK;
 }
 
@@ -234,7 +236,7 @@ int sbp_ctx_create(sbp_ctx **out, int device) {
     size_t lds = prop.sharedMemPerBlock;
     if (prop.maxSharedMemoryPerMultiProcessor > lds) lds = prop.maxSharedMemoryPerMultiProcessor;
     ctx->c.lds_max = lds;
-    ctx->c.tuning = sbp_tuning{4, 512, 4, 0, 4, 512, 4, 0};
+    ctx->c.tuning = sbp_tuning{4, 512, 4, 0, 4, 512, 4, 0, 0, 0};
     if (hipMalloc((void **)&ctx->c.misc, 256) != hipSuccess) {
         (void)hipGetLastError();
         delete ctx;

@@ -71,6 +71,8 @@ def test_forward_clipping_at_record_start_and_levels(ctx):
     dict(adj_dets=1, adj_block=64, adj_bpt=1, adj_grid=0),
     dict(adj_dets=5, adj_block=512, adj_bpt=4, adj_grid=3),
     dict(adj_dets=16, adj_block=128, adj_bpt=2, adj_grid=1),
+    dict(fwd_dets=2, fwd_tile=128, adj_dets=3, adj_tile=100),
+    dict(fwd_dets=4, fwd_tile=64, fwd_grid=5, adj_dets=4, adj_tile=64, adj_block=64, adj_bpt=1),
 ])
 def test_launch_shapes_all_agree(ctx, tuning):
     arr, balls = small_scene(21, nb=2100, nd=19)
