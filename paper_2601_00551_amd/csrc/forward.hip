@@ -10,7 +10,7 @@
 //
 // LDS accumulation.  gfx950 serialises LDS FP32 atomic adds (about 0.3 lanes
 // per clock per CU, against ~7 for 64-bit integer adds), so the FP32 path
-// accumulates in exact 64-bit fixed point: each bin value is rounded to an
+// accumulates in exact 64-bit fixed point: each bin value is truncated to an
 // integer multiple of a power-of-two quantum q = 2^-k chosen per launch from
 // a bound on |bin value| over all balls (|p0| a / (2 K c dt) for GAUSS,
 // |p0| a / (4 c dt) for UNIFORM, using rho > support half-width), so that a
@@ -18,7 +18,7 @@
 // integers, to a global int64 accumulator per sample, which one pass turns
 // into FP32 at the end: every sum is exact, so the signals do not depend on
 // how the work was split or scheduled (bitwise reproducible).  The per-value
-// rounding error is at most q / 2 <= 2^-31 of that bound.  The FP64 path keeps
+// error is below q <= 2^-30 of that bound.  The FP64 path keeps
 // FP64 rows (LDS FP64 adds are not serialised) and flushes with FP64 atomics.
 //
 // Work items are (frame, transducer group, time tile, chunk of block*bpt
@@ -38,7 +38,7 @@ template <typename R> struct FwdAcc;
 template <> struct FwdAcc<float> {
     using T = unsigned long long;
     __device__ static void add(T *p, float v_scaled) {
-        const int iv = (int)rintf(v_scaled);
+        const int iv = (int)v_scaled;   // toward zero: |error| < one quantum
         atomicAdd(p, (unsigned long long)(long long)iv);
     }
     __device__ static float value(T s, float inv_scale) {
@@ -88,51 +88,61 @@ __device__ inline void fwd_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx,
     const int ne = hi > (double)(thi - 1) ? thi - 1 : (int)hi;
     const R amp = b.ampk * g.dir * LevelR<R>::inv2cdt(lc) * g.inv_rho * scale;
     const R c = LevelR<R>::cdt(lc);
-    typename FwdAcc<R>::T *out = row - tlo;
-    // two bins per trip (no register copy of the carried edge value)
-    typename FwdAcc<R>::T *p = out + nb;
-    int cnt = ne - nb + 1;
+    // Bins nb..ne use edges nb..ne+1.  Edge lo and edge hi + 1 lie outside the
+    // support (shape value: eK for GAUSS, 0 for UNIFORM) and every edge between
+    // them inside, so only the inside edges are evaluated and none is clamped.
+    const bool first_out = nb == (int)lo;
+    const bool last_out = ne == (int)hi;
+    typename FwdAcc<R>::T *p = row - tlo + nb;
+    int cnt = ne - nb + 1 - (last_out ? 1 : 0);   // bins whose right edge is inside
     if (PROF == GAUSS) {
         // one exponential per edge: a recurrence drifts by ~1e-7 per step, and
         // bin differences amplify that by a / (c dt), up to ~10^2 here
         const R eK = LevelR<R>::eK(lc);
         const R u0 = (R)(g.s - (double)nb * lc.cdt);
-        R prev = fmax(ex2(u0 * u0 * b.q0), eK);
+        R prev = first_out ? eK : ex2(u0 * u0 * b.q0);
         R j = R(1);
+        // two bins per trip (no register copy of the carried edge value)
         for (; cnt >= 2; cnt -= 2, p += 2, j += R(2)) {
             const R u1 = fma(-j, c, u0);
-            const R u2 = fma(-(j + R(1)), c, u0);
-            const R c1 = fmax(ex2(u1 * u1 * b.q0), eK);
-            const R c2 = fmax(ex2(u2 * u2 * b.q0), eK);
+            const R u2 = u1 - c;
+            const R c1 = ex2(u1 * u1 * b.q0);
+            const R c2 = ex2(u2 * u2 * b.q0);
             FwdAcc<R>::add(p, amp * (prev - c1));
             FwdAcc<R>::add(p + 1, amp * (c1 - c2));
             prev = c2;
         }
         if (cnt) {
             const R u1 = fma(-j, c, u0);
-            FwdAcc<R>::add(p, amp * (prev - fmax(ex2(u1 * u1 * b.q0), eK)));
+            const R c1 = ex2(u1 * u1 * b.q0);
+            FwdAcc<R>::add(p, amp * (prev - c1));
+            prev = c1;
+            ++p;
         }
+        if (last_out) FwdAcc<R>::add(p, amp * (prev - eK));
     } else {
         R u = (R)(g.s - (double)nb * lc.cdt);
-        R prev = fmax(b.q0 - u * u, R(0));
+        R prev = first_out ? R(0) : b.q0 - u * u;
         for (; cnt >= 2; cnt -= 2, p += 2) {
             const R u1 = u - c;
             u = u1 - c;
-            const R c1 = fmax(b.q0 - u1 * u1, R(0));
-            const R c2 = fmax(b.q0 - u * u, R(0));
+            const R c1 = b.q0 - u1 * u1;
+            const R c2 = b.q0 - u * u;
             FwdAcc<R>::add(p, amp * (prev - c1));
             FwdAcc<R>::add(p + 1, amp * (c1 - c2));
             prev = c2;
         }
         if (cnt) {
             u -= c;
-            FwdAcc<R>::add(p, amp * (prev - fmax(b.q0 - u * u, R(0))));
+            const R c1 = b.q0 - u * u;
+            FwdAcc<R>::add(p, amp * (prev - c1));
+            prev = c1;
+            ++p;
         }
+        if (last_out) FwdAcc<R>::add(p, amp * prev);
     }
 }
 
-// Adds the rows to the global sums (gacc, integer, FP32 path) or to y (FP64
-// path) and clears them.
 template <typename R>
 __device__ inline void flush_rows(typename FwdAcc<R>::T *__restrict__ rows, int dg, int TT, int T,
                                   int g, int tile, int D, int f, R *__restrict__ y,
