@@ -199,3 +199,17 @@ def test_context_create_rejects_bad_device():
     p = ctypes.c_void_p()
     assert lib.sbp_ctx_create(ctypes.byref(p), -1) == _abi.SBP_E_ARG
     assert lib.sbp_ctx_create(None, 0) == _abi.SBP_E_ARG
+
+
+def test_image_entry_points_validate_on_the_host():
+    lib = _abi.lib()
+    d = ctypes.c_void_p(256)
+    assert lib.sbp_image_metrics(None, d, d, 10, 20, 20, 1.0, d, d, None) == _abi.SBP_E_DOMAIN
+    assert lib.sbp_image_metrics(None, d, d, 20, 20, 20, 0.0, d, d, None) == _abi.SBP_E_DOMAIN
+    assert lib.sbp_image_metrics(None, d, d, 20, 20, 20, 1.0, d, d, None) == _abi.SBP_E_ARG
+    assert lib.sbp_image_metrics(None, None, d, 20, 20, 20, 1.0, d, d, None) == _abi.SBP_E_ARG
+    grid = _abi.SbpGrid(0.0, 0.0, 0.0, 0.0, 4, 4, 4, 0)
+    model = _abi.SbpModel(1.5, 0.025, 0.0, 5.0, 100, 1, 1, 1, 0, 0)
+    balls = _abi.SbpBalls(d, d, d, d, d)
+    assert lib.sbp_voxelize(None, ctypes.byref(balls), d, 10, ctypes.byref(model), ctypes.byref(grid), d,
+                            None) == _abi.SBP_E_DOMAIN
