@@ -115,6 +115,7 @@ class Recon:
         # optional growth-point hook proposer(recon, stage_index, model, y_k, y_work),
         # called after each split / destroy / duplicate (the learned proposal)
         self.proposer = None
+        self.softplus_on = False    # the size arrays hold a~ (a = softplus(a~)) right now
 
     # ------------------------------------------------------------ helpers --
     def model(self, f, a_softplus=0):
@@ -197,6 +198,7 @@ class Recon:
         if resume:
             meta = self.load_checkpoint()
             start_stage, start_it, step, softplus_on = meta["stage"], meta["it"], meta["step"], meta["softplus_on"]
+            self.softplus_on = softplus_on
         self.t_start = time.perf_counter()
         y_work = torch.empty(self.F, self.D, cfg.T, device=self.dev)
         loss = torch.zeros(self.F, dtype=torch.float64, device=self.dev)
@@ -226,7 +228,7 @@ class Recon:
             while it < stg.iters:
                 if sp_start is not None and it >= sp_start and not softplus_on:
                     api.softplus_reparam(self.ctx, self.state, True)
-                    softplus_on = True
+                    softplus_on = self.softplus_on = True
                     model = self.model(stg.f, a_softplus=1)
                     graph = None
                 # iterations until the next growth, refinement switch or stage end
@@ -282,7 +284,7 @@ class Recon:
             graph = None
             if softplus_on:
                 api.softplus_reparam(self.ctx, self.state, False)
-                softplus_on = False
+                softplus_on = self.softplus_on = False
             resume = False
             self.save_checkpoint(si + 1, 0, 1, False)
         torch.cuda.synchronize(self.dev)
