@@ -49,6 +49,22 @@ int sbp_voxelize(sbp_ctx *ctx, const sbp_balls *balls, const int64_t *ball_off, 
 int sbp_image_metrics(sbp_ctx *ctx, const float *img, const float *ref, int32_t nx, int32_t ny,
                       int32_t nz, float scale, float *work, double *out, void *stream);
 
+/* ------------------------------------------ initialisation inside the array */
+
+/* Envelope test for the random initial cloud of Algorithm 1 (a closed
+ * polygonal envelope mesh built from the array, points drawn inside it by ray
+ * casting).  tri (device, F triangles x 9 floats: v0, v1, v2) is a closed,
+ * consistently triangulated mesh.  For each point i < N (px, py, pz):
+ *   inside[i] = 1 if the ray from the point along the fixed direction
+ *     (1, 0.7071, 0.3183) crosses the mesh an odd number of times (Moller-
+ *     Trumbore, FP32, hits at t > 0) and the point is at least `margin` from
+ *     every triangle; else 0.
+ *   dist[i] (if dist is not NULL) = the distance to the nearest triangle.
+ * Errors: SBP_E_ARG, SBP_E_DOMAIN (F < 4, margin < 0). */
+int sbp_mesh_inside(sbp_ctx *ctx, const float *tri, int32_t F, const float *px, const float *py,
+                    const float *pz, int64_t N, float margin, uint8_t *inside, float *dist,
+                    void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -122,6 +122,7 @@ SIGNATURES = {
     # sbp_image.h
     "sbp_voxelize": (ctypes.c_int, [P, PB, P, I64, PM, PGr, P, P]),
     "sbp_image_metrics": (ctypes.c_int, [P, P, P, I32, I32, I32, F32, P, P, P]),
+    "sbp_mesh_inside": (ctypes.c_int, [P, P, I32, P, P, P, I64, F32, P, P, P]),
 }
 
 _LIB = None

@@ -248,3 +248,113 @@ int sbp_image_metrics(sbp_ctx *ctx, const float *img, const float *ref, int32_t 
 }
 
 }  // extern "C"
+
+namespace sbp {
+
+constexpr int kTriTile = 256;
+
+// Distance from p to triangle (a, b, c): the closest point by the region
+// tests of the triangle's Voronoi regions (vertex, edge, face).
+__device__ inline float tri_dist2(float3 p, float3 a, float3 b, float3 c) {
+    auto sub = [](float3 u, float3 v) { return make_float3(u.x - v.x, u.y - v.y, u.z - v.z); };
+    auto dot = [](float3 u, float3 v) { return u.x * v.x + u.y * v.y + u.z * v.z; };
+    auto d2 = [&](float3 u) { return dot(u, u); };
+    const float3 ab = sub(b, a), ac = sub(c, a), ap = sub(p, a);
+    const float d1 = dot(ab, ap), d2_ = dot(ac, ap);
+    if (d1 <= 0.f && d2_ <= 0.f) return d2(ap);
+    const float3 bp = sub(p, b);
+    const float d3 = dot(ab, bp), d4 = dot(ac, bp);
+    if (d3 >= 0.f && d4 <= d3) return d2(bp);
+    const float vc = d1 * d4 - d3 * d2_;
+    if (vc <= 0.f && d1 >= 0.f && d3 <= 0.f) {
+        const float v = d1 / (d1 - d3);
+        return d2(make_float3(ap.x - v * ab.x, ap.y - v * ab.y, ap.z - v * ab.z));
+    }
+    const float3 cp = sub(p, c);
+    const float d5 = dot(ab, cp), d6 = dot(ac, cp);
+    if (d6 >= 0.f && d5 <= d6) return d2(cp);
+    const float vb = d5 * d2_ - d1 * d6;
+    if (vb <= 0.f && d2_ >= 0.f && d6 <= 0.f) {
+        const float w = d2_ / (d2_ - d6);
+        return d2(make_float3(ap.x - w * ac.x, ap.y - w * ac.y, ap.z - w * ac.z));
+    }
+    const float va = d3 * d6 - d5 * d4;
+    if (va <= 0.f && (d4 - d3) >= 0.f && (d5 - d6) >= 0.f) {
+        const float w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+        const float3 bc = sub(c, b);
+        return d2(make_float3(bp.x - w * bc.x, bp.y - w * bc.y, bp.z - w * bc.z));
+    }
+    const float den = 1.f / (va + vb + vc);
+    const float v = vb * den, w = vc * den;
+    return d2(make_float3(ap.x - ab.x * v - ac.x * w, ap.y - ab.y * v - ac.y * w, ap.z - ab.z * v - ac.z * w));
+}
+
+// One thread per point; the block stages the triangles through LDS.
+__global__ void k_mesh_inside(const float *__restrict__ tri, int F, const float *__restrict__ px,
+                              const float *__restrict__ py, const float *__restrict__ pz, int64_t N,
+                              float margin, int want_dist, uint8_t *__restrict__ inside,
+                              float *__restrict__ dist) {
+    __shared__ float s_tri[kTriTile * 9];
+    const float dx = 1.0f, dy = 0.7071f, dz = 0.3183f;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < N; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const bool act = i < N;
+        const float3 p = act ? make_float3(px[i], py[i], pz[i]) : make_float3(0.f, 0.f, 0.f);
+        int hits = 0;
+        float best = 3.0e38f;
+        for (int t0 = 0; t0 < F; t0 += kTriTile) {
+            const int nt = min(kTriTile, F - t0);
+            __syncthreads();
+            for (int q = threadIdx.x; q < nt * 9; q += blockDim.x) s_tri[q] = tri[(int64_t)t0 * 9 + q];
+            __syncthreads();
+            if (!act) continue;
+            for (int t = 0; t < nt; ++t) {
+                const float *v = s_tri + t * 9;
+                const float3 a = make_float3(v[0], v[1], v[2]), b = make_float3(v[3], v[4], v[5]),
+                             c = make_float3(v[6], v[7], v[8]);
+                // Moller-Trumbore
+                const float e1x = b.x - a.x, e1y = b.y - a.y, e1z = b.z - a.z;
+                const float e2x = c.x - a.x, e2y = c.y - a.y, e2z = c.z - a.z;
+                const float hx = dy * e2z - dz * e2y, hy = dz * e2x - dx * e2z, hz = dx * e2y - dy * e2x;
+                const float det = e1x * hx + e1y * hy + e1z * hz;
+                if (det != 0.0f) {
+                    const float f = 1.0f / det;
+                    const float sx = p.x - a.x, sy = p.y - a.y, sz = p.z - a.z;
+                    const float u = f * (sx * hx + sy * hy + sz * hz);
+                    if (u >= 0.0f && u <= 1.0f) {
+                        const float qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
+                        const float w = f * (dx * qx + dy * qy + dz * qz);
+                        if (w >= 0.0f && u + w <= 1.0f) {
+                            const float tt = f * (e2x * qx + e2y * qy + e2z * qz);
+                            if (tt > 0.0f) ++hits;
+                        }
+                    }
+                }
+                if (margin > 0.0f || want_dist) best = fminf(best, tri_dist2(p, a, b, c));
+            }
+        }
+        if (act) {
+            const float d = sqrtf(best);
+            inside[i] = (uint8_t)((hits & 1) && (!(margin > 0.0f) || d >= margin));
+            if (dist) dist[i] = d;
+        }
+    }
+}
+
+}  // namespace sbp
+
+extern "C" int sbp_mesh_inside(sbp_ctx *ctx, const float *tri, int32_t F, const float *px, const float *py,
+                               const float *pz, int64_t N, float margin, uint8_t *inside, float *dist,
+                               void *stream) {
+    using namespace sbp;
+    if (!tri || (N > 0 && (!px || !py || !pz || !inside))) return fail(SBP_E_ARG, "a required pointer is NULL");
+    if (N < 0) return fail(SBP_E_ARG, "N must be >= 0");
+    if (F < 4) return fail(SBP_E_DOMAIN, "a closed mesh has at least 4 triangles");
+    if (!(margin >= 0.0f)) return fail(SBP_E_DOMAIN, "margin must be >= 0");
+    if (!ctx) return fail(SBP_E_ARG, "ctx is NULL");
+    if (N == 0) return SBP_OK;
+    hipLaunchKernelGGL(k_mesh_inside, dim3(nblocks(N, 4096)), dim3(kIb), 0, (hipStream_t)stream, tri, F, px, py,
+                       pz, N, margin, dist ? 1 : 0, inside, dist);
+    SBP_HIP(hipGetLastError());
+    return SBP_OK;
+}
