@@ -471,8 +471,8 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--n-init", type=int, default=200_000)
     ap.add_argument("--labels", choices=("phantom", "final"), default="phantom")
-    ap.add_argument("--when", default="", help="comma-separated stage indices the network acts in "
-                                               "(default: all)")
+    ap.add_argument("--when", default="0", help="comma-separated stage indices the network acts in "
+                                                "(default: the coarse stage, where its proposals are kept)")
     ap.add_argument("--max-per-stage", type=int, default=None)
     ap.add_argument("--graph-iters", type=int, default=10,
                     help="iterations per captured HIP graph in the batched runs")

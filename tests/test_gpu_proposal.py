@@ -45,7 +45,7 @@ def test_learned_proposal_gains_over_plain(ctx):
         target = plain["final_loss"] * (1.0 + 1e-3)
         t_plain = proposal.first_below(plain["log"], target)
         lp = proposal.LearnedProposer(net, proposal.FeatureBuilder(ctx, grid, a_probe=0.1, half=10.0),
-                                      a_init=wl.a_init)
+                                      a_init=wl.a_init, stages=[0])
         _, learned = proposal.plain_run(ctx, wl, y, stages, capacity=cap, stop_below=target, proposer=lp,
                                         graph_iters=10)
         for ev in lp.events:
