@@ -78,46 +78,59 @@ static int launch_sync(const float *P, uint16_t *W, hipStream_t st) {
 
 // ---------------------------------------------------------------- forward --
 
-// One hidden layer for the wave's 16 rows: out = bf16(relu(A W + b)) into
-// LDS (and transposed into acts if given).
+// One hidden layer of the workgroup's 64 rows: out = bf16(relu(A W + b)) into
+// LDS (and transposed into acts if given).  Wave w owns output columns
+// [64 w, 64 w + 64) for all 64 rows (4 x 4 accumulator tiles), so per k-step
+// it reads 4 A fragments from LDS and 4 B fragments (W^T rows) from global
+// memory for 16 matrix-core products, and the weights' columns are read by one
+// wave only.
 template <int K>
 __device__ inline void hidden_layer(const __bf16 *__restrict__ A, int lda, const __bf16 *__restrict__ Wt,
                                     const float *__restrict__ bias, __bf16 *__restrict__ O,
                                     __bf16 *__restrict__ acts_t, int64_t Mp, int64_t m_base,
-                                    int64_t M, int wrow) {
+                                    int64_t M) {
     const int l = threadIdx.x & 63;
-    floatx4 acc[kH / 16];
+    const int c0 = (threadIdx.x >> 6) * 64;
+    floatx4 acc[4][4];
 #pragma unroll
-    for (int t = 0; t < kH / 16; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
     for (int ks = 0; ks < K / 32; ++ks) {
-        const bf16x8 a = frag(A + (wrow + (l & 15)) * lda + ks * 32 + (l >> 4) * 8);
+        bf16x8 a[4], bq[4];
 #pragma unroll
-        for (int t = 0; t < kH / 16; ++t) {
-            const bf16x8 b = frag(Wt + (t * 16 + (l & 15)) * K + ks * 32 + (l >> 4) * 8);
-            acc[t] = mfma(a, b, acc[t]);
-        }
+        for (int ct = 0; ct < 4; ++ct) bq[ct] = frag(Wt + (c0 + ct * 16 + (l & 15)) * K + ks * 32 + (l >> 4) * 8);
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) a[rt] = frag(A + (rt * 16 + (l & 15)) * lda + ks * 32 + (l >> 4) * 8);
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = mfma(a[rt], bq[ct], acc[rt][ct]);
     }
 #pragma unroll
-    for (int t = 0; t < kH / 16; ++t) {
-        const int col = t * 16 + (l & 15);
+    for (int ct = 0; ct < 4; ++ct) {
+        const int col = c0 + ct * 16 + (l & 15);
         const float bb = bias[col];
-        bf16x4 h4;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = wrow + (l >> 4) * 4 + i;
-            const bool valid = m_base + r < M;
-            const float v = valid ? fmaxf(acc[t][i] + bb, 0.0f) : 0.0f;
-            const __bf16 h = (__bf16)v;
-            O[r * kLd + col] = h;
-            h4[i] = h;
+        for (int rt = 0; rt < 4; ++rt) {
+            bf16x4 h4;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = rt * 16 + (l >> 4) * 4 + i;
+                const bool valid = m_base + r < M;
+                const float v = valid ? fmaxf(acc[rt][ct][i] + bb, 0.0f) : 0.0f;
+                const __bf16 h = (__bf16)v;
+                O[r * kLd + col] = h;
+                h4[i] = h;
+            }
+            if (acts_t)
+                *reinterpret_cast<bf16x4 *>(acts_t + (int64_t)col * Mp + m_base + rt * 16 + (l >> 4) * 4) = h4;
         }
-        if (acts_t)
-            *reinterpret_cast<bf16x4 *>(acts_t + (int64_t)col * Mp + m_base + wrow + (l >> 4) * 4) = h4;
     }
 }
 
-__global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ P, const __bf16 *__restrict__ W,
+__global__ __launch_bounds__(256, 2) void k_mlp_fwd(const float *__restrict__ P, const __bf16 *__restrict__ W,
                                                  const float *__restrict__ X, int64_t M, int64_t Mp,
                                                  float *__restrict__ out, __bf16 *__restrict__ acts) {
     __shared__ __align__(16) __bf16 s_x[kTM * kLdIn];
@@ -131,19 +144,22 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float *__restrict__ P, co
         const int r = i / kIn, k = i % kIn;
         const int64_t m = m_base + r;
         const float v = (m < M && k < SBP_MLP_IN) ? X[m * SBP_MLP_IN + k] : 0.0f;
-        const __bf16 h = (__bf16)v;
-        s_x[r * kLdIn + k] = h;
-        if (acts) acts[(int64_t)k * Mp + m] = h;
+        s_x[r * kLdIn + k] = (__bf16)v;
     }
     __syncthreads();
+    if (acts)   // transposed copy for the weight gradients, rows contiguous
+        for (int i = tid; i < kTM * kIn; i += blockDim.x) {
+            const int k = i / kTM, r = i % kTM;
+            acts[(int64_t)k * Mp + m_base + r] = s_x[r * kLdIn + k];
+        }
     __bf16 *a1 = acts ? acts + (int64_t)kIn * Mp : nullptr;
     __bf16 *a2 = acts ? a1 + (int64_t)kH * Mp : nullptr;
     __bf16 *a3 = acts ? a2 + (int64_t)kH * Mp : nullptr;
-    hidden_layer<kIn>(s_x, kLdIn, W + wW1t, P + oB1, s_a, a1, Mp, m_base, M, wrow);
+    hidden_layer<kIn>(s_x, kLdIn, W + wW1t, P + oB1, s_a, a1, Mp, m_base, M);
     __syncthreads();
-    hidden_layer<kH>(s_a, kLd, W + wW2t, P + oB2, s_b, a2, Mp, m_base, M, wrow);
+    hidden_layer<kH>(s_a, kLd, W + wW2t, P + oB2, s_b, a2, Mp, m_base, M);
     __syncthreads();
-    hidden_layer<kH>(s_b, kLd, W + wW3t, P + oB3, s_a, a3, Mp, m_base, M, wrow);
+    hidden_layer<kH>(s_b, kLd, W + wW3t, P + oB3, s_a, a3, Mp, m_base, M);
     __syncthreads();
     // output layer: one 16x16 tile per wave, columns 0..1 are real
     const int l = tid & 63;
@@ -210,41 +226,52 @@ __global__ void k_mlp_loss_final(const double *__restrict__ partial, int n, int6
 
 // ----------------------------------------------------------- backward data --
 
-// dH_l = (dH_{l+1} W_{l+1}^T) * 1[H_l > 0] for the wave's 16 rows; A is the
-// row-major dH_{l+1} tile in LDS, Wr the row-major W_{l+1} ([k_l][k_{l+1}]).
+// dH_l = (dH_{l+1} W_{l+1}^T) * 1[H_l > 0] for the workgroup's 64 rows; A is
+// the row-major dH_{l+1} tile in LDS, Wr the row-major W_{l+1} ([k_l][k_{l+1}],
+// i.e. the B operand with k_{l+1} contiguous).  Wave w owns columns
+// [64 w, 64 w + 64) of dH_l, as in the forward's hidden layers.
 __device__ inline void back_layer(const __bf16 *__restrict__ A, const __bf16 *__restrict__ Wr,
                                   const __bf16 *__restrict__ h_t, __bf16 *__restrict__ O,
-                                  __bf16 *__restrict__ d_t, int64_t Mp, int64_t m_base, int wrow) {
+                                  __bf16 *__restrict__ d_t, int64_t Mp, int64_t m_base) {
     const int l = threadIdx.x & 63;
-    floatx4 acc[kH / 16];
+    const int c0 = (threadIdx.x >> 6) * 64;
+    floatx4 acc[4][4];
 #pragma unroll
-    for (int t = 0; t < kH / 16; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
     for (int ks = 0; ks < kH / 32; ++ks) {
-        const bf16x8 a = frag(A + (wrow + (l & 15)) * kLd + ks * 32 + (l >> 4) * 8);
+        bf16x8 a[4], bq[4];
 #pragma unroll
-        for (int t = 0; t < kH / 16; ++t) {
-            const bf16x8 b = frag(Wr + (t * 16 + (l & 15)) * kH + ks * 32 + (l >> 4) * 8);
-            acc[t] = mfma(a, b, acc[t]);
-        }
+        for (int ct = 0; ct < 4; ++ct) bq[ct] = frag(Wr + (c0 + ct * 16 + (l & 15)) * kH + ks * 32 + (l >> 4) * 8);
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) a[rt] = frag(A + (rt * 16 + (l & 15)) * kLd + ks * 32 + (l >> 4) * 8);
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = mfma(a[rt], bq[ct], acc[rt][ct]);
     }
 #pragma unroll
-    for (int t = 0; t < kH / 16; ++t) {
-        const int col = t * 16 + (l & 15);
-        const int64_t m0 = m_base + wrow + (l >> 4) * 4;
-        const bf16x4 h4 = *reinterpret_cast<const bf16x4 *>(h_t + (int64_t)col * Mp + m0);
-        bf16x4 d4;
+    for (int ct = 0; ct < 4; ++ct) {
+        const int col = c0 + ct * 16 + (l & 15);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const __bf16 d = (float)h4[i] > 0.0f ? (__bf16)acc[t][i] : (__bf16)0.0f;
-            if (O) O[(wrow + (l >> 4) * 4 + i) * kLd + col] = d;
-            d4[i] = d;
+        for (int rt = 0; rt < 4; ++rt) {
+            const int64_t m0 = m_base + rt * 16 + (l >> 4) * 4;
+            const bf16x4 h4 = *reinterpret_cast<const bf16x4 *>(h_t + (int64_t)col * Mp + m0);
+            bf16x4 d4;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const __bf16 d = (float)h4[i] > 0.0f ? (__bf16)acc[rt][ct][i] : (__bf16)0.0f;
+                if (O) O[(rt * 16 + (l >> 4) * 4 + i) * kLd + col] = d;
+                d4[i] = d;
+            }
+            *reinterpret_cast<bf16x4 *>(d_t + (int64_t)col * Mp + m0) = d4;
         }
-        *reinterpret_cast<bf16x4 *>(d_t + (int64_t)col * Mp + m0) = d4;
     }
 }
 
-__global__ __launch_bounds__(256) void k_mlp_bwd(const __bf16 *__restrict__ W, const __bf16 *__restrict__ acts,
+__global__ __launch_bounds__(256, 2) void k_mlp_bwd(const __bf16 *__restrict__ W, const __bf16 *__restrict__ acts,
                                                  const float *__restrict__ dout, int64_t Mp,
                                                  __bf16 *__restrict__ dacts) {
     __shared__ __align__(16) __bf16 s_a[kTM * kLd];
@@ -259,7 +286,7 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(const __bf16 *__restrict__ W, c
     // dH3 = dout W4^T * 1[H3 > 0]: an inner dimension of 2, plain FMAs
     const __bf16 *w4r = W + wW4r;
     for (int i = tid; i < kTM * kH; i += blockDim.x) {
-        const int r = i / kH, k = i % kH;
+        const int k = i / kTM, r = i % kTM;      // rows fastest: the transposed arrays are read contiguously
         const int64_t m = m_base + r;
         const float g = dout[m * 2] * (float)w4r[k * kOP] + dout[m * 2 + 1] * (float)w4r[k * kOP + 1];
         const __bf16 d = (float)h3[(int64_t)k * Mp + m] > 0.0f ? (__bf16)g : (__bf16)0.0f;
@@ -267,9 +294,9 @@ __global__ __launch_bounds__(256) void k_mlp_bwd(const __bf16 *__restrict__ W, c
         d3[(int64_t)k * Mp + m] = d;
     }
     __syncthreads();
-    back_layer(s_a, W + wW3r, h2, s_b, d2, Mp, m_base, wrow);
+    back_layer(s_a, W + wW3r, h2, s_b, d2, Mp, m_base);
     __syncthreads();
-    back_layer(s_b, W + wW2r, h1, nullptr, d1, Mp, m_base, wrow);
+    back_layer(s_b, W + wW2r, h1, nullptr, d1, Mp, m_base);
 }
 
 // ------------------------------------------------------- weight gradients --
@@ -310,28 +337,41 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad(const __bf16 *__restrict__ At
     }
 }
 
-// bias gradient: g[n] = sum_m Bt[n][m], one block per n
-__global__ void k_mlp_bgrad(const __bf16 *__restrict__ Bt, int64_t Mp, float *__restrict__ g) {
+// bias gradient: g[n] += sum of Bt[n][m] over this block's slice of m
+// (grid: n x slices; g is zeroed beforehand)
+__global__ void k_mlp_bgrad(const __bf16 *__restrict__ Bt, int64_t Mp, int64_t m_per, float *__restrict__ g) {
     __shared__ float s_red[4];
     float acc = 0.0f;
     const __bf16 *row = Bt + (int64_t)blockIdx.x * Mp;
-    for (int64_t m = threadIdx.x; m < Mp; m += blockDim.x) acc += (float)row[m];
+    const int64_t m0 = (int64_t)blockIdx.y * m_per, m1 = min(m0 + m_per, Mp);
+    for (int64_t m = m0 + threadIdx.x; m < m1; m += blockDim.x) acc += (float)row[m];
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
     if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) g[blockIdx.x] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+    if (threadIdx.x == 0) atomicAdd(g + blockIdx.x, s_red[0] + s_red[1] + s_red[2] + s_red[3]);
 }
 
-// bias gradient of the output layer from the FP32 output gradient
-__global__ void k_mlp_bgrad_out(const float *__restrict__ dout, int64_t Mp, float *__restrict__ g) {
-    __shared__ float s_red[4];
-    const int j = blockIdx.x;
-    float acc = 0.0f;
-    for (int64_t m = threadIdx.x; m < Mp; m += blockDim.x) acc += dout[m * 2 + j];
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
-    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = acc;
+// bias gradient of the output layer from the FP32 output gradient [Mp][2]
+__global__ void k_mlp_bgrad_out(const float *__restrict__ dout, int64_t Mp, int64_t m_per, float *__restrict__ g) {
+    __shared__ float s_red[2][4];
+    float a0 = 0.0f, a1 = 0.0f;
+    const int64_t m0 = (int64_t)blockIdx.x * m_per, m1 = min(m0 + m_per, Mp);
+    for (int64_t m = m0 + threadIdx.x; m < m1; m += blockDim.x) {
+        a0 += dout[m * 2];
+        a1 += dout[m * 2 + 1];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        a0 += __shfl_down(a0, o, 64);
+        a1 += __shfl_down(a1, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_red[0][threadIdx.x >> 6] = a0;
+        s_red[1][threadIdx.x >> 6] = a1;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) g[j] = s_red[0] + s_red[1] + s_red[2] + s_red[3];
+    if (threadIdx.x < 2)
+        atomicAdd(g + threadIdx.x, s_red[threadIdx.x][0] + s_red[threadIdx.x][1] + s_red[threadIdx.x][2] +
+                                       s_red[threadIdx.x][3]);
 }
 
 static int launch_wgrad(const __bf16 *At, const __bf16 *Bt, int K, int N, int64_t Mp, float *G,
@@ -439,10 +479,13 @@ int sbp_mlp_backward(sbp_ctx *ctx, const uint16_t *work, const uint16_t *acts, c
     if ((rc = launch_wgrad(h2, d3, kH, kH, Mp, grad + oW3, kH, st))) return rc;
     if ((rc = launch_wgrad(h3, (const __bf16 *)dout_t, kH, SBP_MLP_OUT, Mp, grad + oW4, SBP_MLP_OUT, st)))
         return rc;
-    hipLaunchKernelGGL(k_mlp_bgrad, dim3(kH), dim3(256), 0, st, d1, Mp, grad + oB1);
-    hipLaunchKernelGGL(k_mlp_bgrad, dim3(kH), dim3(256), 0, st, d2, Mp, grad + oB2);
-    hipLaunchKernelGGL(k_mlp_bgrad, dim3(kH), dim3(256), 0, st, d3, Mp, grad + oB3);
-    hipLaunchKernelGGL(k_mlp_bgrad_out, dim3(SBP_MLP_OUT), dim3(256), 0, st, dout, Mp, grad + oB4);
+    // bias gradients: slices of 8192 rows, summed with FP32 atomics into the zeroed grad
+    const int64_t m_per = 8192;
+    const unsigned nsl = (unsigned)((Mp + m_per - 1) / m_per);
+    hipLaunchKernelGGL(k_mlp_bgrad, dim3(kH, nsl), dim3(256), 0, st, d1, Mp, m_per, grad + oB1);
+    hipLaunchKernelGGL(k_mlp_bgrad, dim3(kH, nsl), dim3(256), 0, st, d2, Mp, m_per, grad + oB2);
+    hipLaunchKernelGGL(k_mlp_bgrad, dim3(kH, nsl), dim3(256), 0, st, d3, Mp, m_per, grad + oB3);
+    hipLaunchKernelGGL(k_mlp_bgrad_out, dim3(nsl), dim3(256), 0, st, dout, Mp, m_per, grad + oB4);
     SBP_HIP(hipGetLastError());
     return SBP_OK;
 }
