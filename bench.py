@@ -130,6 +130,43 @@ def mlp_rates(ctx, dev, M=262144, reps=20):
             "train_TFLOPs": train / 1e12, "train_frac_bf16_peak": train / BF16_PEAK}
 
 
+def learned_vs_plain(ctx, train_runs=4, n_init=20000, evals=2, epochs=4):
+    """The second half of the metric: wall time to the plain method's final
+    residual, with and without the growth-proposal network (trained here on
+    `train_runs` plain reconstructions; both runs eager, the network acting in
+    the coarse stage; the plain run's time is its first final-stage iteration
+    at or below its own final loss plus 0.1 %)."""
+    import numpy as np
+    import torch
+    from paper_2601_00551_amd import proposal
+    grid = proposal.Grid.cube(10.0, 0.2)
+    stages = proposal.default_schedule((4, 2, 1), iters=60)
+    t0 = time.perf_counter()
+    X, yg, yp = proposal.generate(ctx, range(train_runs), grid, stages, n_init=n_init, log=lambda *a, **k: None)
+    t_gen = time.perf_counter() - t0
+    net = proposal.ProposalMLP(ctx, seed=0)
+    t0 = time.perf_counter()
+    proposal.train(net, X, yg, yp, epochs=epochs, log=lambda *a, **k: None)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    plain_s, learned_s = [], []
+    for j in range(evals):
+        wl = proposal.proposal_workload(10_000 + j, n_init=n_init)
+        y = proposal.synthetic_measurement(ctx, wl, seed=60_000 + j)
+        cap = 4 * len(wl.init["x"])
+        _, plain = proposal.plain_run(ctx, wl, y, stages, capacity=cap)
+        target = plain["final_loss"] * (1.0 + 1e-3)
+        lp = proposal.LearnedProposer(net, proposal.FeatureBuilder(ctx, grid, a_probe=0.1, half=10.0),
+                                      a_init=wl.a_init, stages=[0])
+        _, learned = proposal.plain_run(ctx, wl, y, stages, capacity=cap, stop_below=target, proposer=lp)
+        plain_s.append(proposal.first_below(plain["log"], target))
+        learned_s.append(learned["t_target"] if learned["t_target"] is not None else float("nan"))
+    return {"workload": f"conformal-ell512-tree-T2048-40MHz, {n_init} initial balls",
+            "plain_s": float(np.mean(plain_s)), "learned_s": float(np.mean(learned_s)),
+            "speedup": float(np.mean(plain_s) / np.mean(learned_s)), "phantoms": evals,
+            "train_runs": train_runs, "train_samples": int(len(X)), "generate_s": t_gen, "train_s": t_train}
+
+
 def _timed(fn, reps):
     """Average milliseconds of fn() over reps calls, bracketed by events on the current stream."""
     import torch
@@ -283,6 +320,8 @@ def main():
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2601_00551_amd", "tuning.json"))
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (the reference for HBM counters)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-vs-plain reconstruction timing")
     ap.add_argument("--suite", action="store_true",
                     help="measure the other workloads instead (one JSON line each)")
     args = ap.parse_args()
@@ -437,6 +476,8 @@ def main():
         "wall_s": wall,
     }
     line["mlp"] = mlp_rates(ctx, dev)
+    if not args.no_learned:
+        line["learned_vs_plain"] = learned_vs_plain(ctx)
     if args.cpu_sample > 0:
         line["cpu_baseline"] = cpu_baseline(wl, {"c": c, "dt": dt, "T": T}, args.cpu_sample)
     print(json.dumps(line), flush=True)
