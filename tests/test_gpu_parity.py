@@ -509,3 +509,50 @@ def test_step_graph_replays_match_eager(ctx):
             assert np.max(np.abs(a - b)) <= 1e-5 * max(1.0, np.abs(b).max()), (rep, k)
     assert graph.step_dev.item() == 10
     graph.close()
+
+
+def test_sixty_four_frames(ctx):
+    """The largest batch the ABI takes (SBP_MAX_FRAMES = 64 frames), with empty
+    and uneven frames: every frame's signals and gradients against the oracle
+    run on that frame alone, the filter's offsets, and a captured step."""
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(640)
+    arr = synth.hemisphere_array(9, 12.0, rng, tilt_deg=20)
+    sizes = rng.integers(0, 120, size=api._abi.MAX_FRAMES)
+    sizes[[0, 7, 63]] = 0
+    parts = [synth.uniform_balls(rng, int(n), 3.5, 0.15) for n in sizes]
+    balls = synth.concat_balls(parts)
+    off = np.cumsum([0] + [int(n) for n in sizes])
+    F, T = len(sizes), 300
+    v = rng.normal(size=(F, 9, T)).astype(np.float32)
+    toff = torch.as_tensor(off, device=dev)
+    y = run_fwd(ctx, arr, balls, gmodel(T), ball_off=toff).cpu().numpy()
+    g = run_adj(ctx, arr, balls, gmodel(T), v, ball_off=toff)
+    for f in range(F):
+        b = {k: balls[k][off[f]:off[f + 1]] for k in PARAMS}
+        if sizes[f] == 0:
+            assert np.all(y[f] == 0.0)
+            continue
+        assert rel_l2(y[f], oracle.simulate(b, arr, otime(T))) <= SIG_TOL, f
+        ref = oracle.vjp(b, arr, otime(T), v[f])
+        for k in PARAMS:
+            assert rel_l2(g[k][off[f]:off[f + 1]], ref[k]) <= GRAD_TOL, (f, k)
+    out, off_out, gf, _ = api.filter_zero_grad(ctx, to_dev(arr, dev), to_dev(balls, dev), gmodel(T),
+                                               torch.as_tensor(v, device=dev), ball_off=toff)
+    gh = gf.cpu().numpy()
+    exp = np.cumsum([0] + [int((gh[off[f]:off[f + 1]] < 0).sum()) for f in range(F)])
+    assert list(off_out.cpu().numpy()) == list(exp)
+    # one captured iteration over all 64 frames equals an eager one
+    prm = api.AdamParams(step=1)
+    st_e = api.State(balls, ball_off=off, device=dev)
+    st_g = api.State(balls, ball_off=off, device=dev)
+    y_ref = torch.as_tensor(y * 0.9, device=dev)
+    yw_e, yw_g = torch.empty_like(y_ref), torch.empty_like(y_ref)
+    graph = api.StepGraph(ctx, to_dev(arr, dev), st_g, gmodel(T), y_ref, yw_g, prm, iters=1, step0=1)
+    le = api.step(ctx, to_dev(arr, dev), st_e, gmodel(T), y_ref, yw_e, prm).cpu().numpy()
+    graph.launch()
+    graph.stream.synchronize()
+    np.testing.assert_array_equal(graph.loss.cpu().numpy(), le)
+    for k in PARAMS:
+        assert torch.equal(st_g.balls[k], st_e.balls[k]), k
+    graph.close()
