@@ -87,10 +87,36 @@ def cpu_baseline(wl, model_kw, n_balls_sample, rng_seed=0):
     oracle.vjp(balls, wl.array, tm, v)
     t2 = time.perf_counter()
     pairs = n_balls_sample * D
-    return {"value": pairs / (t2 - t0), "unit": "pairs/s", "cores": oracle.num_threads(),
+    cores = oracle.num_threads()
+    # one thread on a sixteenth of the sample
+    n1 = max(1, n_balls_sample // 16)
+    b1 = {k: arr[:n1] for k, arr in balls.items()}
+    prev = cores
+    oracle.set_threads(1)
+    try:
+        t3 = time.perf_counter()
+        oracle.simulate(b1, wl.array, tm)
+        oracle.vjp(b1, wl.array, tm, v)
+        t4 = time.perf_counter()
+    finally:
+        oracle.set_threads(prev)
+    return {"value": pairs / (t2 - t0), "unit": "pairs/s", "cores": cores, "cpu_model": cpu_model_name(),
             "kind": "oracle",
             "sample": f"{n_balls_sample} of the {len(wl.init['x'])} balls x all {D} transducers, "
-                      f"T={model_kw['T']}: oracle forward {t1 - t0:.2f} s + VJP {t2 - t1:.2f} s"}
+                      f"T={model_kw['T']}: oracle forward {t1 - t0:.2f} s + VJP {t2 - t1:.2f} s",
+            "single_thread": {"value": n1 * D / (t4 - t3), "unit": "pairs/s",
+                              "sample": f"{n1} balls x {D} transducers, forward + VJP {t4 - t3:.2f} s"}}
+
+
+def cpu_model_name():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 MLP_FLOP_FWD = 2 * (31 * 256 + 2 * 256 * 256 + 256 * 2)   # per candidate row

@@ -82,6 +82,11 @@ def num_threads() -> int:
     return int(_lib().orc_num_threads())
 
 
+def set_threads(n: int) -> int:
+    """Use n OpenMP threads from now on; returns the number in use."""
+    return int(_lib().orc_set_threads(int(n)))
+
+
 def _ctime(tm: Time) -> _CTime:
     return _CTime(float(tm.c), float(tm.dt), float(tm.t0), float(tm.K), int(tm.T), int(tm.f),
                   int(tm.profile), int(tm.directivity), int(tm.sampling), 0)

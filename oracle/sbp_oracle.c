@@ -286,3 +286,16 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Set the number of OpenMP threads (the single-thread timing beside the
+ * all-core one); returns the number now in use. */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+    return orc_num_threads();
+}
