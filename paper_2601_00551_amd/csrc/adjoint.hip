@@ -20,13 +20,73 @@ namespace sbp {
 
 constexpr int kMaxBpt = 4;
 
-// Edges per exact restart of the Gaussian recurrence below.
+// Edges per exact restart of the Gaussian recurrence below; the UNIFORM
+// profile uses blocks of the same length for its moment sums.
 constexpr int kRestart = 16;
-// Edges whose staged values are loaded together in FP32 (eight measured
-// faster than sixteen); the FP64 twin, which already spills at this register
-// budget, keeps one edge per trip.
-template <typename R> struct EdgeGroup { static constexpr int gauss = 8, uniform = 8; };
-template <> struct EdgeGroup<double> { static constexpr int gauss = 1, uniform = 1; };
+// Staged values loaded together (one LDS latency per group, not per edge).
+constexpr int kGroup = 8;
+// FP32 unrolls a whole block with its edge offsets as constants; the FP64
+// twin, which spills at this register budget, keeps a run-time loop.
+template <typename R> struct BlockUnroll { static constexpr bool on = true; };
+template <> struct BlockUnroll<double> { static constexpr bool on = false; };
+
+// Transducer data is read-only for the whole launch and indexed by a
+// wave-uniform value: read it through the scalar cache.
+template <typename R> __device__ __forceinline__ R ld_uniform(const R *p) {
+    return *(const __attribute__((address_space(4))) R *)p;
+}
+
+// Moment sums of one block of n <= kRestart edges starting at m0, j = m - m0:
+//   Z = sum w_j f_j,  Z1 = sum w_j f_j j,  Z2 = sum w_j f_j j^2
+// with f_j = e_j (GAUSS, e_{j+1} = e_j g_j, g_{j+1} = g_j h) or 1 (UNIFORM).
+// Along the edges u_j = u_0 - j c, so sum w f u = u_0 Z - c Z1 and
+// sum w f u^2 = u_0 (u_0 Z - 2 c Z1) + c^2 Z2: three sums per edge replace the
+// running u and its two products.
+template <typename R, int PROF, bool MOM>
+__device__ inline void block_moments(const R *__restrict__ wb, int n, R e, R gq, R h, R &Z, R &Z1,
+                                     R &Z2) {
+    auto edge = [&](R w, R j, bool j0) {
+        const R wf = PROF == GAUSS ? w * e : w;
+        Z += wf;
+        if (MOM && !j0) {
+            Z1 = fma(wf, j, Z1);
+            Z2 = fma(wf, j * j, Z2);
+        }
+        if (PROF == GAUSS) {
+            e *= gq;
+            gq *= h;
+        }
+    };
+    if (BlockUnroll<R>::on && n == kRestart) {
+#pragma unroll
+        for (int g0 = 0; g0 < kRestart; g0 += kGroup) {
+            R w[kGroup];
+#pragma unroll
+            for (int k = 0; k < kGroup; ++k) w[k] = wb[g0 + k];
+#pragma unroll
+            for (int k = 0; k < kGroup; ++k) edge(w[k], R(g0 + k), g0 + k == 0);
+        }
+        return;
+    }
+    int k = 0;
+    R j = R(0);
+    if (BlockUnroll<R>::on) {
+        for (; k + kGroup <= n; k += kGroup) {
+            R w[kGroup];
+#pragma unroll
+            for (int i = 0; i < kGroup; ++i) w[i] = wb[k + i];
+#pragma unroll
+            for (int i = 0; i < kGroup; ++i) {
+                edge(w[i], j, false);
+                j += R(1);
+            }
+        }
+    }
+    for (; k < n; ++k) {
+        edge(wb[k], j, false);
+        j += R(1);
+    }
+}
 
 // Accumulates the pair's support edges in the staged tile [tlo, thi)
 // (wr[m - tlo]).  Everything is linear in (S0, S1, S2), so tiles add up.
@@ -34,11 +94,13 @@ template <> struct EdgeGroup<double> { static constexpr int gauss = 1, uniform =
 // GAUSS: along the edges u_{m+1} = u_m - c, so e_m = exp(-u_m^2 / (2 a^2))
 // obeys e_{m+1} = e_m g_m with g_{m+1} = g_m h, h = exp(-c^2 / a^2): two
 // multiplies per edge instead of an exponential.  Both are recomputed
-// exactly every kRestart edges (relative drift below 1e-5 in between).
+// exactly every kRestart edges (relative drift below 1e-5 in between).  The
+// plain sum of w over the pair's edges telescopes, sum_{m=mb}^{me} w_m =
+// vscale (v_me - v_{mb-1}), and is read from the cotangent row `vrow`.
 template <typename R, int PROF, int DIR, bool FULL>
 __device__ inline void adj_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx, R ny, R nz,
                                 const Level &lc, int tlo, int thi, const R *__restrict__ wr,
-                                R acc[5]) {
+                                const R *__restrict__ vrow, R vscale, R acc[5]) {
     PairG<R> g;
     if (!pair_geometry<R, DIR>(b.x, b.y, b.z, b.w, qx, qy, qz, nx, ny, nz, lc, g)) return;
     // support edges: |u_m| < w  <=>  (s - w) / (c dt) < m < (s + w) / (c dt)
@@ -47,70 +109,44 @@ __device__ inline void adj_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx,
     if (hi < (double)tlo || lo > (double)(thi - 1) || hi < lo) return;
     const int mb = lo < (double)tlo ? tlo : (int)lo;
     const int me = hi > (double)(thi - 1) ? thi - 1 : (int)hi;
+    R vhi = R(0), vlo = R(0);
+    if (PROF == GAUSS) {
+        vhi = me < lc.T ? vrow[me] : R(0);
+        vlo = mb > 0 ? vrow[mb - 1] : R(0);
+    }
     wr -= tlo;
     const R c = LevelR<R>::cdt(lc);
-    constexpr int kUnroll = PROF == GAUSS ? EdgeGroup<R>::gauss : EdgeGroup<R>::uniform;
+    // P = sum w f, A1 = sum w f u, A2 = sum w f u^2 (f = e for GAUSS, 1 for
+    // UNIFORM), W = sum w
     R P = R(0), W = R(0), A1 = R(0), A2 = R(0);
-    // The staged rows are read kUnroll edges at a time, all loads issued before
-    // the arithmetic, so that one LDS latency is paid per group, not per edge.
-    if (PROF == GAUSS) {
-        for (int m0 = mb; m0 <= me; m0 += kRestart) {
-            R u = (R)(g.s - (double)m0 * lc.cdt);
-            R e = ex2(u * u * b.q0);
-            R gq = ex2(b.q0 * c * (c - R(2) * u));
-            const int m1 = min(m0 + kRestart - 1, me);
-            auto edge = [&](R w) {
-                W += w;
-                if (FULL) {
-                    const R we = w * e;
-                    P += we;
-                    const R wu = we * u;
-                    A1 += wu;
-                    A2 = fma(wu, u, A2);
-                    u -= c;
-                } else {
-                    P = fma(w, e, P);
-                }
-                e *= gq;
-                gq *= b.h;
-            };
-            int m = m0;
-            for (; m + kUnroll - 1 <= m1; m += kUnroll) {
-                R w[kUnroll];
-#pragma unroll
-                for (int k = 0; k < kUnroll; ++k) w[k] = wr[m + k];
-#pragma unroll
-                for (int k = 0; k < kUnroll; ++k) edge(w[k]);
-            }
-            for (; m <= m1; ++m) edge(wr[m]);
+    constexpr bool MOM = FULL || PROF == UNIFORM;
+    for (int m0 = mb; m0 <= me; m0 += kRestart) {
+        const R u0 = (R)(g.s - (double)m0 * lc.cdt);
+        const int n = min(kRestart, me - m0 + 1);
+        R e = R(1), gq = R(1);
+        if (PROF == GAUSS) {
+            e = ex2(u0 * u0 * b.q0);
+            gq = ex2(b.q0 * c * (c - R(2) * u0));
         }
-    } else {
-        R u = (R)(g.s - (double)mb * lc.cdt);
-        auto edge = [&](R w) {
-            W += w;
-            const R wu = w * u;
-            A1 += wu;
-            P = fma(wu, u, P);     // sum w u^2
-            u -= c;
-        };
-        int m = mb;
-        for (; m + kUnroll - 1 <= me; m += kUnroll) {
-            R w[kUnroll];
-#pragma unroll
-            for (int k = 0; k < kUnroll; ++k) w[k] = wr[m + k];
-#pragma unroll
-            for (int k = 0; k < kUnroll; ++k) edge(w[k]);
+        R Z = R(0), Z1 = R(0), Z2 = R(0);
+        block_moments<R, PROF, MOM>(wr + m0, n, e, gq, b.h, Z, Z1, Z2);
+        P += Z;
+        if (MOM) {
+            const R cZ1 = c * Z1;
+            A1 += u0 * Z - cZ1;
+            A2 += u0 * fma(u0, Z, R(-2) * cZ1) + c * c * Z2;
         }
-        for (; m <= me; ++m) edge(wr[m]);
     }
     R S0, S1, S2;
     if (PROF == GAUSS) {
+        W = vscale * (vhi - vlo);
         const R A0 = P - LevelR<R>::eK(lc) * W;          // sum w (e - e^{-K^2/2})
         S0 = -(b.a * b.a) * A0;
         S1 = A1;
         S2 = R(-2) * b.a * A0 - A2 / b.a;
     } else {
-        S0 = R(-0.5) * (b.q0 * W - P);                   // -(1/2) sum w (a^2 - u^2)
+        W = P;
+        S0 = R(-0.5) * (b.q0 * W - A2);                  // -(1/2) sum w (a^2 - u^2)
         S1 = A1;
         S2 = -b.a * W;
     }
@@ -202,14 +238,18 @@ __global__ __launch_bounds__(512, 4) void k_adjoint(ArrayP<R> arr, BallsP<R> bal
                     }
                 }
                 __syncthreads();
+                for (int dl = 0; dl < nd; ++dl) {
+                    const int d = __builtin_amdgcn_readfirstlane(d0 + dl);
+                    const R qx = ld_uniform(arr.qx + d), qy = ld_uniform(arr.qy + d),
+                            qz = ld_uniform(arr.qz + d), nx = ld_uniform(arr.nx + d),
+                            ny = ld_uniform(arr.ny + d), nz = ld_uniform(arr.nz + d);
+                    const R *wrow = rows + (int64_t)dl * TT;
+                    const R *vrow = vf + (int64_t)d * T;
 #pragma unroll
-                for (int jb = 0; jb < kMaxBpt; ++jb) {
-                    if (!act[jb]) continue;
-                    for (int dl = 0; dl < nd; ++dl) {
-                        const int d = __builtin_amdgcn_readfirstlane(d0 + dl);
-                        adj_pair<R, PROF, DIR, FULL>(b[jb], arr.qx[d], arr.qy[d], arr.qz[d],
-                                                     arr.nx[d], arr.ny[d], arr.nz[d], lc, tlo, thi,
-                                                     rows + (int64_t)dl * TT, acc[jb]);
+                    for (int jb = 0; jb < kMaxBpt; ++jb) {
+                        if (!act[jb]) continue;
+                        adj_pair<R, PROF, DIR, FULL>(b[jb], qx, qy, qz, nx, ny, nz, lc, tlo, thi,
+                                                     wrow, vrow, vscale, acc[jb]);
                     }
                 }
             }
