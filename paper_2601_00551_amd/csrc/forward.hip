@@ -73,6 +73,12 @@ __global__ void k_amp_bound(BallsP<float> balls, const int64_t *__restrict__ bal
     }
 }
 
+// Bins per unrolled block of the FP32 loops (the FP64 twin keeps the plain
+// loop: its exponential is a call, not an instruction).
+constexpr int kFwdBlock = 8;
+template <typename R> struct FwdBlocks { static constexpr bool on = true; };
+template <> struct FwdBlocks<double> { static constexpr bool on = false; };
+
 // Adds the pair's bins that fall in the time tile [tlo, thi) to row[n - tlo];
 // `scale` multiplies the bin values (the fixed-point quantum's inverse).
 template <typename R, int PROF, int DIR>
@@ -99,8 +105,30 @@ __device__ inline void fwd_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx,
         // one exponential per edge: a recurrence drifts by ~1e-7 per step, and
         // bin differences amplify that by a / (c dt), up to ~10^2 here
         const R eK = LevelR<R>::eK(lc);
-        const R u0 = (R)(g.s - (double)nb * lc.cdt);
-        R prev = first_out ? eK : ex2(u0 * u0 * b.q0);
+        R prev;
+        int m = nb;   // left edge of the next bin
+        {
+            const R u0 = (R)(g.s - (double)nb * lc.cdt);
+            prev = first_out ? eK : ex2(u0 * u0 * b.q0);
+        }
+        if (FwdBlocks<R>::on) {
+            // blocks of kFwdBlock bins, the edge offsets k as constants:
+            // q0 (u_m - k c)^2 = X0 + k (X1 + k X2), u_m formed exactly per block
+            const R X2 = b.q0 * c * c;
+            const R Y1 = R(-2) * b.q0 * c;
+            for (; cnt >= kFwdBlock; cnt -= kFwdBlock, p += kFwdBlock, m += kFwdBlock) {
+                const R ub = (R)(g.s - (double)m * lc.cdt);
+                const R X0 = b.q0 * ub * ub;
+                const R X1 = Y1 * ub;
+#pragma unroll
+                for (int k = 1; k <= kFwdBlock; ++k) {
+                    const R e = ex2(fma(R(k), fma(R(k), X2, X1), X0));
+                    FwdAcc<R>::add(p + (k - 1), amp * (prev - e));
+                    prev = e;
+                }
+            }
+        }
+        const R u0 = (R)(g.s - (double)m * lc.cdt);
         R j = R(1);
         // two bins per trip (no register copy of the carried edge value)
         for (; cnt >= 2; cnt -= 2, p += 2, j += R(2)) {
@@ -121,8 +149,28 @@ __device__ inline void fwd_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx,
         }
         if (last_out) FwdAcc<R>::add(p, amp * (prev - eK));
     } else {
-        R u = (R)(g.s - (double)nb * lc.cdt);
-        R prev = first_out ? R(0) : b.q0 - u * u;
+        R prev;
+        int m = nb;
+        {
+            const R u0 = (R)(g.s - (double)nb * lc.cdt);
+            prev = first_out ? R(0) : b.q0 - u0 * u0;
+        }
+        if (FwdBlocks<R>::on) {
+            // (u_m - k c)^2 - (u_m - (k-1) c)^2 = -2 u_m c + (2k - 1) c^2: past
+            // the block's first bin the bins are linear in k
+            const R B1 = amp * R(2) * c * c;
+            for (; cnt >= kFwdBlock; cnt -= kFwdBlock, p += kFwdBlock, m += kFwdBlock) {
+                const R ub = (R)(g.s - (double)m * lc.cdt);
+                const R u1 = ub - c;
+                FwdAcc<R>::add(p, amp * (prev - (b.q0 - u1 * u1)));
+                const R B0 = amp * fma(R(-2) * c, ub, -(c * c));
+#pragma unroll
+                for (int k = 2; k <= kFwdBlock; ++k) FwdAcc<R>::add(p + (k - 1), fma(B1, R(k), B0));
+                const R ue = fma(R(-kFwdBlock), c, ub);
+                prev = b.q0 - ue * ue;
+            }
+        }
+        R u = (R)(g.s - (double)m * lc.cdt);
         for (; cnt >= 2; cnt -= 2, p += 2) {
             const R u1 = u - c;
             u = u1 - c;
