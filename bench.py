@@ -25,12 +25,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # --- algorithmic VALU lane-operations (FP32-equivalent issue slots; a
-# transcendental counts 4, the quarter rate of sqrt / rcp / exp on CDNA) -----
-OPS_GEOMETRY = 31        # per pair: offset, rho (sqrt), 1/rho, e_hat, cosine, window, amplitude
-OPS_FWD_EDGE = 12        # per edge: u, u^2 k, exp, support clamp, scale, bin difference, accumulate
-OPS_ADJ_EDGE = 13        # per edge: u, u^2 k, exp, support select, three weighted sums
+# transcendental counts 2: exp2, rcp and sqrt issue at half the FMA rate on
+# gfx950, as `bench.py --rates` measures) -----------------------------------
+OPS_GEOMETRY = 27        # per pair: offset, rho (sqrt), 1/rho, e_hat, cosine, window, amplitude
+OPS_FWD_EDGE = 10        # per edge: u, u^2 k, exp, support clamp, scale, bin difference, accumulate
+OPS_ADJ_EDGE = 11        # per edge: u, u^2 k, exp, support select, three weighted sums
 OPS_ADJ_PAIR = 26        # per pair: S0..S2, dL/dp0, dL/da, radial and directivity terms
-OPS_FLT_EDGE = 10        # per edge (p0 only): u, u^2 k, exp, select, one weighted sum
+OPS_FLT_EDGE = 8         # per edge (p0 only): u, u^2 k, exp, select, one weighted sum
 OPS_FLT_PAIR = 3
 VALU_PEAK = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock = 3.93e13 lane-ops/s
 
@@ -353,10 +354,18 @@ def main():
                     help="skip the learned-vs-plain reconstruction timing")
     ap.add_argument("--suite", action="store_true",
                     help="measure the other workloads instead (one JSON line each)")
+    ap.add_argument("--rates", action="store_true",
+                    help="only run the issue-rate microbenchmark (VALU, transcendental, LDS)")
     args = ap.parse_args()
     if args.suite:
         suite(args)
         return
+    if args.rates:
+        import subprocess
+        exe = os.path.join(ROOT, "paper_2601_00551_amd", "rates", "sbp_rates")
+        if not os.path.exists(exe):
+            raise SystemExit("sbp_rates is not built: run __graft_entry__.build() first")
+        sys.exit(subprocess.run([exe]).returncode)
     if args.copy_calibration:
         import torch
         src = torch.ones(1 << 28, device="cuda:0")     # 1 GiB of float32
@@ -369,7 +378,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design only, see DESIGN.md)", file=sys.stderr)
+              "(sharding over several GPUs is a design only, not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -19,7 +19,7 @@ Every function follows the definition the paper states (section 4 of
 * :func:`softplus` / :func:`softplus_inv` -- the positivity reparameterisation
   of section 4.3;
 * :func:`grow` -- the split / destroy / duplicate growth rule of section 4.1
-  (thresholds are not given by the paper; parity unpinned, see DESIGN.md).
+  (thresholds are not given by the paper; parity unpinned).
 """
 from __future__ import annotations
 

@@ -20,7 +20,7 @@
  *   and for a transducer outside the support only the first term survives for
  *   t >= 0.  With u = rho - c t this is p = p0 * u * fhat(u) / (2 rho).
  *
- *   Readings taken where the paper is silent (each is listed in the design doc):
+ *   Readings taken where the paper is silent:
  *     - profile GAUSS: fhat(s) = exp(-s^2 / (2 a^2)), truncated at |s| < K a;
  *       profile UNIFORM: fhat(s) = 1 for |s| < a (the textbook N-shaped pulse).
  *     - sampling BIN: sample n is the mean of p over the bin

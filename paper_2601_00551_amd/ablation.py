@@ -8,7 +8,7 @@ one workload and records, every few iterations, the image quality of the
 voxelised cloud against the voxelised phantom (MSE / PSNR / SSIM, on the GPU);
 the time spent measuring is excluded from the reported wall times.
 
-    python -m paper_2601_00551_amd.ablation --out gpurun_out/ablation.json
+    python -m paper_2601_00551_amd.ablation --out ablation.json
 """
 from __future__ import annotations
 

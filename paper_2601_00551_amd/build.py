@@ -53,6 +53,21 @@ def _compile(src, verbose):
     return obj
 
 
+RATES_SRC = os.path.join(HERE, "rates", "rates.hip")
+RATES_OUT = os.path.join(HERE, "rates", "sbp_rates")
+
+
+def build_rates(verbose: bool = False) -> str:
+    """The issue-rate microbenchmark that `bench.py --rates` runs (same flags)."""
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-Xclang", "-target-feature",
+           "-Xclang", "-packed-fp32-ops", RATES_SRC, "-o", RATES_OUT + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(RATES_OUT + ".tmp", RATES_OUT)
+    return RATES_OUT
+
+
 def build(verbose: bool = False, jobs: int = 8) -> str:
     srcs = sources()
     with ThreadPoolExecutor(max_workers=jobs) as ex:
@@ -62,6 +77,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(OUT + ".tmp", OUT)
+    build_rates(verbose)
     return OUT
 
 

@@ -1,0 +1,146 @@
+// Issue-rate microbenchmark for the roofline of the VALU-bound kernels:
+// lane-operations per second on this device for FP32 FMA and multiply, the
+// FP32 transcendentals the physics kernels use (exp2, reciprocal, square
+// root), FP64 FMA, and LDS 64/32-bit integer atomic adds and 32-bit reads at
+// pseudo-random addresses inside one 4096-entry row (the access pattern of
+// the forward's accumulation and of the adjoint's staged rows).
+//
+// Every lane runs eight independent chains so that latency is hidden; the
+// grid fills every CU with eight 256-thread workgroups.  Output: one JSON
+// line with lane-ops/s and lane-ops per clock per CU at the nominal clock.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+
+#define CHECK(x)                                                                      \
+    do {                                                                              \
+        hipError_t e_ = (x);                                                          \
+        if (e_ != hipSuccess) {                                                       \
+            fprintf(stderr, "HIP error %s at line %d\n", hipGetErrorString(e_), __LINE__); \
+            return 1;                                                                 \
+        }                                                                             \
+    } while (0)
+
+enum { OP_FMA, OP_MUL, OP_EXP, OP_RCP, OP_SQRT };
+
+template <int OP>
+__device__ __forceinline__ float op(float x, float a, float b) {
+    if (OP == OP_FMA) return fmaf(x, a, b);
+    if (OP == OP_MUL) return x * a;
+    if (OP == OP_EXP) return __builtin_amdgcn_exp2f(x);
+    if (OP == OP_RCP) return __builtin_amdgcn_rcpf(x);
+    return __builtin_amdgcn_sqrtf(x);
+}
+
+template <int OP>
+__global__ __launch_bounds__(256) void k_f32(float *out, int iters, float a, float b) {
+    float x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = 1.0f + 1e-3f * (float)(threadIdx.x + k);
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) x[k] = op<OP>(x[k], a, b);
+        }
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += x[k];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_f64(double *out, int iters, double a, double b) {
+    double x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = 1.0 + 1e-3 * (double)(threadIdx.x + k);
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) x[k] = fma(x[k], a, b);
+        }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += x[k];
+    out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+// READ = false: atomic adds; READ = true: plain loads summed in registers.
+template <typename T, bool READ>
+__global__ __launch_bounds__(256) void k_lds(unsigned long long *out, int iters) {
+    __shared__ T row[4096];
+    for (int i = threadIdx.x; i < 4096; i += blockDim.x) row[i] = (T)i;
+    __syncthreads();
+    uint32_t h = (blockIdx.x * 256u + threadIdx.x) * 2654435761u + 12345u;
+    T acc = 0;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            h = h * 1664525u + 1013904223u;
+            const uint32_t idx = (h >> 16) & 4095u;
+            if (READ)
+                acc += row[idx];
+            else
+                atomicAdd(&row[idx], (T)(h & 7u));
+        }
+    }
+    __syncthreads();
+    unsigned long long s = (unsigned long long)acc;
+    for (int i = threadIdx.x; i < 4096; i += blockDim.x) s += (unsigned long long)row[i];
+    atomicAdd(out, s);
+}
+
+int main() {
+    hipDeviceProp_t prop;
+    CHECK(hipGetDeviceProperties(&prop, 0));
+    const int cus = prop.multiProcessorCount;
+    const double clk = 2.4e9;
+    const int blocks = cus * 8, threads = 256;
+    float *out = nullptr;
+    double *outd = nullptr;
+    unsigned long long *outl = nullptr;
+    CHECK(hipMalloc(&out, (size_t)blocks * threads * sizeof(float)));
+    CHECK(hipMalloc(&outd, (size_t)blocks * threads * sizeof(double)));
+    CHECK(hipMalloc(&outl, sizeof(unsigned long long)));
+    hipEvent_t e0, e1;
+    CHECK(hipEventCreate(&e0));
+    CHECK(hipEventCreate(&e1));
+    printf("{\"cus\": %d, \"nominal_clock_hz\": %.3e, \"rates\": {", cus, clk);
+    bool first = true;
+    auto run = [&](const char *name, auto launch, double lane_ops) -> int {
+        launch();
+        CHECK(hipDeviceSynchronize());
+        CHECK(hipEventRecord(e0));
+        launch();
+        CHECK(hipEventRecord(e1));
+        CHECK(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        CHECK(hipEventElapsedTime(&ms, e0, e1));
+        const double r = lane_ops / (ms * 1e-3);
+        printf("%s\"%s\": {\"lane_ops_per_s\": %.4e, \"per_clk_per_cu\": %.2f, \"ms\": %.3f}",
+               first ? "" : ", ", name, r, r / cus / clk, ms);
+        first = false;
+        return 0;
+    };
+    const int it = 20000;
+    const double nv = (double)blocks * threads * it * 32;
+    if (run("fma_f32", [&] { hipLaunchKernelGGL(k_f32<OP_FMA>, dim3(blocks), dim3(threads), 0, 0, out, it, 0.999f, 1e-3f); }, nv)) return 1;
+    if (run("mul_f32", [&] { hipLaunchKernelGGL(k_f32<OP_MUL>, dim3(blocks), dim3(threads), 0, 0, out, it, 0.999f, 1e-3f); }, nv)) return 1;
+    if (run("exp2_f32", [&] { hipLaunchKernelGGL(k_f32<OP_EXP>, dim3(blocks), dim3(threads), 0, 0, out, it / 4, 0.f, 0.f); }, nv / 4)) return 1;
+    if (run("rcp_f32", [&] { hipLaunchKernelGGL(k_f32<OP_RCP>, dim3(blocks), dim3(threads), 0, 0, out, it / 4, 0.f, 0.f); }, nv / 4)) return 1;
+    if (run("sqrt_f32", [&] { hipLaunchKernelGGL(k_f32<OP_SQRT>, dim3(blocks), dim3(threads), 0, 0, out, it / 4, 0.f, 0.f); }, nv / 4)) return 1;
+    if (run("fma_f64", [&] { hipLaunchKernelGGL(k_f64, dim3(blocks), dim3(threads), 0, 0, outd, it, 0.999, 1e-3); }, nv)) return 1;
+    const int li = 2000;
+    const double nl = (double)blocks * threads * li * 8;
+    if (run("lds_add_u64_random", [&] { hipLaunchKernelGGL((k_lds<unsigned long long, false>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
+    if (run("lds_add_u32_random", [&] { hipLaunchKernelGGL((k_lds<unsigned int, false>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
+    if (run("lds_read_b32_random", [&] { hipLaunchKernelGGL((k_lds<unsigned int, true>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
+    printf("}}\n");
+    CHECK(hipFree(out));
+    CHECK(hipFree(outd));
+    CHECK(hipFree(outl));
+    return 0;
+}

@@ -14,9 +14,9 @@ rate, lowest first,
 
 Every step runs in libsbp.so through the C-ABI; this module only sequences the
 calls, decides convergence from the (host-copied) loss, logs, and writes /
-reads checkpoints.  Readings of what the paper leaves open (stage structure,
-convergence rule, learning rates, per-stage Adam restart) are listed in
-DESIGN.md.
+reads checkpoints.  The stage structure, convergence rule, learning rates and
+per-stage Adam restart are readings of what the paper leaves open, not values
+it prints.
 """
 from __future__ import annotations
 
