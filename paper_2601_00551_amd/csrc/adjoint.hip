@@ -173,8 +173,14 @@ __device__ inline void adj_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx,
 // partial sums to part[(slice * NF + field) * pstride + ball] (NF = 5, or 1
 // for the p0-only variant) and k_adj_reduce adds the slices in a fixed order,
 // so results do not depend on scheduling.
+// Occupancy target of the launch bounds: the FP32 kernel is capped at 128
+// VGPRs (four waves per SIMD); the FP64 twin, a correctness path, gets the
+// registers it needs instead of spilling.
+template <typename R> struct AdjMinBlocks { static constexpr int v = 4; };
+template <> struct AdjMinBlocks<double> { static constexpr int v = 2; };
+
 template <typename R, int PROF, int DIR, bool FULL>
-__global__ __launch_bounds__(512, 4) void k_adjoint(ArrayP<R> arr, BallsP<R> balls,
+__global__ __launch_bounds__(512, AdjMinBlocks<R>::v) void k_adjoint(ArrayP<R> arr, BallsP<R> balls,
                                                  const int64_t *__restrict__ ball_off, int F,
                                                  int ds, int TT, int bpt, int nsl, int dsl,
                                                  Level lc, const R *__restrict__ v, R vscale,

@@ -98,6 +98,7 @@ __device__ inline BallK<R, PROF> load_ball(R x, R y, R z, R p, R araw, const Lev
         b.w = a;
         b.q0 = a * a;
         b.ampk = R(-0.5) * p;
+        b.h = R(1);
     } else {
         b.w = (R)(lc.K_d * (double)a);
         b.q0 = R(-1.4426950408889634) / (R(2) * a * a);

@@ -1,9 +1,10 @@
 // Issue-rate microbenchmark for the roofline of the VALU-bound kernels:
 // lane-operations per second on this device for FP32 FMA and multiply, the
 // FP32 transcendentals the physics kernels use (exp2, reciprocal, square
-// root), FP64 FMA, and LDS 64/32-bit integer atomic adds and 32-bit reads at
-// pseudo-random addresses inside one 4096-entry row (the access pattern of
-// the forward's accumulation and of the adjoint's staged rows).
+// root), FP64 FMA, and LDS 64/32-bit integer atomic adds and 32/64/128-bit
+// reads at pseudo-random addresses inside one row (the access pattern of the
+// forward's accumulation and of the adjoint's staged rows; wide reads count
+// every dword as one lane-operation).
 //
 // Every lane runs eight independent chains so that latency is hidden; the
 // grid fills every CU with eight 256-thread workgroups.  Output: one JSON
@@ -93,6 +94,28 @@ __global__ __launch_bounds__(256) void k_lds(unsigned long long *out, int iters)
     atomicAdd(out, s);
 }
 
+// Aligned random reads of W dwords per lane (the row holds 4096 dwords).
+template <int W>
+__global__ __launch_bounds__(256) void k_lds_wide(unsigned long long *out, int iters) {
+    typedef unsigned int vec __attribute__((ext_vector_type(W)));
+    __shared__ vec row[4096 / W];
+    for (int i = threadIdx.x; i < 4096 / W; i += blockDim.x) row[i] = (vec)(unsigned)i;
+    __syncthreads();
+    uint32_t h = (blockIdx.x * 256u + threadIdx.x) * 2654435761u + 12345u;
+    vec acc = (vec)0u;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            h = h * 1664525u + 1013904223u;
+            acc += row[(h >> 16) & (4096u / W - 1u)];
+        }
+    }
+    unsigned long long s = 0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) s += acc[k];
+    atomicAdd(out, s);
+}
+
 int main() {
     hipDeviceProp_t prop;
     CHECK(hipGetDeviceProperties(&prop, 0));
@@ -138,6 +161,8 @@ int main() {
     if (run("lds_add_u64_random", [&] { hipLaunchKernelGGL((k_lds<unsigned long long, false>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_u32_random", [&] { hipLaunchKernelGGL((k_lds<unsigned int, false>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_read_b32_random", [&] { hipLaunchKernelGGL((k_lds<unsigned int, true>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
+    if (run("lds_read_b64_random", [&] { hipLaunchKernelGGL(k_lds_wide<2>, dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl * 2)) return 1;
+    if (run("lds_read_b128_random", [&] { hipLaunchKernelGGL(k_lds_wide<4>, dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl * 4)) return 1;
     printf("}}\n");
     CHECK(hipFree(out));
     CHECK(hipFree(outd));
