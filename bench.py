@@ -33,6 +33,7 @@ OPS_ADJ_EDGE = 11        # per edge: u, u^2 k, exp, support select, three weight
 OPS_ADJ_PAIR = 26        # per pair: S0..S2, dL/dp0, dL/da, radial and directivity terms
 OPS_FLT_EDGE = 8         # per edge (p0 only): u, u^2 k, exp, select, one weighted sum
 OPS_FLT_PAIR = 3
+OPS_FWD_EDGE_UNIFORM = 7  # per edge, UNIFORM profile: u, u^2, a^2 - u^2, clamp, scale, difference, accumulate
 VALU_PEAK = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock = 3.93e13 lane-ops/s
 
 
@@ -333,7 +334,7 @@ def suite(args):
     tf, tb = fwd_adj(A, st, model, y)
     B, D = len(wl.init["x"]), len(wl.array["qx"])
     E = edges_per_pair(0.15, c * wl.dt)
-    ops_f = B * D * (OPS_GEOMETRY + E * OPS_FWD_EDGE)
+    ops_f = B * D * (OPS_GEOMETRY + E * OPS_FWD_EDGE_UNIFORM)
     print(json.dumps({"workload": wl.name.replace("uniform2M", "uniform2M-uniformballs"), "profile": "uniform",
                       "forward_ms": tf, "adjoint_ms": tb, "fwd_adj_pairs_per_s": B * D / ((tf + tb) * 1e-3),
                       "forward_frac_alu": ops_f / (tf * 1e-3) / VALU_PEAK}), flush=True)
