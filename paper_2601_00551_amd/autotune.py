@@ -62,10 +62,10 @@ def apply_cached(ctx, path: str, model, D: int, B: int) -> dict:
     """Install the cached launch shape for this workload; returns what is in use."""
     cache = load(path)
     entry = lookup(cache, shape_key(_arch(), model, D, B)) if cache else None
+    t = dict(DEFAULTS)          # no entry for this profile: the defaults, not the last workload's shape
     if entry:
-        t = dict(DEFAULTS)
         t.update({k: int(v) for k, v in entry.items() if k in DEFAULTS})
-        ctx.tuning = t
+    ctx.tuning = t
     return ctx.tuning
 
 
@@ -144,6 +144,7 @@ def main(argv=None):
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json"))
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--levels", default="1")
+    ap.add_argument("--profile", choices=("gauss", "uniform"), default="gauss")
     args = ap.parse_args(argv)
     dev = torch.device("cuda:0")
     ctx = api.Context(0)
@@ -157,7 +158,8 @@ def main(argv=None):
     Bt = {k: torch.as_tensor(v, device=dev) for k, v in balls.items()}
     rng = np.random.default_rng(7)
     for f in (int(x) for x in args.levels.split(",")):
-        model = api.Model(c=1.5, dt=wl.dt, T=wl.T // f, f=f, profile=api.PROFILE_GAUSS,
+        model = api.Model(c=1.5, dt=wl.dt, T=wl.T // f, f=f,
+                          profile=api.PROFILE_GAUSS if args.profile == "gauss" else api.PROFILE_UNIFORM,
                           directivity=api.DIR_COS)
         v = torch.as_tensor(rng.normal(size=(1, len(wl.array["qx"]), model.T)).astype(np.float32), device=dev)
         res = tune(ctx, A, Bt, model, v, reps=args.reps, path=args.out, log=lambda s: print(s, flush=True))
