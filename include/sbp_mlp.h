@@ -60,7 +60,11 @@ int sbp_mlp_loss(sbp_ctx *ctx, const float *out, const float *label_grow, const 
 
 /* Backpropagation through the network: grad (FP32, SBP_MLP_NPARAM, overwritten)
  * = d loss / d params, from the activations of sbp_mlp_forward and the output
- * gradient of sbp_mlp_loss.  dacts is a workspace of 3 * 256 * Mp BF16. */
+ * gradient of sbp_mlp_loss.  dacts is a workspace of 3 * 256 * Mp BF16.  The
+ * weight gradients are summed per slice of rows into the context's scratch
+ * (up to 256 x 257 x 256 floats, grown on demand) and the slices added in a
+ * fixed order, so the result does not depend on scheduling.
+ * Errors: SBP_E_ARG (NULL, M < 1), SBP_E_NOMEM (scratch), SBP_E_HIP. */
 int sbp_mlp_backward(sbp_ctx *ctx, const uint16_t *work, const uint16_t *acts, const float *dout,
                      const uint16_t *dout_t, int64_t M, uint16_t *dacts, float *grad,
                      void *stream);

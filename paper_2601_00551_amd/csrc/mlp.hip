@@ -124,6 +124,7 @@ __device__ inline void hidden_layer(const __bf16 *__restrict__ A, int lda, const
                 O[r * kLd + col] = h;
                 h4[i] = h;
             }
+            // transposed copy for the weight gradients (four rows of one column)
             if (acts_t)
                 *reinterpret_cast<bf16x4 *>(acts_t + (int64_t)col * Mp + m_base + rt * 16 + (l >> 4) * 4) = h4;
         }
@@ -226,13 +227,50 @@ __global__ void k_mlp_loss_final(const double *__restrict__ partial, int n, int6
 
 // ----------------------------------------------------------- backward data --
 
+// Writes the workgroup's 64 x 256 row-major LDS tile O transposed into
+// dst_t[col][Mp] (rows m_base .. m_base + 63): thread t owns column t and
+// stores its 64 values as eight 16-byte vectors, 128 contiguous bytes per
+// column (lane-scattered 8-byte stores of the MFMA layout waste most of each
+// memory transaction).  If h_t is given, a value is kept only where the
+// saved activation h_t[col][m] is positive (the ReLU derivative), and O is
+// updated with the masked values.  Call between barriers.  The forward keeps
+// the MFMA-layout stores: measured faster there, where they overlap the next
+// layer's loads; the backward's masked read-modify-write is faster this way.
+__device__ inline void store_tile_t(__bf16 *__restrict__ O, const __bf16 *__restrict__ h_t,
+                                    __bf16 *__restrict__ dst_t, int64_t Mp, int64_t m_base) {
+    const int col = threadIdx.x;
+    __bf16 *dst = dst_t + (int64_t)col * Mp + m_base;
+    const __bf16 *hp = h_t ? h_t + (int64_t)col * Mp + m_base : nullptr;
+    bf16x8 h[kTM / 8];
+    if (hp) {
+#pragma unroll
+        for (int v = 0; v < kTM / 8; ++v) h[v] = frag(hp + v * 8);   // all issued before any store
+    }
+#pragma unroll
+    for (int v = 0; v < kTM / 8; ++v) {
+        bf16x8 d;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int r = v * 8 + e;
+            __bf16 x = O[r * kLd + col];
+            if (hp) {
+                x = (float)h[v][e] > 0.0f ? x : (__bf16)0.0f;
+                O[r * kLd + col] = x;
+            }
+            d[e] = x;
+        }
+        *reinterpret_cast<bf16x8 *>(dst + v * 8) = d;
+    }
+}
+
 // dH_l = (dH_{l+1} W_{l+1}^T) * 1[H_l > 0] for the workgroup's 64 rows; A is
 // the row-major dH_{l+1} tile in LDS, Wr the row-major W_{l+1} ([k_l][k_{l+1}],
 // i.e. the B operand with k_{l+1} contiguous).  Wave w owns columns
-// [64 w, 64 w + 64) of dH_l, as in the forward's hidden layers.
+// [64 w, 64 w + 64) of dH_l, as in the forward's hidden layers.  This writes
+// the unmasked product (BF16) into the LDS tile O; store_tile_t then applies
+// the ReLU mask and writes dH_l transposed.
 __device__ inline void back_layer(const __bf16 *__restrict__ A, const __bf16 *__restrict__ Wr,
-                                  const __bf16 *__restrict__ h_t, __bf16 *__restrict__ O,
-                                  __bf16 *__restrict__ d_t, int64_t Mp, int64_t m_base) {
+                                  __bf16 *__restrict__ O) {
     const int l = threadIdx.x & 63;
     const int c0 = (threadIdx.x >> 6) * 64;
     floatx4 acc[4][4];
@@ -256,18 +294,9 @@ __device__ inline void back_layer(const __bf16 *__restrict__ A, const __bf16 *__
     for (int ct = 0; ct < 4; ++ct) {
         const int col = c0 + ct * 16 + (l & 15);
 #pragma unroll
-        for (int rt = 0; rt < 4; ++rt) {
-            const int64_t m0 = m_base + rt * 16 + (l >> 4) * 4;
-            const bf16x4 h4 = *reinterpret_cast<const bf16x4 *>(h_t + (int64_t)col * Mp + m0);
-            bf16x4 d4;
+        for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const __bf16 d = (float)h4[i] > 0.0f ? (__bf16)acc[rt][ct][i] : (__bf16)0.0f;
-                if (O) O[(rt * 16 + (l >> 4) * 4 + i) * kLd + col] = d;
-                d4[i] = d;
-            }
-            *reinterpret_cast<bf16x4 *>(d_t + (int64_t)col * Mp + m0) = d4;
-        }
+            for (int i = 0; i < 4; ++i) O[(rt * 16 + (l >> 4) * 4 + i) * kLd + col] = (__bf16)acc[rt][ct][i];
     }
 }
 
@@ -277,78 +306,143 @@ __global__ __launch_bounds__(256, 2) void k_mlp_bwd(const __bf16 *__restrict__ W
     __shared__ __align__(16) __bf16 s_a[kTM * kLd];
     __shared__ __align__(16) __bf16 s_b[kTM * kLd];
     const int tid = threadIdx.x;
-    const int wrow = (tid >> 6) * 16;
     const int64_t m_base = (int64_t)blockIdx.x * kTM;
     const __bf16 *h1 = acts + (int64_t)kIn * Mp;
     const __bf16 *h2 = h1 + (int64_t)kH * Mp;
     const __bf16 *h3 = h2 + (int64_t)kH * Mp;
     __bf16 *d1 = dacts, *d2 = dacts + (int64_t)kH * Mp, *d3 = d2 + (int64_t)kH * Mp;
-    // dH3 = dout W4^T * 1[H3 > 0]: an inner dimension of 2, plain FMAs
+    // dH3 = dout W4^T * 1[H3 > 0]: an inner dimension of 2, plain FMAs.  Thread
+    // t owns column t: its 64 saved activations are read as eight 16-byte
+    // vectors issued together (one memory latency, not 64), the tile's output
+    // gradients come from LDS.
+    __shared__ float s_dout[kTM * 2];
+    if (tid < kTM * 2) s_dout[tid] = dout[m_base * 2 + tid];
     const __bf16 *w4r = W + wW4r;
-    for (int i = tid; i < kTM * kH; i += blockDim.x) {
-        const int k = i / kTM, r = i % kTM;      // rows fastest: the transposed arrays are read contiguously
-        const int64_t m = m_base + r;
-        const float g = dout[m * 2] * (float)w4r[k * kOP] + dout[m * 2 + 1] * (float)w4r[k * kOP + 1];
-        const __bf16 d = (float)h3[(int64_t)k * Mp + m] > 0.0f ? (__bf16)g : (__bf16)0.0f;
-        s_a[r * kLd + k] = d;
-        d3[(int64_t)k * Mp + m] = d;
+    {
+        const int k = tid;
+        const float w0 = (float)w4r[k * kOP], w1 = (float)w4r[k * kOP + 1];
+        const __bf16 *hk = h3 + (int64_t)k * Mp + m_base;
+        __bf16 *dk = d3 + (int64_t)k * Mp + m_base;
+        bf16x8 h[kTM / 8];
+#pragma unroll
+        for (int v = 0; v < kTM / 8; ++v) h[v] = frag(hk + v * 8);
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < kTM / 8; ++v) {
+            bf16x8 dv;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int r = v * 8 + e;
+                const float g = s_dout[2 * r] * w0 + s_dout[2 * r + 1] * w1;
+                const __bf16 d = (float)h[v][e] > 0.0f ? (__bf16)g : (__bf16)0.0f;
+                s_a[r * kLd + k] = d;
+                dv[e] = d;
+            }
+            *reinterpret_cast<bf16x8 *>(dk + v * 8) = dv;
+        }
     }
     __syncthreads();
-    back_layer(s_a, W + wW3r, h2, s_b, d2, Mp, m_base);
+    back_layer(s_a, W + wW3r, s_b);
     __syncthreads();
-    back_layer(s_b, W + wW2r, h1, nullptr, d1, Mp, m_base);
+    store_tile_t(s_b, h2, d2, Mp, m_base);
+    __syncthreads();
+    back_layer(s_b, W + wW2r, s_a);
+    __syncthreads();
+    store_tile_t(s_a, h1, d1, Mp, m_base);
 }
 
 // ------------------------------------------------------- weight gradients --
 
-// G[k][n] (row-major, ldg) += sum over rows m in this block's slice of
-// At[k][m] * Bt[n][m]   (At: [K][Mp], Bt: [N][Mp], BF16, m-contiguous).
-// Block = 4 waves on a 64 x 64 tile of G (4 C tiles per wave); grid.z splits m.
-__global__ __launch_bounds__(256) void k_mlp_wgrad(const __bf16 *__restrict__ At, const __bf16 *__restrict__ Bt,
-                                                   int K, int N, int64_t Mp, int64_t m_per,
-                                                   float *__restrict__ G, int ldg) {
+// Partial weight (and bias) gradients of one slice of rows m:
+//   part[s][k][n] = sum over m in slice s of At[k][m] * Bt[n][m]   (k < K, n < NP)
+//   part[s][K][n] = sum over m in slice s of Bt[n][m]              (bias, if BIAS)
+// At: [K][Mp], Bt: [NP][Mp] (BF16, m-contiguous, NP a multiple of 16).  One
+// workgroup takes the whole K x NP block for its slice, so At and Bt are read
+// from memory once per call; wave w owns a WK x WN sub-block (waves laid out
+// K/WK by NP/WN) and per 32-wide m-step loads WK/16 + WN/16 fragments for
+// (WK/16)(WN/16) matrix-core products.  The bias sums ride along as products
+// of a ones fragment with the B fragments, in the waves that own k = 0.
+// Slices are added in a fixed order by k_mlp_wgrad_reduce (no atomics:
+// gradients are reproducible).
+template <int WK, int WN, bool BIAS>
+__global__ __launch_bounds__(512) void k_mlp_wgrad(const __bf16 *__restrict__ At,
+                                                   const __bf16 *__restrict__ Bt, int K, int NP,
+                                                   int64_t Mp, int64_t m_per,
+                                                   float *__restrict__ part) {
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int kb = blockIdx.x * 64 + w * 16;
-    if (kb >= K) return;
-    const int64_t m0 = (int64_t)blockIdx.z * m_per;
+    const int nwn = NP / WN;
+    const int k0 = (w / nwn) * WK, n0 = (w % nwn) * WN;
+    if (k0 >= K) return;
+    const int64_t m0 = (int64_t)blockIdx.x * m_per;
     const int64_t m1 = min(m0 + m_per, Mp);
-    floatx4 acc[4];
+    floatx4 acc[WK / 16][WN / 16];
+    floatx4 accb[WN / 16];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int i = 0; i < WK / 16; ++i)
+#pragma unroll
+        for (int j = 0; j < WN / 16; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < WN / 16; ++j) accb[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 ones;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) ones[e] = (__bf16)1.0f;
+    const bool bias_wave = BIAS && k0 == 0;
+    const __bf16 *pa = At + (int64_t)(k0 + (l & 15)) * Mp + (l >> 4) * 8;
+    const __bf16 *pb = Bt + (int64_t)(n0 + (l & 15)) * Mp + (l >> 4) * 8;
     for (int64_t m = m0; m < m1; m += 32) {
-        const bf16x8 a = frag(At + (int64_t)(kb + (l & 15)) * Mp + m + (l >> 4) * 8);
+        bf16x8 a[WK / 16], b[WN / 16];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int nb = blockIdx.y * 64 + t * 16;
-            if (nb >= N) break;
-            const bf16x8 b = frag(Bt + (int64_t)(nb + (l & 15)) * Mp + m + (l >> 4) * 8);
-            acc[t] = mfma(a, b, acc[t]);
+        for (int i = 0; i < WK / 16; ++i) a[i] = frag(pa + (int64_t)i * 16 * Mp + m);
+#pragma unroll
+        for (int j = 0; j < WN / 16; ++j) b[j] = frag(pb + (int64_t)j * 16 * Mp + m);
+#pragma unroll
+        for (int i = 0; i < WK / 16; ++i)
+#pragma unroll
+            for (int j = 0; j < WN / 16; ++j) acc[i][j] = mfma(a[i], b[j], acc[i][j]);
+        if (bias_wave) {
+#pragma unroll
+            for (int j = 0; j < WN / 16; ++j) accb[j] = mfma(ones, b[j], accb[j]);
         }
     }
+    const int rows = K + (BIAS ? 1 : 0);
+    float *ps = part + (int64_t)blockIdx.x * rows * NP;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int n = blockIdx.y * 64 + t * 16 + (l & 15);
-        if (n >= N || n >= ldg) continue;
+    for (int i = 0; i < WK / 16; ++i)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int k = kb + (l >> 4) * 4 + i;
-            atomicAdd(G + (int64_t)k * ldg + n, acc[t][i]);
-        }
+        for (int j = 0; j < WN / 16; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                ps[(int64_t)(k0 + i * 16 + (l >> 4) * 4 + r) * NP + n0 + j * 16 + (l & 15)] = acc[i][j][r];
+    if (bias_wave && (l >> 4) == 0) {
+        // every row of the ones product holds the column sums; row 0 is lane l < 16
+#pragma unroll
+        for (int j = 0; j < WN / 16; ++j) ps[(int64_t)K * NP + n0 + j * 16 + l] = accb[j][0];
     }
 }
 
-// bias gradient: g[n] += sum of Bt[n][m] over this block's slice of m
-// (grid: n x slices; g is zeroed beforehand)
-__global__ void k_mlp_bgrad(const __bf16 *__restrict__ Bt, int64_t Mp, int64_t m_per, float *__restrict__ g) {
-    __shared__ float s_red[4];
-    float acc = 0.0f;
-    const __bf16 *row = Bt + (int64_t)blockIdx.x * Mp;
-    const int64_t m0 = (int64_t)blockIdx.y * m_per, m1 = min(m0 + m_per, Mp);
-    for (int64_t m = m0 + threadIdx.x; m < m1; m += blockDim.x) acc += (float)row[m];
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
-    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) atomicAdd(g + blockIdx.x, s_red[0] + s_red[1] + s_red[2] + s_red[3]);
+// G[k][n] = sum over slices of part[s][k][n] for k < K, n < N (G row stride
+// ldg), slice 0 first; the bias row k = K, if present, goes to gb[n].
+__global__ void k_mlp_wgrad_reduce(const float *__restrict__ part, int nsl, int rows, int NP, int K,
+                                   int N, float *__restrict__ G, int ldg, float *__restrict__ gb) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * NP) return;
+    const int k = i / NP, n = i % NP;
+    if (n >= N) return;
+    // eight interleaved running sums (slices sl = j mod 8), added in a fixed
+    // order: more loads in flight than one dependent chain
+    const int64_t stride = (int64_t)rows * NP;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int sl = 0;
+    for (; sl + 8 <= nsl; sl += 8) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[j] += part[(int64_t)(sl + j) * stride + i];
+    }
+    for (int j = 0; sl < nsl; ++sl, ++j) acc[j] += part[(int64_t)sl * stride + i];
+    const float s = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    if (k < K)
+        G[(int64_t)k * ldg + n] = s;
+    else if (gb)
+        gb[n] = s;
 }
 
 // bias gradient of the output layer from the FP32 output gradient [Mp][2]
@@ -374,16 +468,36 @@ __global__ void k_mlp_bgrad_out(const float *__restrict__ dout, int64_t Mp, int6
                                        s_red[threadIdx.x][3]);
 }
 
-static int launch_wgrad(const __bf16 *At, const __bf16 *Bt, int K, int N, int64_t Mp, float *G,
-                        int ldg, hipStream_t st) {
-    int64_t splits = Mp / 4096;
-    if (splits < 1) splits = 1;
-    if (splits > 64) splits = 64;
-    int64_t m_per = (Mp + splits - 1) / splits;
-    m_per = (m_per + 31) / 32 * 32;
-    splits = (Mp + m_per - 1) / m_per;
-    dim3 grid((K + 63) / 64, (N + 63) / 64, (unsigned)splits);
-    hipLaunchKernelGGL(k_mlp_wgrad, grid, dim3(256), 0, st, At, Bt, K, N, Mp, m_per, G, ldg);
+// Rows per slice of the weight gradients: at least 1024 (so that a slice's
+// matrix-core work outweighs writing its partial block), and no more slices
+// than CUs (the partial-sum buffer stays below 256 x (K + 1) x NP floats).
+static int64_t wgrad_slices(const Ctx *c, int64_t Mp, int64_t *m_per) {
+    int64_t cus = c->num_cus > 0 ? c->num_cus : 256;
+    if (cus > 256) cus = 256;
+    int64_t mp = (Mp + cus - 1) / cus;
+    mp = (mp + 31) / 32 * 32;
+    if (mp < 1024) mp = 1024;
+    *m_per = mp;
+    return (Mp + mp - 1) / mp;
+}
+
+template <int WK, int WN, bool BIAS>
+static int launch_wgrad(Ctx *c, const __bf16 *At, const __bf16 *Bt, int K, int NP, int N, int64_t Mp,
+                        float *G, int ldg, float *gb, hipStream_t st) {
+    if ((K / WK) * (NP / WN) > 8 || K % WK || NP % WN) return fail(SBP_E_ARG, "wgrad tiling");
+    int64_t m_per = 0;
+    const int64_t nsl = wgrad_slices(c, Mp, &m_per);
+    const int rows = K + (BIAS ? 1 : 0);
+    const size_t bytes = (size_t)nsl * rows * NP * sizeof(float);
+    int rc = ensure_scratch(c, bytes);
+    if (rc) return rc;
+    float *part = (float *)c->scratch;
+    hipLaunchKernelGGL((k_mlp_wgrad<WK, WN, BIAS>), dim3((unsigned)nsl), dim3(512), 0, st, At, Bt, K, NP,
+                       Mp, m_per, part);
+    SBP_HIP(hipGetLastError());
+    const int n = rows * NP;
+    hipLaunchKernelGGL(k_mlp_wgrad_reduce, dim3((n + 255) / 256), dim3(256), 0, st, (const float *)part,
+                       (int)nsl, rows, NP, K, N, G, ldg, gb);
     SBP_HIP(hipGetLastError());
     return SBP_OK;
 }
@@ -474,17 +588,18 @@ int sbp_mlp_backward(sbp_ctx *ctx, const uint16_t *work, const uint16_t *acts, c
     const __bf16 *x_t = A, *h1 = A + (int64_t)kIn * Mp, *h2 = h1 + (int64_t)kH * Mp,
                  *h3 = h2 + (int64_t)kH * Mp;
     const __bf16 *d1 = dA, *d2 = dA + (int64_t)kH * Mp, *d3 = d2 + (int64_t)kH * Mp;
-    if ((rc = launch_wgrad(x_t, d1, kIn, kH, Mp, grad + oW1, kH, st))) return rc;
-    if ((rc = launch_wgrad(h1, d2, kH, kH, Mp, grad + oW2, kH, st))) return rc;
-    if ((rc = launch_wgrad(h2, d3, kH, kH, Mp, grad + oW3, kH, st))) return rc;
-    if ((rc = launch_wgrad(h3, (const __bf16 *)dout_t, kH, SBP_MLP_OUT, Mp, grad + oW4, SBP_MLP_OUT, st)))
+    // weight gradients and, folded into the same pass, the hidden-layer bias gradients
+    Ctx *c = &ctx->c;
+    if ((rc = launch_wgrad<32, 32, true>(c, x_t, d1, kIn, kH, kH, Mp, grad + oW1, kH, grad + oB1, st))) return rc;
+    if ((rc = launch_wgrad<64, 128, true>(c, h1, d2, kH, kH, kH, Mp, grad + oW2, kH, grad + oB2, st))) return rc;
+    if ((rc = launch_wgrad<64, 128, true>(c, h2, d3, kH, kH, kH, Mp, grad + oW3, kH, grad + oB3, st))) return rc;
+    if ((rc = launch_wgrad<32, 16, false>(c, h3, (const __bf16 *)dout_t, kH, kOP, SBP_MLP_OUT, Mp, grad + oW4,
+                                          SBP_MLP_OUT, nullptr, st)))
         return rc;
-    // bias gradients: slices of 8192 rows, summed with FP32 atomics into the zeroed grad
+    // output-layer bias gradient from the FP32 output gradient: slices of 8192 rows,
+    // FP32 atomics into the zeroed grad
     const int64_t m_per = 8192;
     const unsigned nsl = (unsigned)((Mp + m_per - 1) / m_per);
-    hipLaunchKernelGGL(k_mlp_bgrad, dim3(kH, nsl), dim3(256), 0, st, d1, Mp, m_per, grad + oB1);
-    hipLaunchKernelGGL(k_mlp_bgrad, dim3(kH, nsl), dim3(256), 0, st, d2, Mp, m_per, grad + oB2);
-    hipLaunchKernelGGL(k_mlp_bgrad, dim3(kH, nsl), dim3(256), 0, st, d3, Mp, m_per, grad + oB3);
     hipLaunchKernelGGL(k_mlp_bgrad_out, dim3(nsl), dim3(256), 0, st, dout, Mp, m_per, grad + oB4);
     SBP_HIP(hipGetLastError());
     return SBP_OK;

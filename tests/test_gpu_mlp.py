@@ -78,7 +78,7 @@ def test_forward_exact_abs_network(ctx):
     np.testing.assert_array_equal(out[:, 1], np.maximum(X, 0).sum(1) - 2.0)
 
 
-@pytest.mark.parametrize("M", [64, 777, 5000])
+@pytest.mark.parametrize("M", [64, 777, 5000, 70000])   # 1, 1, 5 and 69 slices of rows
 def test_loss_and_backward_match_oracle(ctx, M):
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(200 + M)
