@@ -79,6 +79,34 @@ constexpr int kFwdBlock = 8;
 template <typename R> struct FwdBlocks { static constexpr bool on = true; };
 template <> struct FwdBlocks<double> { static constexpr bool on = false; };
 
+// N consecutive GAUSS bins from edge m (u_m = ub): the right edge of bin k
+// (k = 1..N) has shape value e_k = 2^(q0 (ub - k c)^2), evaluated as
+// 2^(X0 + k (X1 + k X2)); bin k adds amp (e_{k-1} - e_k), e_0 = prev.
+template <typename R, int N>
+__device__ inline void gauss_bins(typename FwdAcc<R>::T *p, R ub, R q0, R X2, R Y1, R amp, R &prev) {
+    const R X0 = q0 * ub * ub;
+    const R X1 = Y1 * ub;
+#pragma unroll
+    for (int k = 1; k <= N; ++k) {
+        const R e = ex2(fma(R(k), fma(R(k), X2, X1), X0));
+        FwdAcc<R>::add(p + (k - 1), amp * (prev - e));
+        prev = e;
+    }
+}
+
+// N consecutive UNIFORM bins from edge m: shape value a^2 - u^2 at the edges,
+// bins past the first linear in k (B0 + B1 k).
+template <typename R, int N>
+__device__ inline void uniform_bins(typename FwdAcc<R>::T *p, R ub, R q0, R c, R amp, R B1, R &prev) {
+    const R u1 = ub - c;
+    FwdAcc<R>::add(p, amp * (prev - (q0 - u1 * u1)));
+    const R B0 = amp * fma(R(-2) * c, ub, -(c * c));
+#pragma unroll
+    for (int k = 2; k <= N; ++k) FwdAcc<R>::add(p + (k - 1), fma(B1, R(k), B0));
+    const R ue = fma(R(-N), c, ub);
+    prev = q0 - ue * ue;
+}
+
 // Adds the pair's bins that fall in the time tile [tlo, thi) to row[n - tlo];
 // `scale` multiplies the bin values (the fixed-point quantum's inverse).
 template <typename R, int PROF, int DIR>
@@ -112,40 +140,48 @@ __device__ inline void fwd_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx,
             prev = first_out ? eK : ex2(u0 * u0 * b.q0);
         }
         if (FwdBlocks<R>::on) {
-            // blocks of kFwdBlock bins, the edge offsets k as constants:
-            // q0 (u_m - k c)^2 = X0 + k (X1 + k X2), u_m formed exactly per block
+            // blocks of kFwdBlock bins, then the remainder as blocks of 4, 2
+            // and 1 (a typical support leaves 7): the edge offsets k are
+            // constants, q0 (u_m - k c)^2 = X0 + k (X1 + k X2), u_m formed
+            // exactly per block
             const R X2 = b.q0 * c * c;
             const R Y1 = R(-2) * b.q0 * c;
-            for (; cnt >= kFwdBlock; cnt -= kFwdBlock, p += kFwdBlock, m += kFwdBlock) {
-                const R ub = (R)(g.s - (double)m * lc.cdt);
-                const R X0 = b.q0 * ub * ub;
-                const R X1 = Y1 * ub;
-#pragma unroll
-                for (int k = 1; k <= kFwdBlock; ++k) {
-                    const R e = ex2(fma(R(k), fma(R(k), X2, X1), X0));
-                    FwdAcc<R>::add(p + (k - 1), amp * (prev - e));
-                    prev = e;
-                }
+            for (; cnt >= kFwdBlock; cnt -= kFwdBlock, p += kFwdBlock, m += kFwdBlock)
+                gauss_bins<R, kFwdBlock>(p, (R)(g.s - (double)m * lc.cdt), b.q0, X2, Y1, amp, prev);
+            if (cnt & 4) {
+                gauss_bins<R, 4>(p, (R)(g.s - (double)m * lc.cdt), b.q0, X2, Y1, amp, prev);
+                p += 4;
+                m += 4;
             }
-        }
-        const R u0 = (R)(g.s - (double)m * lc.cdt);
-        R j = R(1);
-        // two bins per trip (no register copy of the carried edge value)
-        for (; cnt >= 2; cnt -= 2, p += 2, j += R(2)) {
-            const R u1 = fma(-j, c, u0);
-            const R u2 = u1 - c;
-            const R c1 = ex2(u1 * u1 * b.q0);
-            const R c2 = ex2(u2 * u2 * b.q0);
-            FwdAcc<R>::add(p, amp * (prev - c1));
-            FwdAcc<R>::add(p + 1, amp * (c1 - c2));
-            prev = c2;
-        }
-        if (cnt) {
-            const R u1 = fma(-j, c, u0);
-            const R c1 = ex2(u1 * u1 * b.q0);
-            FwdAcc<R>::add(p, amp * (prev - c1));
-            prev = c1;
-            ++p;
+            if (cnt & 2) {
+                gauss_bins<R, 2>(p, (R)(g.s - (double)m * lc.cdt), b.q0, X2, Y1, amp, prev);
+                p += 2;
+                m += 2;
+            }
+            if (cnt & 1) {
+                gauss_bins<R, 1>(p, (R)(g.s - (double)m * lc.cdt), b.q0, X2, Y1, amp, prev);
+                p += 1;
+            }
+        } else {
+            const R u0 = (R)(g.s - (double)m * lc.cdt);
+            R j = R(1);
+            // two bins per trip (no register copy of the carried edge value)
+            for (; cnt >= 2; cnt -= 2, p += 2, j += R(2)) {
+                const R u1 = fma(-j, c, u0);
+                const R u2 = u1 - c;
+                const R c1 = ex2(u1 * u1 * b.q0);
+                const R c2 = ex2(u2 * u2 * b.q0);
+                FwdAcc<R>::add(p, amp * (prev - c1));
+                FwdAcc<R>::add(p + 1, amp * (c1 - c2));
+                prev = c2;
+            }
+            if (cnt) {
+                const R u1 = fma(-j, c, u0);
+                const R c1 = ex2(u1 * u1 * b.q0);
+                FwdAcc<R>::add(p, amp * (prev - c1));
+                prev = c1;
+                ++p;
+            }
         }
         if (last_out) FwdAcc<R>::add(p, amp * (prev - eK));
     } else {
@@ -157,35 +193,43 @@ __device__ inline void fwd_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx,
         }
         if (FwdBlocks<R>::on) {
             // (u_m - k c)^2 - (u_m - (k-1) c)^2 = -2 u_m c + (2k - 1) c^2: past
-            // the block's first bin the bins are linear in k
+            // the block's first bin the bins are linear in k; remainder as
+            // blocks of 4, 2 and 1
             const R B1 = amp * R(2) * c * c;
-            for (; cnt >= kFwdBlock; cnt -= kFwdBlock, p += kFwdBlock, m += kFwdBlock) {
-                const R ub = (R)(g.s - (double)m * lc.cdt);
-                const R u1 = ub - c;
-                FwdAcc<R>::add(p, amp * (prev - (b.q0 - u1 * u1)));
-                const R B0 = amp * fma(R(-2) * c, ub, -(c * c));
-#pragma unroll
-                for (int k = 2; k <= kFwdBlock; ++k) FwdAcc<R>::add(p + (k - 1), fma(B1, R(k), B0));
-                const R ue = fma(R(-kFwdBlock), c, ub);
-                prev = b.q0 - ue * ue;
+            for (; cnt >= kFwdBlock; cnt -= kFwdBlock, p += kFwdBlock, m += kFwdBlock)
+                uniform_bins<R, kFwdBlock>(p, (R)(g.s - (double)m * lc.cdt), b.q0, c, amp, B1, prev);
+            if (cnt & 4) {
+                uniform_bins<R, 4>(p, (R)(g.s - (double)m * lc.cdt), b.q0, c, amp, B1, prev);
+                p += 4;
+                m += 4;
             }
-        }
-        R u = (R)(g.s - (double)m * lc.cdt);
-        for (; cnt >= 2; cnt -= 2, p += 2) {
-            const R u1 = u - c;
-            u = u1 - c;
-            const R c1 = b.q0 - u1 * u1;
-            const R c2 = b.q0 - u * u;
-            FwdAcc<R>::add(p, amp * (prev - c1));
-            FwdAcc<R>::add(p + 1, amp * (c1 - c2));
-            prev = c2;
-        }
-        if (cnt) {
-            u -= c;
-            const R c1 = b.q0 - u * u;
-            FwdAcc<R>::add(p, amp * (prev - c1));
-            prev = c1;
-            ++p;
+            if (cnt & 2) {
+                uniform_bins<R, 2>(p, (R)(g.s - (double)m * lc.cdt), b.q0, c, amp, B1, prev);
+                p += 2;
+                m += 2;
+            }
+            if (cnt & 1) {
+                uniform_bins<R, 1>(p, (R)(g.s - (double)m * lc.cdt), b.q0, c, amp, B1, prev);
+                p += 1;
+            }
+        } else {
+            R u = (R)(g.s - (double)m * lc.cdt);
+            for (; cnt >= 2; cnt -= 2, p += 2) {
+                const R u1 = u - c;
+                u = u1 - c;
+                const R c1 = b.q0 - u1 * u1;
+                const R c2 = b.q0 - u * u;
+                FwdAcc<R>::add(p, amp * (prev - c1));
+                FwdAcc<R>::add(p + 1, amp * (c1 - c2));
+                prev = c2;
+            }
+            if (cnt) {
+                u -= c;
+                const R c1 = b.q0 - u * u;
+                FwdAcc<R>::add(p, amp * (prev - c1));
+                prev = c1;
+                ++p;
+            }
         }
         if (last_out) FwdAcc<R>::add(p, amp * prev);
     }
