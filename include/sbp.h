@@ -215,6 +215,9 @@ int sbp_downsample(sbp_ctx *ctx, const float *y, int64_t R, int32_t T, int32_t f
  * value is rounded to a multiple of a per-call power-of-two quantum (at most
  * 2^-31 of the largest possible bin value) and the multiples are summed
  * exactly, so the result is bitwise reproducible however the work is split.
+ * The error is absolute: a ball whose bins are 10^k times smaller than the
+ * bound (max |p0| a over the call's balls, taken at the support edge) keeps
+ * about 31 - 3.3 k significant bits per bin.
  * The context's scratch holds 8 bytes per output sample during the call.
  * Errors: SBP_E_ARG, SBP_E_DOMAIN, SBP_E_HIP, SBP_E_NOMEM. */
 int sbp_simulate_signals(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *balls,
