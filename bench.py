@@ -248,13 +248,14 @@ def suite(args):
         cur = torch.cuda.current_stream(dev)
         launch = lambda: g.launch(stream=cur)
         launch()
-        # eager, graph, eager: the clock drifts under sustained load, so the
-        # eager figure is the mean of the two runs bracketing the graph's
-        t_e1 = _timed(eager, iters * reps)
-        t_graph = _timed(launch, reps) / iters
-        t_e2 = _timed(eager, iters * reps)
+        # the clock drifts under sustained load: alternate eager and graph
+        # runs three times and average the last two pairs, once it has settled
+        te, tg = [], []
+        for _ in range(3):
+            te.append(_timed(eager, iters * reps))
+            tg.append(_timed(launch, reps) / iters)
         g.close()
-        return 0.5 * (t_e1 + t_e2), t_graph
+        return 0.5 * (te[1] + te[2]), 0.5 * (tg[1] + tg[2])
 
     def filtered(A, init, model, y_k, off=None):
         n = len(init["x"])
