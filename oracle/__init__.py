@@ -164,6 +164,15 @@ def downsample(y, f: int) -> np.ndarray:
     return out / f
 
 
+def decimate(y, f: int) -> np.ndarray:
+    """Keep every f-th sample along the last axis, T_k = floor(T / f): the
+    pyramid of point-sampled records (the value at t0 + n f dt is sample n f
+    of the full-rate record)."""
+    y = _f64(y)
+    Tk = y.shape[-1] // f
+    return y[..., 0:Tk * f:f].copy()
+
+
 def residual_loss(y_sim, y_ref):
     """Loss L = sum (y_sim - y_ref)^2 (a sum, no 1/N) and its cotangent dL/dy = 2 e."""
     e = _f64(y_sim) - _f64(y_ref)

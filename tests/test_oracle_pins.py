@@ -266,6 +266,61 @@ def test_pyramid_identity(profile, f):
     assert np.max(np.abs(yd - yk)) <= 1e-15 * max(1.0, np.max(np.abs(y)))
 
 
+@pytest.mark.parametrize("f", [2, 4, 16])
+def test_point_pyramid_is_decimation(f):
+    """Point sampling: sample n f of Sim(dt, T) is taken at t0 + n f dt, the
+    time of sample n of Sim(f dt, floor(T/f)), so Decimate_f pairs with POINT
+    as Downsample_f pairs with BIN (equal up to the rounding of the sample
+    times)."""
+    rng = np.random.default_rng(19)
+    b, arr = random_setup(rng, nb=5, nd=4)
+    T = 1003
+    tm1 = Time(T=T, f=1, t0=0.3, profile=GAUSS, directivity=COS, sampling=POINT)
+    tmk = Time(T=T // f, f=f, t0=0.3, profile=GAUSS, directivity=COS, sampling=POINT)
+    y = oracle.simulate(b, arr, tm1)
+    yd = oracle.decimate(y, f)
+    yk = oracle.simulate(b, arr, tmk)
+    assert yd.shape == yk.shape == (4, T // f)
+    assert np.count_nonzero(yk) > 20
+    assert np.max(np.abs(yd - yk)) <= 1e-12 * np.max(np.abs(y))
+    # and by its definition: every f-th sample, starting at sample 0
+    np.testing.assert_array_equal(yd, np.stack([y[:, n * f] for n in range(T // f)], axis=1))
+
+
+def test_gauss_point_equals_kirchhoff_derivative():
+    """POINT under the truncated Gaussian: the value at tau_n is the Poisson-
+    Kirchhoff pressure d/dt (t M_ct[f]) at t = tau_n, here by a fourth-order
+    central difference of the quadrature (samples within a few steps of the
+    truncation edges, where the pressure jumps, are left out)."""
+    a, K, c, dt, p0 = 0.15, 5.0, 1.5, 0.025, 0.7
+    R = K * a
+    fprof = lambda s: p0 * math.exp(-s * s / (2 * a * a)) if s < R else 0.0
+    b = one_ball(0.1, -0.2, 0.05, p0, a)
+    q = np.array([[0.1, -0.2, 0.05 + 4.3717], [0.1 + 5.2209, -0.2, 0.05]])
+    arr = dets(q, [[0, 0, -1], [-1, 0, 0]])
+    T = 400
+    y = oracle.simulate(b, arr, Time(c=c, dt=dt, T=T, profile=GAUSS, directivity=OMNI, K=K,
+                                     sampling=POINT))
+    h = 2e-3
+    F = lambda t: t * spherical_mean(fprof, rho, c * t, R)
+    checked = 0
+    for d in range(2):
+        rho = float(np.linalg.norm(q[d] - np.array([0.1, -0.2, 0.05])))
+        edges = ((rho - R) / c, (rho + R) / c)
+        ref = np.zeros(T)
+        for n in range(T):
+            tau = n * dt
+            if not (edges[0] < tau < edges[1]):
+                continue
+            if min(abs(tau - e) for e in edges) < 3 * h:
+                ref[n] = y[d, n]      # left out: the difference straddles the jump
+                continue
+            ref[n] = (-F(tau + 2 * h) + 8 * F(tau + h) - 8 * F(tau - h) + F(tau - 2 * h)) / (12 * h)
+            checked += 1
+        assert np.max(np.abs(y[d] - ref)) <= 1e-6 * np.max(np.abs(ref)), d
+    assert checked > 70
+
+
 def test_near_field_and_empty():
     arr = dets([[0, 0, 0]], [[0, 0, 1]])
     tm = Time(T=100, profile=GAUSS, directivity=OMNI)
