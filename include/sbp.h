@@ -56,6 +56,8 @@ extern "C" {
 #define SBP_PROFILE_GAUSS 1   /* fhat(s) = exp(-s^2 / (2 a^2)) for |s| < K a (section 4.1) */
 #define SBP_DIR_OMNI 0        /* every transducer hears every direction equally */
 #define SBP_DIR_COS 1         /* trace scaled by max(0, n_hat . e_hat) */
+#define SBP_SAMPLING_BIN 0    /* sample n = mean pressure over [t0 + n dt_k, t0 + (n+1) dt_k) */
+#define SBP_SAMPLING_POINT 1  /* sample n = pressure at t0 + n dt_k (GAUSS only) */
 
 /* Gradient / update masks over the five ball parameters. */
 #define SBP_X 1u
@@ -87,7 +89,7 @@ typedef struct sbp_model {
     int32_t profile;   /* SBP_PROFILE_* */
     int32_t directivity; /* SBP_DIR_* */
     int32_t a_softplus;  /* 0 or 1 */
-    int32_t reserved;    /* must be 0 */
+    int32_t sampling;    /* SBP_SAMPLING_* (0, the paper's bin means, unless stated) */
 } sbp_model;
 
 /* Transducer array: D positions q and unit normals n (SoA, device, float). */
@@ -204,6 +206,14 @@ int sbp_ctx_get_tuning(const sbp_ctx *ctx, sbp_tuning *t);
 int sbp_downsample(sbp_ctx *ctx, const float *y, int64_t R, int32_t T, int32_t f,
                    float *y_out, void *stream);
 
+/* Decimation, the pyramid that pairs with SBP_SAMPLING_POINT (a point-sampled
+ * record at dt, decimated by f, is the point-sampled record at f dt):
+ * y_out[r][n] = y[r][n f] for n < T/f, R rows of length T; y_out holds
+ * R * (T/f) floats.
+ * Errors: SBP_E_ARG (NULL, R < 1), SBP_E_DOMAIN (f < 1, T/f < 1). */
+int sbp_decimate(sbp_ctx *ctx, const float *y, int64_t R, int32_t T, int32_t f,
+                 float *y_out, void *stream);
+
 /* Simulate of section 4.2 / 4.3: y[f][d][n] = sum over the balls i of frame f of
  *   p0_i * D_id / (2 rho_id c dt_k) * (psi(u_n) - psi(u_{n+1})),
  *   u_m = rho_id - c (t0 + m dt_k),
@@ -211,6 +221,9 @@ int sbp_downsample(sbp_ctx *ctx, const float *y, int64_t R, int32_t T, int32_t f
  * (psi is the antiderivative of u * fhat(u), zero outside the support;
  * rho_id = |r_i - q_d|; D_id is the directivity).  Pairs with
  * rho_id <= support half-width and balls with a <= 0 contribute nothing.
+ * Under model->sampling = SBP_SAMPLING_POINT (GAUSS) sample n is instead the
+ * pressure p0_i D_id u_n fhat(u_n) / (2 rho_id) itself, |u_n| < K a; the
+ * adjoint and the filter follow the same model.
  * y is [F][D][model->T]; it is overwritten unless accumulate = 1.  Every bin
  * value is rounded to a multiple of a per-call power-of-two quantum (at most
  * 2^-31 of the largest possible bin value) and the multiples are summed

@@ -23,6 +23,7 @@ ERROR_NAMES = {SBP_E_ARG: "SBP_E_ARG", SBP_E_DOMAIN: "SBP_E_DOMAIN", SBP_E_HIP: 
 
 PROFILE_UNIFORM, PROFILE_GAUSS = 0, 1
 DIR_OMNI, DIR_COS = 0, 1
+SAMPLING_BIN, SAMPLING_POINT = 0, 1
 X, Y, Z, P0, A = 1, 2, 4, 8, 16
 XYZ, ALL, COARSE = 7, 31, 24
 MAX_FRAMES = 64
@@ -34,7 +35,7 @@ class SbpModel(ctypes.Structure):
     _fields_ = [("c", ctypes.c_double), ("dt", ctypes.c_double), ("t0", ctypes.c_double),
                 ("gauss_K", ctypes.c_double), ("T", ctypes.c_int32), ("f", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("directivity", ctypes.c_int32),
-                ("a_softplus", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("a_softplus", ctypes.c_int32), ("sampling", ctypes.c_int32)]
 
 
 class SbpArray(ctypes.Structure):
@@ -94,6 +95,7 @@ SIGNATURES = {
     "sbp_ctx_set_tuning": (ctypes.c_int, [P, PT]),
     "sbp_ctx_get_tuning": (ctypes.c_int, [P, PT]),
     "sbp_downsample": (ctypes.c_int, [P, P, I64, I32, I32, P, P]),
+    "sbp_decimate": (ctypes.c_int, [P, P, I64, I32, I32, P, P]),
     "sbp_simulate_signals": (ctypes.c_int, [P, PA, PB, P, I32, I64, PM, P, I32, P]),
     "sbp_residual_loss": (ctypes.c_int, [P, P, P, I64, I32, P, P, P]),
     "sbp_adjoint_gradients": (ctypes.c_int, [P, PA, PB, P, I32, I64, PM, P, U32, PB, P]),

@@ -13,7 +13,8 @@ import dataclasses
 import torch
 
 from . import _abi
-from ._abi import (A, ALL, COARSE, DIR_COS, DIR_OMNI, P0, PROFILE_GAUSS, PROFILE_UNIFORM, X, XYZ, Y, Z,
+from ._abi import (A, ALL, COARSE, DIR_COS, DIR_OMNI, P0, PROFILE_GAUSS, PROFILE_UNIFORM, SAMPLING_BIN,
+                   SAMPLING_POINT, X, XYZ, Y, Z,
                    check, lib)
 
 PARAMS = ("x", "y", "z", "p0", "a")
@@ -32,11 +33,12 @@ class Model:
     directivity: int = DIR_COS
     gauss_K: float = 5.0
     a_softplus: int = 0
+    sampling: int = SAMPLING_BIN   # SAMPLING_POINT: point-sampled variant (GAUSS only)
 
     def struct(self) -> _abi.SbpModel:
         return _abi.SbpModel(float(self.c), float(self.dt), float(self.t0), float(self.gauss_K),
                              int(self.T), int(self.f), int(self.profile), int(self.directivity),
-                             int(self.a_softplus), 0)
+                             int(self.a_softplus), int(self.sampling))
 
     def level(self, f: int, T_base: int) -> "Model":
         """The level with downsampling factor f of a record of T_base samples."""
@@ -221,6 +223,17 @@ def downsample(ctx, y, f: int, out=None, stream=None):
     if out is None:
         out = torch.empty(y.shape[:-1] + (T // f,), dtype=torch.float32, device=y.device)
     check(lib().sbp_downsample(ctx.ptr, _p(y), R, T, int(f), _p(_need(out, name="out")), _stream(stream)))
+    return out
+
+
+def decimate(ctx, y, f: int, out=None, stream=None):
+    """sbp_decimate along the last axis (keeps every f-th sample)."""
+    _need(y, name="y")
+    T = y.shape[-1]
+    R = y.numel() // T
+    if out is None:
+        out = torch.empty(y.shape[:-1] + (T // f,), dtype=torch.float32, device=y.device)
+    check(lib().sbp_decimate(ctx.ptr, _p(y), R, T, int(f), _p(_need(out, name="out")), _stream(stream)))
     return out
 
 

@@ -37,22 +37,22 @@ template <typename R> __device__ __forceinline__ R ld_uniform(const R *p) {
 }
 
 // Moment sums of one block of n <= kRestart edges starting at m0, j = m - m0:
-//   Z = sum w_j f_j,  Z1 = sum w_j f_j j,  Z2 = sum w_j f_j j^2
-// with f_j = e_j (GAUSS, e_{j+1} = e_j g_j, g_{j+1} = g_j h) or 1 (UNIFORM).
-// Along the edges u_j = u_0 - j c, so sum w f u = u_0 Z - c Z1 and
-// sum w f u^2 = u_0 (u_0 Z - 2 c Z1) + c^2 Z2: three sums per edge replace the
-// running u and its two products.
-template <typename R, int PROF, bool MOM>
+//   Z = sum w_j f_j,  Z1 = sum w_j f_j j,  Z2 = sum w_j f_j j^2,  Z3 = sum w_j f_j j^3
+// (the first NMOM of them) with f_j = e_j (GAUSS, e_{j+1} = e_j g_j,
+// g_{j+1} = g_j h) or 1 (UNIFORM).  Along the edges u_j = u_0 - j c, so
+// sum w f u = u_0 Z - c Z1, sum w f u^2 = u_0 (u_0 Z - 2 c Z1) + c^2 Z2, and
+// likewise for u^3: a few sums per edge replace the running u and its powers.
+template <typename R, int PROF, int NMOM>
 __device__ inline void block_moments(const R *__restrict__ wb, int n, R e, R gq, R h, R &Z, R &Z1,
-                                     R &Z2) {
+                                     R &Z2, R &Z3) {
+    constexpr bool EXPO = PROF != UNIFORM;
     auto edge = [&](R w, R j, bool j0) {
-        const R wf = PROF == GAUSS ? w * e : w;
+        const R wf = EXPO ? w * e : w;
         Z += wf;
-        if (MOM && !j0) {
-            Z1 = fma(wf, j, Z1);
-            Z2 = fma(wf, j * j, Z2);
-        }
-        if (PROF == GAUSS) {
+        if (NMOM >= 2 && !j0) Z1 = fma(wf, j, Z1);
+        if (NMOM >= 3 && !j0) Z2 = fma(wf, j * j, Z2);
+        if (NMOM >= 4 && !j0) Z3 = fma(wf, j * j * j, Z3);
+        if (EXPO) {
             e *= gq;
             gq *= h;
         }
@@ -85,6 +85,70 @@ __device__ inline void block_moments(const R *__restrict__ wb, int n, R e, R gq,
     for (; k < n; ++k) {
         edge(wb[k], j, false);
         j += R(1);
+    }
+}
+
+// Point sampling (GPOINT): sample m carries p0 D g(u_m) / (2 rho) with
+// g(u) = u e(u), e(u) = exp(-u^2 / (2 a^2)) for |u| < K a.  The staged row
+// holds w_m = vscale v_m (not differenced), and
+//   S0 = sum w g,  S1 = sum w g' = sum w e (1 - u^2 / a^2),
+//   S2 = sum w dg/da = sum w e u^3 / a^3
+// over the samples inside the support; the gradients then follow from the
+// same closed forms as the bin means with G = D / (2 rho).
+template <typename R, int DIR, bool FULL>
+__device__ inline void adj_pair_point(const BallK<R, GPOINT> &b, R qx, R qy, R qz, R nx, R ny, R nz,
+                                      const Level &lc, int tlo, int thi, const R *__restrict__ wr,
+                                      R acc[5]) {
+    PairG<R> g;
+    if (!pair_geometry<R, DIR>(b.x, b.y, b.z, b.w, qx, qy, qz, nx, ny, nz, lc, g)) return;
+    // samples inside the support: (s - w) / (c dt) < m < (s + w) / (c dt), m < T
+    const double lo = floor((g.s - (double)b.w) * lc.inv_cdt) + 1.0;
+    const double hi = ceil((g.s + (double)b.w) * lc.inv_cdt) - 1.0;
+    const int top = min(thi, lc.T) - 1;
+    if (hi < (double)tlo || lo > (double)top || hi < lo) return;
+    const int mb = lo < (double)tlo ? tlo : (int)lo;
+    const int me = hi > (double)top ? top : (int)hi;
+    wr -= tlo;
+    const R c = LevelR<R>::cdt(lc);
+    constexpr int NMOM = FULL ? 4 : 2;
+    // U1 = sum w e u, U2 = sum w e u^2, U3 = sum w e u^3, E0 = sum w e
+    R E0 = R(0), U1 = R(0), U2 = R(0), U3 = R(0);
+    for (int m0 = mb; m0 <= me; m0 += kRestart) {
+        const R u0 = (R)(g.s - (double)m0 * lc.cdt);
+        const int n = min(kRestart, me - m0 + 1);
+        R e = ex2(u0 * u0 * b.q0);
+        R gq = ex2(b.q0 * c * (c - R(2) * u0));
+        R Z = R(0), Z1 = R(0), Z2 = R(0), Z3 = R(0);
+        block_moments<R, GPOINT, NMOM>(wr + m0, n, e, gq, b.h, Z, Z1, Z2, Z3);
+        const R cZ1 = c * Z1;
+        U1 += u0 * Z - cZ1;
+        if (FULL) {
+            const R c2Z2 = c * c * Z2;
+            E0 += Z;
+            U2 += u0 * fma(u0, Z, R(-2) * cZ1) + c2Z2;
+            // u0^3 Z - 3 u0^2 c Z1 + 3 u0 c^2 Z2 - c^3 Z3
+            U3 += fma(u0, fma(u0, fma(u0, Z, R(-3) * cZ1), R(3) * c2Z2), -(c * c * c * Z3));
+        }
+    }
+    const R inv_a2 = R(1) / (b.a * b.a);
+    const R S0 = U1;
+    const R G = g.dir * R(0.5) * g.inv_rho;
+    acc[3] = fma(G, S0, acc[3]);
+    if (FULL) {
+        const R S1 = E0 - U2 * inv_a2;
+        const R S2 = U3 * inv_a2 / b.a;
+        const R pG = b.p * G;
+        acc[4] = fma(pG, S2, acc[4]);
+        const R radial = pG * (S1 - S0 * g.inv_rho);
+        acc[0] = fma(radial, g.ex, acc[0]);
+        acc[1] = fma(radial, g.ey, acc[1]);
+        acc[2] = fma(radial, g.ez, acc[2]);
+        if (DIR == COS) {
+            const R ct = b.p * R(0.5) * S0 * g.inv_rho * g.inv_rho;
+            acc[0] = fma(ct, nx - g.dir * g.ex, acc[0]);
+            acc[1] = fma(ct, ny - g.dir * g.ey, acc[1]);
+            acc[2] = fma(ct, nz - g.dir * g.ez, acc[2]);
+        }
     }
 }
 
@@ -128,8 +192,8 @@ __device__ inline void adj_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx,
             e = ex2(u0 * u0 * b.q0);
             gq = ex2(b.q0 * c * (c - R(2) * u0));
         }
-        R Z = R(0), Z1 = R(0), Z2 = R(0);
-        block_moments<R, PROF, MOM>(wr + m0, n, e, gq, b.h, Z, Z1, Z2);
+        R Z = R(0), Z1 = R(0), Z2 = R(0), Z3 = R(0);
+        block_moments<R, PROF, MOM ? 3 : 1>(wr + m0, n, e, gq, b.h, Z, Z1, Z2, Z3);
         P += Z;
         if (MOM) {
             const R cZ1 = c * Z1;
@@ -239,8 +303,12 @@ __global__ __launch_bounds__(512, AdjMinBlocks<R>::v) void k_adjoint(ArrayP<R> a
                     R *wr = rows + (int64_t)dl * TT;
                     for (int m = tlo + tid; m < thi; m += nth) {
                         const R cur = m < T ? vr[m] : R(0);
-                        const R prv = m > 0 ? vr[m - 1] : R(0);
-                        wr[m - tlo] = vscale * (cur - prv);
+                        if (PROF == GPOINT) {       // samples, not bin edges
+                            wr[m - tlo] = vscale * cur;
+                        } else {
+                            const R prv = m > 0 ? vr[m - 1] : R(0);
+                            wr[m - tlo] = vscale * (cur - prv);
+                        }
                     }
                 }
                 __syncthreads();
@@ -254,8 +322,12 @@ __global__ __launch_bounds__(512, AdjMinBlocks<R>::v) void k_adjoint(ArrayP<R> a
 #pragma unroll
                     for (int jb = 0; jb < kMaxBpt; ++jb) {
                         if (!act[jb]) continue;
-                        adj_pair<R, PROF, DIR, FULL>(b[jb], qx, qy, qz, nx, ny, nz, lc, tlo, thi,
-                                                     wrow, vrow, vscale, acc[jb]);
+                        if constexpr (PROF == GPOINT)
+                            adj_pair_point<R, DIR, FULL>(b[jb], qx, qy, qz, nx, ny, nz, lc, tlo, thi,
+                                                         wrow, acc[jb]);
+                        else
+                            adj_pair<R, PROF, DIR, FULL>(b[jb], qx, qy, qz, nx, ny, nz, lc, tlo, thi,
+                                                         wrow, vrow, vscale, acc[jb]);
                     }
                 }
             }
@@ -411,6 +483,13 @@ static int dispatch_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls
                             const R *v, R vscale, uint32_t mask, const BallsP<R> &grad, void *ws,
                             size_t ws_bytes, hipStream_t st) {
     const Level lc = make_level(m);
+    if (profile_code(m) == GPOINT) {
+        if (m->directivity == SBP_DIR_COS)
+            return run_adjoint<R, GPOINT, COS, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v,
+                                                     vscale, mask, grad, ws, ws_bytes, st);
+        return run_adjoint<R, GPOINT, OMNI, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v, vscale,
+                                                  mask, grad, ws, ws_bytes, st);
+    }
     if (m->profile == SBP_PROFILE_GAUSS) {
         if (m->directivity == SBP_DIR_COS)
             return run_adjoint<R, GAUSS, COS, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v,

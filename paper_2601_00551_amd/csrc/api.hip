@@ -83,7 +83,10 @@ static int check_model(const sbp_model *m) {
     if (m->directivity != SBP_DIR_OMNI && m->directivity != SBP_DIR_COS)
         return fail(SBP_E_DOMAIN, "unknown directivity %d", m->directivity);
     if (m->a_softplus != 0 && m->a_softplus != 1) return fail(SBP_E_DOMAIN, "a_softplus must be 0 or 1");
-    if (m->reserved != 0) return fail(SBP_E_DOMAIN, "model.reserved must be 0");
+    if (m->sampling != SBP_SAMPLING_BIN && m->sampling != SBP_SAMPLING_POINT)
+        return fail(SBP_E_DOMAIN, "unknown sampling %d", m->sampling);
+    if (m->sampling == SBP_SAMPLING_POINT && m->profile != SBP_PROFILE_GAUSS)
+        return fail(SBP_E_DOMAIN, "point sampling is implemented for the GAUSS profile only");
     if (m->profile == SBP_PROFILE_GAUSS && (!(m->gauss_K > 0.0) || !std::isfinite(m->gauss_K)))
         return fail(SBP_E_DOMAIN, "gauss_K must be > 0");
     return SBP_OK;
@@ -295,6 +298,18 @@ int sbp_downsample(sbp_ctx *ctx, const float *y, int64_t R, int32_t T, int32_t f
     if (rc) return rc;
     if ((rc = set_device(ctx->c))) return rc;
     return launch_downsample(y, R, T, f, y_out, (hipStream_t)stream);
+}
+
+int sbp_decimate(sbp_ctx *ctx, const float *y, int64_t R, int32_t T, int32_t f, float *y_out,
+                 void *stream) {
+    if (!y || !y_out) return fail(SBP_E_ARG, "y or y_out is NULL");
+    if (R < 1) return fail(SBP_E_ARG, "R must be >= 1");
+    if (f < 1) return fail(SBP_E_DOMAIN, "f must be >= 1");
+    if (T < 1 || T / f < 1) return fail(SBP_E_DOMAIN, "T / f must be >= 1");
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = set_device(ctx->c))) return rc;
+    return launch_decimate(y, R, T, f, y_out, (hipStream_t)stream);
 }
 
 int sbp_simulate_signals(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *balls,

@@ -58,6 +58,26 @@ int launch_downsample(const float *y, int64_t R_, int T, int f, float *out, hipS
     return SBP_OK;
 }
 
+// Decimation, the pyramid of point-sampled records: out[r][n] = y[r][n f].
+__global__ void k_decimate(const float *__restrict__ y, int64_t R_, int T, int f, int Tk,
+                           float *__restrict__ out) {
+    const int64_t n_out = R_ * (int64_t)Tk;
+    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < n_out;
+         o += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = o / Tk;
+        const int n = (int)(o - r * Tk);
+        out[o] = y[r * (int64_t)T + (int64_t)n * f];
+    }
+}
+
+int launch_decimate(const float *y, int64_t R_, int T, int f, float *out, hipStream_t st) {
+    const int Tk = T / f;
+    hipLaunchKernelGGL(k_decimate, dim3(ew_grid(R_ * (int64_t)Tk)), dim3(kEw), 0, st, y, R_, T, f, Tk,
+                       out);
+    SBP_HIP(hipGetLastError());
+    return SBP_OK;
+}
+
 // ------------------------------------------------------- residual + loss --
 
 __device__ inline double block_sum(double x, double *s_part) {

@@ -51,10 +51,11 @@ template <> struct FwdAcc<double> {
     __device__ static double value(T s, double) { return s; }
 };
 
-// max over live balls of |p0| * a (a after softplus), as float bits in *slot
-// (zeroed before the launch; non-negative floats order like their bits).
+// max over live balls of |p0| * a (a after softplus; |p0| alone under point
+// sampling, where the peak pressure does not scale with a), as float bits in
+// *slot (zeroed before the launch; non-negative floats order like their bits).
 __global__ void k_amp_bound(BallsP<float> balls, const int64_t *__restrict__ ball_off, int F,
-                            int a_softplus, unsigned *slot) {
+                            int a_softplus, int point, unsigned *slot) {
     __shared__ float s_red[8];
     const int64_t count = ball_off[F];
     float m = 0.0f;
@@ -62,7 +63,7 @@ __global__ void k_amp_bound(BallsP<float> balls, const int64_t *__restrict__ bal
          i += (int64_t)gridDim.x * blockDim.x) {
         float a = balls.a[i];
         if (a_softplus) a = softplus_dev(a);
-        if (a > 0.0f) m = fmaxf(m, fabsf(balls.p0[i]) * a);
+        if (a > 0.0f) m = fmaxf(m, point ? fabsf(balls.p0[i]) : fabsf(balls.p0[i]) * a);
     }
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_down(m, o, 64));
     if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = m;
@@ -105,6 +106,62 @@ __device__ inline void uniform_bins(typename FwdAcc<R>::T *p, R ub, R q0, R c, R
     for (int k = 2; k <= N; ++k) FwdAcc<R>::add(p + (k - 1), fma(B1, R(k), B0));
     const R ue = fma(R(-N), c, ub);
     prev = q0 - ue * ue;
+}
+
+// N consecutive point samples from sample m (u_m = ub): sample k (k = 0..N-1)
+// adds amp u_k e_k, u_k = ub - k c, e_k = 2^(X0 + k (X1 + k X2)).
+template <typename R, int N>
+__device__ inline void point_samples(typename FwdAcc<R>::T *p, R ub, R q0, R c, R X2, R Y1, R amp) {
+    const R X0 = q0 * ub * ub;
+    const R X1 = Y1 * ub;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const R u = fma(R(-k), c, ub);
+        const R e = ex2(fma(R(k), fma(R(k), X2, X1), X0));
+        FwdAcc<R>::add(p + k, amp * u * e);
+    }
+}
+
+// Point sampling (GPOINT): adds p0 D u e(u) / (2 rho) at every sample of the
+// tile [tlo, thi) whose time lies strictly inside the pulse's support.
+template <typename R, int DIR>
+__device__ inline void fwd_pair_point(const BallK<R, GPOINT> &b, R qx, R qy, R qz, R nx, R ny, R nz,
+                                      const Level &lc, int tlo, int thi, R scale,
+                                      typename FwdAcc<R>::T *__restrict__ row) {
+    PairG<R> g;
+    if (!pair_geometry<R, DIR>(b.x, b.y, b.z, b.w, qx, qy, qz, nx, ny, nz, lc, g)) return;
+    const double lo = floor((g.s - (double)b.w) * lc.inv_cdt) + 1.0;
+    const double hi = ceil((g.s + (double)b.w) * lc.inv_cdt) - 1.0;
+    if (hi < (double)tlo || lo > (double)(thi - 1) || hi < lo) return;
+    const int nb = lo < (double)tlo ? tlo : (int)lo;
+    const int ne = hi > (double)(thi - 1) ? thi - 1 : (int)hi;
+    const R amp = b.p * g.dir * R(0.5) * g.inv_rho * scale;
+    const R c = LevelR<R>::cdt(lc);
+    typename FwdAcc<R>::T *p = row - tlo + nb;
+    int cnt = ne - nb + 1;
+    int m = nb;
+    if (FwdBlocks<R>::on) {
+        const R X2 = b.q0 * c * c;
+        const R Y1 = R(-2) * b.q0 * c;
+        for (; cnt >= kFwdBlock; cnt -= kFwdBlock, p += kFwdBlock, m += kFwdBlock)
+            point_samples<R, kFwdBlock>(p, (R)(g.s - (double)m * lc.cdt), b.q0, c, X2, Y1, amp);
+        if (cnt & 4) {
+            point_samples<R, 4>(p, (R)(g.s - (double)m * lc.cdt), b.q0, c, X2, Y1, amp);
+            p += 4;
+            m += 4;
+        }
+        if (cnt & 2) {
+            point_samples<R, 2>(p, (R)(g.s - (double)m * lc.cdt), b.q0, c, X2, Y1, amp);
+            p += 2;
+            m += 2;
+        }
+        if (cnt & 1) point_samples<R, 1>(p, (R)(g.s - (double)m * lc.cdt), b.q0, c, X2, Y1, amp);
+    } else {
+        for (; cnt > 0; --cnt, ++p, ++m) {
+            const R u = (R)(g.s - (double)m * lc.cdt);
+            FwdAcc<R>::add(p, amp * u * ex2(u * u * b.q0));
+        }
+    }
 }
 
 // Adds the pair's bins that fall in the time tile [tlo, thi) to row[n - tlo];
@@ -265,7 +322,9 @@ __device__ inline void flush_rows(typename FwdAcc<R>::T *__restrict__ rows, int 
 // Power-of-two scale with |bin value| * scale <= 2^30 (FP32 path).
 __device__ inline float fixed_scale(const unsigned *slot, int profile, const Level &lc) {
     const float pa = __uint_as_float(*slot);
-    const float bound = pa * lc.inv2cdt * (profile == GAUSS ? 1.0f / lc.K : 0.5f);
+    // point samples: |u e(u)| <= a e^{-1/2} and rho > K a, so |p| < |p0| / (2 K)
+    const float bound = profile == GPOINT ? pa * 0.5f / lc.K
+                                          : pa * lc.inv2cdt * (profile == GAUSS ? 1.0f / lc.K : 0.5f);
     if (!(bound > 0.0f) || !(bound < 3.0e38f)) return 1.0f;
     int e = 0;
     frexpf(bound, &e);              // bound < 2^e
@@ -347,8 +406,12 @@ __global__ __launch_bounds__(512, 4) void k_forward(ArrayP<R> arr, BallsP<R> bal
             for (int dl = 0; dl < dg; ++dl) {
                 const int d = __builtin_amdgcn_readfirstlane(g * dg + dl);
                 if (d >= D) break;
-                fwd_pair<R, PROF, DIR>(b, arr.qx[d], arr.qy[d], arr.qz[d], arr.nx[d], arr.ny[d],
-                                       arr.nz[d], lc, tlo, thi, scale, rows + (int64_t)dl * TT);
+                if constexpr (PROF == GPOINT)
+                    fwd_pair_point<R, DIR>(b, arr.qx[d], arr.qy[d], arr.qz[d], arr.nx[d], arr.ny[d],
+                                           arr.nz[d], lc, tlo, thi, scale, rows + (int64_t)dl * TT);
+                else
+                    fwd_pair<R, PROF, DIR>(b, arr.qx[d], arr.qy[d], arr.qz[d], arr.nx[d], arr.ny[d],
+                                           arr.nz[d], lc, tlo, thi, scale, rows + (int64_t)dl * TT);
             }
         }
     }
@@ -438,12 +501,17 @@ int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const i
         hipLaunchKernelGGL(k_amp_bound, dim3((int)nb), dim3(256), 0, st,
                            BallsP<float>{(float *)balls.x, (float *)balls.y, (float *)balls.z,
                                          (float *)balls.p0, (float *)balls.a},
-                           ball_off, F, m->a_softplus, bound_slot);
+                           ball_off, F, m->a_softplus, (int)(profile_code(m) == GPOINT), bound_slot);
         SBP_HIP(hipGetLastError());
         bound = bound_slot;
     }
     int rc;
-    if (m->profile == SBP_PROFILE_GAUSS) {
+    if (profile_code(m) == GPOINT) {
+        if (m->directivity == SBP_DIR_COS)
+            rc = run_forward<R, GPOINT, COS>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, gacc, st);
+        else
+            rc = run_forward<R, GPOINT, OMNI>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, gacc, st);
+    } else if (m->profile == SBP_PROFILE_GAUSS) {
         if (m->directivity == SBP_DIR_COS)
             rc = run_forward<R, GAUSS, COS>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, gacc, st);
         else
@@ -458,7 +526,7 @@ int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const i
     int64_t nb = (ns + 255) / 256;
     if (nb > 4096) nb = 4096;
     hipLaunchKernelGGL(k_fwd_convert, dim3((int)nb), dim3(256), 0, st, (const unsigned long long *)gacc,
-                       ns, bound, m->profile, lc, accumulate, (float *)y);
+                       ns, bound, profile_code(m), lc, accumulate, (float *)y);
     SBP_HIP(hipGetLastError());
     return SBP_OK;
 }

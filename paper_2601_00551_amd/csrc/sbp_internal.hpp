@@ -23,6 +23,15 @@
 namespace sbp {
 
 enum { UNIFORM = SBP_PROFILE_UNIFORM, GAUSS = SBP_PROFILE_GAUSS };
+// Kernel-internal profile code of GAUSS balls under point sampling (the
+// samples are pressure values u fhat(u) p0 D / (2 rho) at the sample times,
+// not bin means); its ball constants are GAUSS's.
+enum { GPOINT = 2 };
+
+// Internal profile code of a model.
+inline int profile_code(const sbp_model *m) {
+    return m->sampling == SBP_SAMPLING_POINT ? GPOINT : m->profile;
+}
 enum { OMNI = SBP_DIR_OMNI, COS = SBP_DIR_COS };
 
 // Per-launch constants of one temporal level.
@@ -216,6 +225,7 @@ template <typename R>
 int launch_fill(R *p, int64_t n, R value, hipStream_t st);
 
 int launch_downsample(const float *y, int64_t R_, int T, int f, float *out, hipStream_t st);
+int launch_decimate(const float *y, int64_t R_, int T, int f, float *out, hipStream_t st);
 size_t residual_ws_bytes(int F);
 int launch_residual_loss(double *partial_ws, const float *ys, const float *yr, int64_t n, int F,
                          float *v, double *loss, hipStream_t st);

@@ -22,14 +22,16 @@ def to_dev(d, device, dtype=None):
     return {k: torch.as_tensor(np.ascontiguousarray(v), dtype=dt, device=device) for k, v in d.items()}
 
 
-def otime(T, dt=0.025, f=1, profile=oracle.GAUSS, directivity=oracle.COS, K=5.0, t0=0.0, c=1.5):
-    return oracle.Time(c=c, dt=dt, t0=t0, T=T, f=f, profile=profile, directivity=directivity, K=K)
+def otime(T, dt=0.025, f=1, profile=oracle.GAUSS, directivity=oracle.COS, K=5.0, t0=0.0, c=1.5,
+          sampling=oracle.BIN):
+    return oracle.Time(c=c, dt=dt, t0=t0, T=T, f=f, profile=profile, directivity=directivity, K=K,
+                       sampling=sampling)
 
 
-def gmodel(T, dt=0.025, f=1, profile=1, directivity=1, K=5.0, t0=0.0, c=1.5, a_softplus=0):
+def gmodel(T, dt=0.025, f=1, profile=1, directivity=1, K=5.0, t0=0.0, c=1.5, a_softplus=0, sampling=0):
     from paper_2601_00551_amd.api import Model
     return Model(c=c, dt=dt, t0=t0, T=T, f=f, profile=profile, directivity=directivity, gauss_K=K,
-                 a_softplus=a_softplus)
+                 a_softplus=a_softplus, sampling=sampling)
 
 
 def small_scene(seed, nb=5000, nd=37, radius=12.0, half=4.0, a=0.15, tilt=25.0):

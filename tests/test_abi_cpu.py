@@ -111,6 +111,11 @@ def test_adjoint_validation():
     assert call(_abi.P0, grad=g2) == _abi.SBP_E_ARG and "ctx" in last()   # p0-only with others NULL is fine
     assert call(_abi.ALL, grad=g2) == _abi.SBP_E_ARG and "grad" in last()
     assert call(_abi.ALL, model=_model(f=-2)) == _abi.SBP_E_DOMAIN
+    assert call(_abi.ALL, model=_model(sampling=7)) == _abi.SBP_E_DOMAIN and "sampling" in last()
+    # point sampling exists for the GAUSS profile only
+    assert call(_abi.ALL, model=_model(sampling=_abi.SAMPLING_POINT, profile=0)) == _abi.SBP_E_DOMAIN
+    assert "GAUSS" in last()
+    assert call(_abi.ALL, model=_model(sampling=_abi.SAMPLING_POINT)) == _abi.SBP_E_ARG   # then ctx
 
 
 def test_downsample_validation():
@@ -120,6 +125,16 @@ def test_downsample_validation():
     assert lib.sbp_downsample(None, FAKE, 0, 100, 2, FAKE, None) == _abi.SBP_E_ARG
     assert lib.sbp_downsample(None, None, 4, 100, 2, FAKE, None) == _abi.SBP_E_ARG
     assert lib.sbp_downsample(None, FAKE, 4, 100, 2, FAKE, None) == _abi.SBP_E_ARG
+    assert "ctx" in last()
+
+
+def test_decimate_validation():
+    lib = _abi.lib()
+    assert lib.sbp_decimate(None, FAKE, 4, 100, 0, FAKE, None) == _abi.SBP_E_DOMAIN
+    assert lib.sbp_decimate(None, FAKE, 4, 3, 4, FAKE, None) == _abi.SBP_E_DOMAIN
+    assert lib.sbp_decimate(None, FAKE, 0, 100, 2, FAKE, None) == _abi.SBP_E_ARG
+    assert lib.sbp_decimate(None, FAKE, 4, 100, 2, None, None) == _abi.SBP_E_ARG
+    assert lib.sbp_decimate(None, FAKE, 4, 100, 2, FAKE, None) == _abi.SBP_E_ARG
     assert "ctx" in last()
 
 
