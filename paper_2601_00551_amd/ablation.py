@@ -6,9 +6,11 @@ filtering and iterates at the full sampling rate only, while Pro filters the
 cloud and raises the sampling rate level by level.  This module runs both on
 one workload and records, every few iterations, the image quality of the
 voxelised cloud against the voxelised phantom (MSE / PSNR / SSIM, on the GPU);
-the time spent measuring is excluded from the reported wall times.
+the time spent measuring is excluded from the reported wall times.  Both
+schedules also run on point samples (the pressure at the sample times, with
+the decimation pyramid) next to the bin means of the default path.
 
-    python -m paper_2601_00551_amd.ablation --out ablation.json
+    python -m paper_2601_00551_amd.ablation --variants pro,slingbag,pro_point,slingbag_point --out a.json
 """
 from __future__ import annotations
 
@@ -67,8 +69,9 @@ class QualityProbe:
             self.measure(r, si, it, L)
 
 
-def run(ctx, wl, y, stages, grid, gt_vol, every=10, capacity=0):
-    cfg = recon.ReconConfig(stages=stages, T=wl.T, dt=wl.dt, dup_frac=0.05, capacity=capacity)
+def run(ctx, wl, y, stages, grid, gt_vol, every=10, capacity=0, sampling=api.SAMPLING_BIN):
+    cfg = recon.ReconConfig(stages=stages, T=wl.T, dt=wl.dt, dup_frac=0.05, capacity=capacity,
+                            sampling=sampling)
     r = recon.Recon(wl.array, y, wl.init, cfg, ctx=ctx)
     probe = QualityProbe(ctx, gt_vol, grid, api.Model(), every=every)
     out = r.run(on_iter=probe)
@@ -84,38 +87,56 @@ def time_to(trace, psnr):
     return None
 
 
+# (name, schedule, sampling): the bin-average path of the paper, and the same
+# two schedules on point samples with the decimation pyramid
+VARIANTS = {
+    "pro": (pro_schedule, api.SAMPLING_BIN),
+    "slingbag": (slingbag_schedule, api.SAMPLING_BIN),
+    "pro_point": (pro_schedule, api.SAMPLING_POINT),
+    "slingbag_point": (slingbag_schedule, api.SAMPLING_POINT),
+}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="SlingBAG Pro vs a SlingBAG-style schedule")
     ap.add_argument("--iters", type=int, default=60)
     ap.add_argument("--seeds", type=int, default=1)
+    ap.add_argument("--variants", default="pro,slingbag",
+                    help="comma-separated subset of " + ",".join(VARIANTS))
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
+    names = [v for v in args.variants.split(",") if v]
+    for v in names:
+        if v not in VARIANTS:
+            ap.error(f"unknown variant {v!r}")
     ctx = api.context(0)
     dev = torch.device("cuda:0")
     grid = proposal.Grid.cube(10.0, 0.2)
     rows = []
     for s in range(args.seeds):
         wl = synth.conformal_config(seed_index=s)
-        y = proposal.synthetic_measurement(ctx, wl, seed=2000 + s)
+        # each sampling mode fits a record made the same way (same noise draw)
+        ys = {smp: proposal.synthetic_measurement(ctx, wl, seed=2000 + s, sampling=smp)
+              for smp in {VARIANTS[v][1] for v in names}}
         gt = {k: torch.as_tensor(np.asarray(v), device=dev) for k, v in wl.gt.items()}
         off = torch.tensor([0, len(wl.gt["x"])], dtype=torch.int64, device=dev)
         gt_vol = image.voxelize(ctx, gt, off, api.Model(), grid)
         cap = 4 * len(wl.init["x"])
         res = {}
-        for name, stages in (("pro", pro_schedule(iters=args.iters)),
-                             ("slingbag", slingbag_schedule(iters=args.iters))):
-            res[name] = run(ctx, wl, y, stages, grid, gt_vol, capacity=cap)
+        for name in names:
+            sched, smp = VARIANTS[name]
+            res[name] = run(ctx, wl, ys[smp], sched(iters=args.iters), grid, gt_vol, capacity=cap,
+                            sampling=smp)
             last = res[name]["trace"][-1]
             print(json.dumps(dict(event="run", seed=s, schedule=name, wall_s=res[name]["wall_s"],
                                   final_loss=res[name]["final_loss"], balls=res[name]["balls"],
                                   psnr=last["psnr"], ssim=last["ssim"], mse=last["mse"])), flush=True)
-        target = min(res["pro"]["trace"][-1]["psnr"], res["slingbag"]["trace"][-1]["psnr"])
-        row = dict(seed=s, psnr_target=target, pro_t=time_to(res["pro"]["trace"], target),
-                   slingbag_t=time_to(res["slingbag"]["trace"], target),
-                   pro=res["pro"], slingbag=res["slingbag"])
+        target = min(res[n]["trace"][-1]["psnr"] for n in names)
+        row = dict(seed=s, psnr_target=target, **{n + "_t": time_to(res[n]["trace"], target) for n in names},
+                   **res)
         rows.append(row)
-        print(json.dumps(dict(event="compare", seed=s, psnr_target=target, pro_t=row["pro_t"],
-                              slingbag_t=row["slingbag_t"])), flush=True)
+        print(json.dumps(dict(event="compare", seed=s, psnr_target=target,
+                              **{n + "_t": row[n + "_t"] for n in names})), flush=True)
     if args.out:
         with open(args.out, "w") as fh:
             json.dump(rows, fh)

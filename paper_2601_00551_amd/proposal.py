@@ -354,11 +354,11 @@ def proposal_workload(index, n_init=200_000, n_det=512):
     return synth.Workload(f"proposal-{index}", arr, gt, init, 2048, 0.025, (4, 2, 1), 0.1)
 
 
-def synthetic_measurement(ctx, wl, noise=0.05, seed=0, device="cuda:0"):
+def synthetic_measurement(ctx, wl, noise=0.05, seed=0, device="cuda:0", sampling=api.SAMPLING_BIN):
     dev = torch.device(device)
     A = {k: torch.as_tensor(v, device=dev) for k, v in wl.array.items()}
     gt = {k: torch.as_tensor(v, device=dev) for k, v in wl.gt.items()}
-    y = api.simulate_signals(ctx, A, gt, api.Model(c=synth.C, dt=wl.dt, T=wl.T, f=1))
+    y = api.simulate_signals(ctx, A, gt, api.Model(c=synth.C, dt=wl.dt, T=wl.T, f=1, sampling=sampling))
     if noise > 0:
         rng = np.random.default_rng(seed)
         sigma = noise * float(y.abs().max())

@@ -55,6 +55,7 @@ class ReconConfig:
     profile: int = api.PROFILE_GAUSS
     directivity: int = api.DIR_COS
     gauss_K: float = 5.0
+    sampling: int = api.SAMPLING_BIN   # POINT: point samples, pyramid by decimation
     lr: tuple = (0.005, 0.005, 0.005, 0.02, 0.002)   # x, y, z, p0, a
     growth: dict = dataclasses.field(default_factory=lambda: dict(
         destroy_frac=0.02, a_min=0.02, a_split=0.3, dup_offset=0.5))
@@ -121,7 +122,8 @@ class Recon:
     def model(self, f, a_softplus=0):
         c = self.cfg
         return api.Model(c=c.c, dt=c.dt, t0=c.t0, T=c.T // f, f=f, profile=c.profile,
-                         directivity=c.directivity, gauss_K=c.gauss_K, a_softplus=a_softplus)
+                         directivity=c.directivity, gauss_K=c.gauss_K, a_softplus=a_softplus,
+                         sampling=c.sampling)
 
     def _rule(self, dup_frac):
         g = dict(self.cfg.growth)
@@ -207,7 +209,8 @@ class Recon:
             stg = Stage(**stg) if isinstance(stg, dict) else stg
             model = self.model(stg.f, a_softplus=int(softplus_on))
             T_k = model.T
-            y_k = api.downsample(self.ctx, self.y_real, stg.f)
+            pyramid = api.decimate if cfg.sampling == api.SAMPLING_POINT else api.downsample
+            y_k = pyramid(self.ctx, self.y_real, stg.f)
             yw = y_work.view(-1)[: self.F * self.D * T_k].view(self.F, self.D, T_k)
             fresh = not (resume and si == start_stage and start_it > 0)
             if fresh:
