@@ -146,7 +146,7 @@ __device__ inline bool pair_geometry(R bx, R by, R bz, R w, R qx, R qy, R qz,
     R inv_rho;
     if (sizeof(R) == 4) {
         // FP32 square root refined by one Newton step in FP64: relative error
-        // about 1e-14, from a quarter-rate FP32 root instead of the FP64 one
+        // about 1e-14, from a half-rate FP32 root instead of the FP64 one
         const float r0 = __builtin_amdgcn_sqrtf((float)r2);
         const float i0 = __builtin_amdgcn_rcpf(r0);
         rho = fma(fma(-(double)r0, (double)r0, r2), (double)(0.5f * i0), (double)r0);
