@@ -1,10 +1,11 @@
 """Launch-shape autotuner for the forward and adjoint kernels.
 
-For a workload shape (profile, directivity, transducers D, samples T_k, balls
-B) it times candidate launch shapes of the two kernels on the real inputs,
+For a workload shape (profile, directivity, sampling, transducers D, samples
+T_k, balls B) it times candidate launch shapes of the two kernels on the real inputs,
 keeps the fastest of each, and caches the choice in a JSON file keyed by the
 device architecture and a bucketed shape.  apply_cached() looks a shape up
-(nearest bucket of the same profile / directivity if there is no exact entry)
+(nearest bucket of the same profile / directivity / sampling if there is no
+exact entry)
 and installs it on a context.
 """
 from __future__ import annotations
@@ -27,7 +28,9 @@ def _bucket(n: int) -> int:
 
 
 def shape_key(arch: str, model, D: int, B: int) -> str:
-    return f"{arch}|p{model.profile}d{model.directivity}|D{_bucket(D)}|T{model.T}|B{_bucket(B)}"
+    # point sampling runs other kernel instantiations: a bucket of its own
+    smp = "s1" if getattr(model, "sampling", 0) else ""
+    return f"{arch}|p{model.profile}d{model.directivity}{smp}|D{_bucket(D)}|T{model.T}|B{_bucket(B)}"
 
 
 def _arch() -> str:
@@ -145,6 +148,7 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--levels", default="1")
     ap.add_argument("--profile", choices=("gauss", "uniform"), default="gauss")
+    ap.add_argument("--sampling", choices=("bin", "point"), default="bin")
     args = ap.parse_args(argv)
     dev = torch.device("cuda:0")
     ctx = api.Context(0)
@@ -160,7 +164,8 @@ def main(argv=None):
     for f in (int(x) for x in args.levels.split(",")):
         model = api.Model(c=1.5, dt=wl.dt, T=wl.T // f, f=f,
                           profile=api.PROFILE_GAUSS if args.profile == "gauss" else api.PROFILE_UNIFORM,
-                          directivity=api.DIR_COS)
+                          directivity=api.DIR_COS,
+                          sampling=api.SAMPLING_POINT if args.sampling == "point" else api.SAMPLING_BIN)
         v = torch.as_tensor(rng.normal(size=(1, len(wl.array["qx"]), model.T)).astype(np.float32), device=dev)
         res = tune(ctx, A, Bt, model, v, reps=args.reps, path=args.out, log=lambda s: print(s, flush=True))
         print(json.dumps({"workload": wl.name, "f": f, "chosen": res["chosen"],

@@ -12,8 +12,8 @@ class FakeCtx:
 
 
 class M:
-    def __init__(self, profile, directivity=1, T=4096):
-        self.profile, self.directivity, self.T = profile, directivity, T
+    def __init__(self, profile, directivity=1, T=4096, sampling=0):
+        self.profile, self.directivity, self.T, self.sampling = profile, directivity, T, sampling
 
 
 def write_cache(tmp_path, entries):
@@ -43,3 +43,20 @@ def test_missing_profile_falls_back_to_defaults(tmp_path, monkeypatch):
     assert ctx.tuning == tuned
     # UNIFORM has no entry: the previous workload's shape must not leak through
     assert autotune.apply_cached(ctx, path, M(0), 1024, 2_000_000) == autotune.DEFAULTS
+
+
+def test_point_sampling_has_its_own_buckets(tmp_path, monkeypatch):
+    monkeypatch.setattr(autotune, "_arch", lambda: "gfx950")
+    assert autotune.shape_key("gfx950", M(1), 1024, 2_000_000) == "gfx950|p1d1|D1024|T4096|B2097152"
+    assert autotune.shape_key("gfx950", M(1, sampling=1), 1024, 2_000_000) == "gfx950|p1d1s1|D1024|T4096|B2097152"
+    binned = dict(autotune.DEFAULTS, fwd_dets=1, adj_dets=2)
+    point = dict(autotune.DEFAULTS, fwd_dets=2, adj_dets=4)
+    path = write_cache(tmp_path, {"gfx950|p1d1|D1024|T4096|B2097152": binned})
+    ctx = FakeCtx()
+    assert autotune.apply_cached(ctx, path, M(1), 1024, 2_000_000) == binned
+    # no point-sampling entry: defaults, not the bin-mean shape
+    assert autotune.apply_cached(ctx, path, M(1, sampling=1), 1024, 2_000_000) == autotune.DEFAULTS
+    path = write_cache(tmp_path, {"gfx950|p1d1|D1024|T4096|B2097152": binned,
+                                  "gfx950|p1d1s1|D512|T2048|B262144": point})
+    assert autotune.apply_cached(ctx, path, M(1, sampling=1), 1024, 2_000_000) == point   # nearest
+    assert autotune.apply_cached(ctx, path, M(1), 512, 200_000) == binned

@@ -147,6 +147,59 @@ def test_point_forward_bitwise_reproducible(ctx):
         assert np.array_equal(y, ys[0])
 
 
+def test_point_softplus_parameterisation(ctx):
+    arr, balls = small_scene(321, nb=1200, nd=15)
+    T = 450
+    at = oracle.softplus_inv(balls["a"]).astype(np.float32)
+    b2 = dict(balls, a=at)
+    m = pm(T, a_softplus=1)
+    ob = dict(balls, a=oracle.softplus(at))
+    assert rel_l2(run_fwd(ctx, arr, b2, m)[0].cpu().numpy(), oracle.simulate(ob, arr, pt(T))) <= SIG_TOL
+    v = np.random.default_rng(2).normal(size=(15, T)).astype(np.float32)
+    g = run_adj(ctx, arr, b2, m, v)
+    ref = oracle.vjp(ob, arr, pt(T), v)
+    ref["a"] = ref["a"] * oracle.sigmoid(at)
+    for k in PARAMS:
+        assert rel_l2(g[k], ref[k]) <= GRAD_TOL, k
+
+
+def test_point_frames_and_edge_cases(ctx):
+    """Three frames (one empty); one ball seen by one transducer over a few
+    samples; a transducer inside the support; a dead ball."""
+    rng = np.random.default_rng(331)
+    arr = synth.hemisphere_array(23, 12.0, rng, tilt_deg=20)
+    parts = [synth.uniform_balls(rng, n, 4.0, 0.15) for n in (1700, 0, 2300)]
+    balls = synth.concat_balls(parts)
+    off = np.array([0, 1700, 1700, 4000])
+    T = 450
+    dev = torch.device("cuda:0")
+    y = run_fwd(ctx, arr, balls, pm(T), ball_off=torch.tensor(off, device=dev)).cpu().numpy()
+    v = rng.normal(size=(3, 23, T)).astype(np.float32)
+    g = run_adj(ctx, arr, balls, pm(T), v, ball_off=torch.tensor(off, device=dev))
+    assert y.shape == (3, 23, T) and np.all(y[1] == 0.0)
+    for f in (0, 2):
+        assert rel_l2(y[f], oracle.simulate(parts[f], arr, pt(T))) <= SIG_TOL
+        ref = oracle.vjp(parts[f], arr, pt(T), v[f])
+        for k in PARAMS:
+            assert rel_l2(g[k][off[f]:off[f + 1]], ref[k]) <= GRAD_TOL
+    one = {"x": np.array([0.0], np.float32), "y": np.array([0.0], np.float32), "z": np.array([0.0], np.float32),
+           "p0": np.array([1.0], np.float32), "a": np.array([0.15], np.float32)}
+    a1 = {k: w[:1] for k, w in arr.items()}
+    rho = float(np.sqrt(a1["qx"][0] ** 2 + a1["qy"][0] ** 2 + a1["qz"][0] ** 2))
+    scale = np.abs(oracle.simulate(one, a1, pt(80, t0=rho / 1.5 - 1.0))).max()
+    for T1, dt0 in ((1, 0.05), (2, -0.1), (7, 0.2), (7, -0.0123)):
+        t0 = rho / 1.5 + dt0
+        yo = run_fwd(ctx, a1, one, pm(T1, t0=t0))[0].cpu().numpy()
+        ref = oracle.simulate(one, a1, pt(T1, t0=t0))
+        assert yo.shape == ref.shape and np.max(np.abs(yo - ref)) <= 1e-5 * scale, (T1, dt0)
+    near = dict(one, x=np.array([a1["qx"][0] + 0.2], np.float32), y=a1["qy"].copy(), z=a1["qz"].copy())
+    assert np.all(run_fwd(ctx, a1, near, pm(50))[0].cpu().numpy() == 0)
+    gn = run_adj(ctx, a1, near, pm(50), np.ones((1, 50), np.float32))
+    assert all(np.all(gn[k] == 0) for k in PARAMS)
+    dead = dict(one, a=np.array([-0.1], np.float32))
+    assert np.all(run_fwd(ctx, a1, dead, pm(50, t0=rho / 1.5 - 0.1))[0].cpu().numpy() == 0)
+
+
 def test_point_f64_twins_match_oracle_tightly(ctx):
     arr, balls = small_scene(271, nb=700, nd=9)
     T = 450
