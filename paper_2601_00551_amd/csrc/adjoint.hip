@@ -232,6 +232,85 @@ __device__ inline void adj_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx,
     }
 }
 
+// Stages edges [tlo, thi) of the nd cotangent rows d0.. into LDS rows of
+// stride TS (a multiple of four): w_m = vscale (v_m - v_{m-1}) for bin means
+// (v is zero outside [0, T)), w_m = vscale v_m for point samples.  FP32: a
+// thread takes four consecutive edges at a time (one 16-byte load, one
+// 16-byte LDS store) and issues the loads of kStageU such quads before it uses
+// any, so a pass pays the global latency a few times rather than once per
+// edge; quads at the record's ends, or rows that are not 16-byte aligned, go
+// edge by edge.  The values are the same either way.
+constexpr int kStageU = 5;
+
+template <typename R, bool DIFF>
+__device__ inline R stage_edge(const R *__restrict__ vr, int m, int T, R vscale) {
+    const R cur = m < T ? vr[m] : R(0);
+    if (!DIFF) return vscale * cur;
+    const R prv = m > 0 ? vr[m - 1] : R(0);
+    return vscale * (cur - prv);
+}
+
+template <typename R, bool DIFF>
+__device__ inline void stage_rows(const R *__restrict__ vf, int d0, int nd, int T, int tlo, int thi,
+                                  R vscale, R *rows, int TS) {
+    const int tid = threadIdx.x;
+    const int nth = blockDim.x;
+    if constexpr (sizeof(R) != sizeof(float)) {
+        for (int dl = 0; dl < nd; ++dl) {
+            const R *vr = vf + (int64_t)(d0 + dl) * T;
+            R *wr = rows + (int64_t)dl * TS;
+            for (int m = tlo + tid; m < thi; m += nth) wr[m - tlo] = stage_edge<R, DIFF>(vr, m, T, vscale);
+        }
+    } else {
+        const int nq = (thi - tlo + 3) >> 2;
+        for (int dl = 0; dl < nd; ++dl) {
+            const float *vr = vf + (int64_t)(d0 + dl) * T;
+            float *wr = rows + (int64_t)dl * TS;
+            const bool vec = (reinterpret_cast<uintptr_t>(vr + tlo) & 15) == 0;
+            for (int q0 = tid; q0 < nq; q0 += nth * kStageU) {
+                float4 cv[kStageU];
+                float pv[kStageU];
+#pragma unroll
+                for (int u = 0; u < kStageU; ++u) {
+                    const int q = q0 + u * nth;
+                    const int m = tlo + 4 * q;
+                    if (vec && q < nq && m >= 1 && m + 4 <= T && m + 4 <= thi) {
+                        cv[u] = *reinterpret_cast<const float4 *>(vr + m);
+                        pv[u] = DIFF ? vr[m - 1] : 0.0f;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kStageU; ++u) {
+                    const int q = q0 + u * nth;
+                    const int m = tlo + 4 * q;
+                    if (q >= nq) continue;
+                    if (vec && m >= 1 && m + 4 <= T && m + 4 <= thi) {
+                        float4 w;
+                        if (DIFF) {
+                            w.x = vscale * (cv[u].x - pv[u]);
+                            w.y = vscale * (cv[u].y - cv[u].x);
+                            w.z = vscale * (cv[u].z - cv[u].y);
+                            w.w = vscale * (cv[u].w - cv[u].z);
+                        } else {
+                            w.x = vscale * cv[u].x;
+                            w.y = vscale * cv[u].y;
+                            w.z = vscale * cv[u].z;
+                            w.w = vscale * cv[u].w;
+                        }
+                        *reinterpret_cast<float4 *>(wr + 4 * q) = w;
+                    } else {
+                        for (int k = 0; k < 4 && m + k < thi; ++k)
+                            wr[m + k - tlo] = stage_edge<float, DIFF>(vr, m + k, T, vscale);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Row stride of the staged tiles: the tile length rounded up to four floats.
+__host__ __device__ inline int adj_row_stride(int TT) { return (TT + 3) & ~3; }
+
 // Work items are (frame, ball chunk, transducer slice).  With one slice the
 // kernel writes the gradients; with nsl > 1 each item writes its slice's
 // partial sums to part[(slice * NF + field) * pstride + ball] (NF = 5, or 1
@@ -259,6 +338,7 @@ __global__ __launch_bounds__(512, AdjMinBlocks<R>::v) void k_adjoint(ArrayP<R> a
     const int T = lc.T;
     const int D = arr.D;
     const int64_t CH = (int64_t)nth * bpt;
+    const int TS = adj_row_stride(TT);
     for (int i = tid; i <= F; i += nth) s_off[i] = ball_off[i];
     __syncthreads();
     if (tid == 0) {
@@ -298,26 +378,15 @@ __global__ __launch_bounds__(512, AdjMinBlocks<R>::v) void k_adjoint(ArrayP<R> a
             for (int tlo = 0; tlo <= T; tlo += TT) {
                 const int thi = min(tlo + TT, T + 1);
                 __syncthreads();
-                for (int dl = 0; dl < nd; ++dl) {
-                    const R *vr = vf + (int64_t)(d0 + dl) * T;
-                    R *wr = rows + (int64_t)dl * TT;
-                    for (int m = tlo + tid; m < thi; m += nth) {
-                        const R cur = m < T ? vr[m] : R(0);
-                        if (PROF == GPOINT) {       // samples, not bin edges
-                            wr[m - tlo] = vscale * cur;
-                        } else {
-                            const R prv = m > 0 ? vr[m - 1] : R(0);
-                            wr[m - tlo] = vscale * (cur - prv);
-                        }
-                    }
-                }
+                // point samples are staged as they are, bin edges differenced
+                stage_rows<R, PROF != GPOINT>(vf, d0, nd, T, tlo, thi, vscale, rows, TS);
                 __syncthreads();
                 for (int dl = 0; dl < nd; ++dl) {
                     const int d = __builtin_amdgcn_readfirstlane(d0 + dl);
                     const R qx = ld_uniform(arr.qx + d), qy = ld_uniform(arr.qy + d),
                             qz = ld_uniform(arr.qz + d), nx = ld_uniform(arr.nx + d),
                             ny = ld_uniform(arr.ny + d), nz = ld_uniform(arr.nz + d);
-                    const R *wrow = rows + (int64_t)dl * TT;
+                    const R *wrow = rows + (int64_t)dl * TS;
                     const R *vrow = vf + (int64_t)d * T;
 #pragma unroll
                     for (int jb = 0; jb < kMaxBpt; ++jb) {
@@ -437,8 +506,9 @@ static int run_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
     const size_t avail = c->lds_max > reserve ? c->lds_max - reserve : 0;
     int ds = c->tuning.adj_dets;
     if (ds > arr.D) ds = arr.D;
-    // edges 0..T staged per pass: the whole record if the ds rows fit
-    int64_t TT = (int64_t)(avail / ((size_t)ds * sizeof(R)));
+    // edges 0..T staged per pass: the whole record if the ds rows fit (rows
+    // padded to four floats)
+    int64_t TT = (int64_t)(avail / ((size_t)ds * sizeof(R))) & ~(int64_t)3;
     if (TT > (int64_t)lc.T + 1) TT = (int64_t)lc.T + 1;
     if (TT < (int64_t)lc.T + 1 && TT < 64) return fail(SBP_E_DOMAIN, "LDS too small for %d rows", ds);
     if (c->tuning.adj_tile > 0 && TT > c->tuning.adj_tile) TT = c->tuning.adj_tile;
@@ -450,7 +520,7 @@ static int run_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
     }
     R *part = pl.nsl > 1 ? (R *)ws : nullptr;
     const int block = pl.block;
-    const size_t lds = (size_t)ds * (size_t)TT * sizeof(R);
+    const size_t lds = (size_t)ds * (size_t)adj_row_stride((int)TT) * sizeof(R);
     SBP_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds));
     int grid = c->tuning.adj_grid;
