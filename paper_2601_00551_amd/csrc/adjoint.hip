@@ -238,8 +238,10 @@ __device__ inline void adj_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx,
 // thread takes four consecutive edges at a time (one 16-byte load, one
 // 16-byte LDS store) and issues the loads of kStageU such quads before it uses
 // any, so a pass pays the global latency a few times rather than once per
-// edge; quads at the record's ends, or rows that are not 16-byte aligned, go
-// edge by edge.  The values are the same either way.
+// edge; the two quads at the record's ends load separately (one thread per
+// row, loads ahead of use), and the tail of a tile or of a record that is not
+// a multiple of four, and rows that are not 16-byte aligned, go edge by edge.
+// The values are the same either way.
 constexpr int kStageU = 5;
 
 template <typename R, bool DIFF>
@@ -298,11 +300,35 @@ __device__ inline void stage_rows(const R *__restrict__ vf, int d0, int nd, int 
                             w.w = vscale * cv[u].w;
                         }
                         *reinterpret_cast<float4 *>(wr + 4 * q) = w;
-                    } else {
+                    } else if (!(vec && (T & 3) == 0 && (m == 0 || m == T))) {
                         for (int k = 0; k < 4 && m + k < thi; ++k)
                             wr[m + k - tlo] = stage_edge<float, DIFF>(vr, m + k, T, vscale);
                     }
                 }
+            }
+        }
+        // The two end quads of aligned rows whose length is a multiple of
+        // four, thread dl for row dl: edges 0..3 (v_{-1} = 0) and edge T
+        // (v_T = 0), all loads ahead of use.
+        if (tid < nd) {
+            const float *vr = vf + (int64_t)(d0 + tid) * T;
+            float *wr = rows + (int64_t)tid * TS;
+            if ((reinterpret_cast<uintptr_t>(vr + tlo) & 15) == 0 && (T & 3) == 0) {
+                const bool head = tlo == 0;
+                const bool tail = thi == T + 1;
+                float4 h = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                float pt = 0.0f;
+                if (head) h = *reinterpret_cast<const float4 *>(vr);
+                if (tail && DIFF) pt = vr[T - 1];
+                if (head) {
+                    float4 w;
+                    w.x = vscale * h.x;
+                    w.y = DIFF ? vscale * (h.y - h.x) : vscale * h.y;
+                    w.z = DIFF ? vscale * (h.z - h.y) : vscale * h.z;
+                    w.w = DIFF ? vscale * (h.w - h.z) : vscale * h.w;
+                    *reinterpret_cast<float4 *>(wr) = w;
+                }
+                if (tail) wr[T - tlo] = DIFF ? vscale * (0.0f - pt) : vscale * 0.0f;
             }
         }
     }

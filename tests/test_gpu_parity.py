@@ -135,6 +135,27 @@ def test_adjoint_matches_oracle(ctx, profile, directivity):
         assert rel_l2(g[k], ref[k]) <= GRAD_TOL, (k, rel_l2(g[k], ref[k]))
 
 
+@pytest.mark.parametrize("T,t0", [(448, 8.0), (400, 0.0), (449, 8.0), (401, 0.0)])
+def test_adjoint_pulses_cut_at_the_record_ends(ctx, T, t0):
+    """Pulses that start before the record (t0 = 8 us) or end after it (T = 400
+    at 0.025 us): the staged cotangent's first and last edges carry the cut,
+    for lengths that are and are not a multiple of four."""
+    arr, balls = small_scene(35, nb=2000, nd=21)
+    v = np.random.default_rng(T).normal(size=(21, T)).astype(np.float32)
+    m, tm = gmodel(T, t0=t0), otime(T, t0=t0)
+    g = run_adj(ctx, arr, balls, m, v)
+    ref = oracle.vjp(balls, arr, tm, v)
+    for k in PARAMS:
+        assert rel_l2(g[k], ref[k]) <= GRAD_TOL, (k, rel_l2(g[k], ref[k]))
+    # some supports do straddle the record's start or end
+    q = np.stack([arr["qx"], arr["qy"], arr["qz"]], 1)
+    b = np.stack([balls["x"], balls["y"], balls["z"]], 1)
+    rho = np.linalg.norm(b[:, None, :] - q[None, :, :], axis=2)
+    w = 5.0 * balls["a"][:, None]
+    edge = t0 if t0 > 0 else t0 + T * 0.025
+    assert np.count_nonzero((rho - w < 1.5 * edge) & (rho + w > 1.5 * edge)) > 100
+
+
 def test_adjoint_masks(ctx):
     arr, balls = small_scene(41, nb=1500, nd=17)
     T = 450
