@@ -238,11 +238,17 @@ __device__ inline void adj_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx,
 // thread takes four consecutive edges at a time (one 16-byte load, one
 // 16-byte LDS store) and issues the loads of kStageU such quads before it uses
 // any, so a pass pays the global latency a few times rather than once per
-// edge; the two quads at the record's ends load separately (one thread per
-// row, loads ahead of use), and the tail of a tile or of a record that is not
-// a multiple of four, and rows that are not 16-byte aligned, go edge by edge.
+// edge; the two quads at the record's ends load separately (one lane per row,
+// loads ahead of use), and the tail of a tile or of a record that is not a
+// multiple of four, and rows that are not 16-byte aligned, go edge by edge.
 // The values are the same either way.
-constexpr int kStageU = 5;
+//
+// kStageU, the quads in flight per thread: four covers a 4096-sample row in
+// one round with 256 threads; the point-sampled OMNI gradient kernel takes
+// three, the most that keeps its pass loop free of register spills.
+template <int PROF, int DIR, bool FULL> struct StageDepth {
+    static constexpr int v = (PROF == GPOINT && DIR == OMNI && FULL) ? 3 : 4;
+};
 
 template <typename R, bool DIFF>
 __device__ inline R stage_edge(const R *__restrict__ vr, int m, int T, R vscale) {
@@ -252,7 +258,7 @@ __device__ inline R stage_edge(const R *__restrict__ vr, int m, int T, R vscale)
     return vscale * (cur - prv);
 }
 
-template <typename R, bool DIFF>
+template <typename R, bool DIFF, int kStageU>
 __device__ inline void stage_rows(const R *__restrict__ vf, int d0, int nd, int T, int tlo, int thi,
                                   R vscale, R *rows, int TS) {
     const int tid = threadIdx.x;
@@ -308,11 +314,14 @@ __device__ inline void stage_rows(const R *__restrict__ vf, int d0, int nd, int 
             }
         }
         // The two end quads of aligned rows whose length is a multiple of
-        // four, thread dl for row dl: edges 0..3 (v_{-1} = 0) and edge T
-        // (v_T = 0), all loads ahead of use.
-        if (tid < nd) {
-            const float *vr = vf + (int64_t)(d0 + tid) * T;
-            float *wr = rows + (int64_t)tid * TS;
+        // four, lane 0 of wave dl for row dl (addresses wave-uniform): edges
+        // 0..3 (v_{-1} = 0) and edge T (v_T = 0), all loads ahead of use.
+        const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int nwave = (nth + 63) >> 6;
+        for (int dl = wave; dl < nd; dl += nwave) {
+            if ((tid & 63) != 0) continue;
+            const float *vr = vf + (int64_t)(d0 + dl) * T;
+            float *wr = rows + (int64_t)dl * TS;
             if ((reinterpret_cast<uintptr_t>(vr + tlo) & 15) == 0 && (T & 3) == 0) {
                 const bool head = tlo == 0;
                 const bool tail = thi == T + 1;
@@ -405,7 +414,8 @@ __global__ __launch_bounds__(512, AdjMinBlocks<R>::v) void k_adjoint(ArrayP<R> a
                 const int thi = min(tlo + TT, T + 1);
                 __syncthreads();
                 // point samples are staged as they are, bin edges differenced
-                stage_rows<R, PROF != GPOINT>(vf, d0, nd, T, tlo, thi, vscale, rows, TS);
+                stage_rows<R, PROF != GPOINT, StageDepth<PROF, DIR, FULL>::v>(vf, d0, nd, T, tlo, thi,
+                                                                              vscale, rows, TS);
                 __syncthreads();
                 for (int dl = 0; dl < nd; ++dl) {
                     const int d = __builtin_amdgcn_readfirstlane(d0 + dl);
