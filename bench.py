@@ -286,6 +286,7 @@ def suite(args):
         y_k = api.downsample(ctx, y, f)
         st, t_filter = filtered(A, wl.init, model, y_k)
         kept = st.count()
+        autotune.apply_cached(ctx, args.tuning, model, D, kept)     # shapes for the kept cloud
         tf, tb = fwd_adj(A, st, model, y_k)
         te, tg = iteration_rates(A, st, model, y_k, iters=10, reps=2)
         print(json.dumps({"workload": wl.name, "level_f": f, "samples": wl.T // f,
@@ -314,6 +315,7 @@ def suite(args):
     st, t_filter = filtered(A, balls, model, y.contiguous(), off=off)
     kept_off = st.ball_off.cpu().numpy()
     kept = int(kept_off[-1])
+    autotune.apply_cached(ctx, args.tuning, model, D, int(np.max(np.diff(kept_off))))
     tf, tb = fwd_adj(A, st, model, y.contiguous())
     te, tg = iteration_rates(A, st, model, y.contiguous(), iters=5, reps=2)
     print(json.dumps({"workload": "batched-16-frames-ell512-T2048-40MHz", "frames": F,

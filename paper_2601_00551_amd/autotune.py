@@ -19,6 +19,9 @@ FWD_SPACE = {"fwd_dets": (1, 2, 4, 8), "fwd_block": (256, 512), "fwd_bpt": (1, 2
              "fwd_tile": (0, 2048, 1024)}
 ADJ_SPACE = {"adj_dets": (2, 4, 8), "adj_block": (128, 256, 512), "adj_bpt": (1, 2, 4),
              "adj_tile": (0, 2048)}
+# The launch-shape cache shipped with the package (tuned on an MI355X).
+DEFAULT_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
+
 DEFAULTS = {"fwd_dets": 4, "fwd_block": 512, "fwd_bpt": 4, "fwd_grid": 0, "adj_dets": 4,
             "adj_block": 512, "adj_bpt": 4, "adj_grid": 0, "fwd_tile": 0, "adj_tile": 0}
 
@@ -144,11 +147,14 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=("large", "conformal"), default="large")
     ap.add_argument("--balls", type=int, default=2_000_000)
-    ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json"))
+    ap.add_argument("--out", default=DEFAULT_PATH)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--levels", default="1")
     ap.add_argument("--profile", choices=("gauss", "uniform"), default="gauss")
     ap.add_argument("--sampling", choices=("bin", "point"), default="bin")
+    ap.add_argument("--subsample", type=float, default=1.0,
+                    help="tune on this seeded random fraction of the initial cloud (the size the "
+                         "zero-gradient filter leaves, about one half on the conformal workload)")
     args = ap.parse_args(argv)
     dev = torch.device("cuda:0")
     ctx = api.Context(0)
@@ -158,6 +164,10 @@ def main(argv=None):
     else:
         wl = synth.conformal_config()
         balls = wl.init
+    if args.subsample < 1.0:
+        n = len(balls["x"])
+        keep = np.sort(np.random.default_rng(11).choice(n, int(n * args.subsample), replace=False))
+        balls = {k: np.asarray(v)[keep] for k, v in balls.items()}
     A = {k: torch.as_tensor(v, device=dev) for k, v in wl.array.items()}
     Bt = {k: torch.as_tensor(v, device=dev) for k, v in balls.items()}
     rng = np.random.default_rng(7)

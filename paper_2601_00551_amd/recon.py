@@ -28,7 +28,7 @@ import time
 import numpy as np
 import torch
 
-from . import api
+from . import api, autotune
 from .api import ALL, COARSE, PARAMS
 
 
@@ -56,6 +56,7 @@ class ReconConfig:
     directivity: int = api.DIR_COS
     gauss_K: float = 5.0
     sampling: int = api.SAMPLING_BIN   # POINT: point samples, pyramid by decimation
+    tuning: str | None = autotune.DEFAULT_PATH   # launch-shape cache applied at stage entry (None: keep)
     lr: tuple = (0.005, 0.005, 0.005, 0.02, 0.002)   # x, y, z, p0, a
     growth: dict = dataclasses.field(default_factory=lambda: dict(
         destroy_frac=0.02, a_min=0.02, a_split=0.3, dup_offset=0.5))
@@ -124,6 +125,13 @@ class Recon:
         return api.Model(c=c.c, dt=c.dt, t0=c.t0, T=c.T // f, f=f, profile=c.profile,
                          directivity=c.directivity, gauss_K=c.gauss_K, a_softplus=a_softplus,
                          sampling=c.sampling)
+
+    def _tune(self, model):
+        """Install the cached launch shape for this level and the largest frame's
+        current ball count (results do not depend on it beyond rounding)."""
+        if self.cfg.tuning:
+            n = int(torch.diff(self.state.ball_off).max().item()) if self.F else 0
+            autotune.apply_cached(self.ctx, self.cfg.tuning, model, self.D, max(n, 1))
 
     def _rule(self, dup_frac):
         g = dict(self.cfg.growth)
@@ -214,6 +222,7 @@ class Recon:
             yw = y_work.view(-1)[: self.F * self.D * T_k].view(self.F, self.D, T_k)
             fresh = not (resume and si == start_stage and start_it > 0)
             if fresh:
+                self._tune(model)
                 if stg.filter:
                     self._filter(model, y_k)
                 if stg.duplicate and cfg.dup_frac > 0:
@@ -224,6 +233,7 @@ class Recon:
                 self._log(si, -1, stg, None, "stage-entry")
             else:
                 it0 = start_it
+            self._tune(model)     # for the cloud the stage iterates on
             sp_start = stg.iters - int(round(stg.softplus_frac * stg.iters)) if stg.softplus_frac > 0 else None
             hist = []
             it = it0
