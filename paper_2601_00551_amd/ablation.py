@@ -112,6 +112,15 @@ def main(argv=None):
     ctx = api.context(0)
     dev = torch.device("cuda:0")
     grid = proposal.Grid.cube(10.0, 0.2)
+    # untimed warm-up: first launches of each kernel and launch shape
+    wl = synth.conformal_config(seed_index=0)
+    ys = proposal.synthetic_measurement(ctx, wl, seed=2000)
+    off = torch.tensor([0, len(wl.gt["x"])], dtype=torch.int64, device=dev)
+    gt_vol = image.voxelize(ctx, {k: torch.as_tensor(np.asarray(v), device=dev) for k, v in wl.gt.items()},
+                            off, api.Model(), grid)
+    for name in names:
+        sched, smp = VARIANTS[name]
+        run(ctx, wl, ys, sched(iters=3), grid, gt_vol, capacity=4 * len(wl.init["x"]), sampling=smp)
     rows = []
     for s in range(args.seeds):
         wl = synth.conformal_config(seed_index=s)

@@ -41,10 +41,20 @@ def _arch() -> str:
     return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
 
 
+_LOADED: dict = {}
+
+
 def load(path: str) -> dict:
+    """The cache file's entries (parsed once per file version: the
+    reconstruction driver looks shapes up at every stage entry)."""
     if path and os.path.exists(path):
-        with open(path) as fh:
-            return json.load(fh)
+        st = os.stat(path)
+        stamp = (st.st_mtime_ns, st.st_size, st.st_ino)
+        hit = _LOADED.get(path)
+        if hit is None or hit[0] != stamp:
+            with open(path) as fh:
+                hit = _LOADED[path] = (stamp, json.load(fh))
+        return hit[1]
     return {}
 
 
@@ -130,7 +140,7 @@ def tune(ctx, arr, balls, model, v, reps: int = 3, path: str | None = None, log=
     chosen.update(best_a[0])
     ctx.tuning = chosen
     if path:
-        cache = load(path)
+        cache = dict(load(path))
         cache[shape_key(_arch(), model, D, B)] = chosen
         with open(path + ".tmp", "w") as fh:
             json.dump(cache, fh, indent=1, sort_keys=True)
