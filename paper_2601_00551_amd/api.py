@@ -84,6 +84,26 @@ def _need(t, dtype=torch.float32, name="tensor"):
     return t
 
 
+def _at_least(t, n, name):
+    """The kernels index device buffers by the sizes passed beside them: a
+    buffer shorter than that is a host-side error here, not a GPU fault."""
+    if t is not None and t.numel() < n:
+        raise ValueError(f"{name} holds {t.numel()} elements, the call needs {n}")
+    return t
+
+
+def _exactly(t, n, name):
+    if t is not None and t.numel() != n:
+        raise ValueError(f"{name} holds {t.numel()} elements, the call needs exactly {n}")
+    return t
+
+
+def _check_balls(b, n, what="balls"):
+    for k in PARAMS:
+        if b is not None and b.get(k) is not None:
+            _at_least(b[k], n, f"{what}[{k!r}]")
+
+
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
@@ -91,6 +111,8 @@ def _stream(stream=None):
 
 def array_struct(arr, dtype=torch.float32) -> _abi.SbpArray:
     ts = [_need(arr[k], dtype, k) for k in ARRAY_KEYS]
+    for k, t in zip(ARRAY_KEYS, ts):
+        _exactly(t, ts[0].numel(), f"array[{k!r}]")
     return _abi.SbpArray(*[t.data_ptr() for t in ts], int(ts[0].numel()), 0)
 
 
@@ -167,8 +189,10 @@ def simulate_signals(ctx, arr, balls, model: Model, ball_off=None, y=None, accum
     D = arr["qx"].numel()
     if y is None:
         y = torch.empty((F, D, model.T), dtype=dtype, device=dev)
-    _need(y, dtype, "y")
+    _exactly(_need(y, dtype, "y"), F * D * model.T, "y")
     cap = balls["x"].numel() if B_cap is None else int(B_cap)
+    _check_balls(balls, cap)
+    _at_least(off, 1, "ball_off")
     fn = lib().sbp_simulate_signals if dtype == torch.float32 else lib().sbp_simulate_signals_f64
     check(fn(ctx.ptr, ctypes.byref(array_struct(arr, dtype)), ctypes.byref(balls_struct(balls, dtype)),
              _p(off), F, cap, ctypes.byref(model.struct()), _p(y), int(bool(accumulate)), _stream(stream)))
@@ -187,6 +211,9 @@ def adjoint_gradients(ctx, arr, balls, model: Model, v, mask=ALL, ball_off=None,
                 for i, k in enumerate(PARAMS)}
     _need(v, dtype, "v")
     cap = n if B_cap is None else int(B_cap)
+    _exactly(v, F * arr["qx"].numel() * model.T, "v")
+    _check_balls(balls, cap)
+    _check_balls({k: grad.get(k) for k in PARAMS if mask & (1 << PARAMS.index(k))}, cap, "grad")
     fn = lib().sbp_adjoint_gradients if dtype == torch.float32 else lib().sbp_adjoint_gradients_f64
     check(fn(ctx.ptr, ctypes.byref(array_struct(arr, dtype)), ctypes.byref(balls_struct(balls, dtype)),
              _p(off), F, cap, ctypes.byref(model.struct()), _p(v), int(mask),
@@ -210,6 +237,9 @@ def residual_loss(ctx, y_sim, y_ref, v_out=None, loss=None, stream=None):
     n = y_sim[0].numel()
     if loss is None:
         loss = torch.empty(F, dtype=torch.float64, device=y_sim.device)
+    _exactly(y_ref, y_sim.numel(), "y_ref")
+    _exactly(v_out, y_sim.numel(), "v_out")
+    _at_least(loss, F, "loss")
     check(lib().sbp_residual_loss(ctx.ptr, _p(y_sim), _p(y_ref), n, F, _p(_need(v_out, name="v_out")),
                                   _p(_need(loss, torch.float64, "loss")), _stream(stream)))
     return loss
@@ -220,8 +250,11 @@ def downsample(ctx, y, f: int, out=None, stream=None):
     _need(y, name="y")
     T = y.shape[-1]
     R = y.numel() // T
+    if f < 1:
+        raise ValueError("f must be >= 1")
     if out is None:
         out = torch.empty(y.shape[:-1] + (T // f,), dtype=torch.float32, device=y.device)
+    _exactly(_need(out, name="out"), R * (T // f), "out")
     check(lib().sbp_downsample(ctx.ptr, _p(y), R, T, int(f), _p(_need(out, name="out")), _stream(stream)))
     return out
 
@@ -231,8 +264,11 @@ def decimate(ctx, y, f: int, out=None, stream=None):
     _need(y, name="y")
     T = y.shape[-1]
     R = y.numel() // T
+    if f < 1:
+        raise ValueError("f must be >= 1")
     if out is None:
         out = torch.empty(y.shape[:-1] + (T // f,), dtype=torch.float32, device=y.device)
+    _exactly(_need(out, name="out"), R * (T // f), "out")
     check(lib().sbp_decimate(ctx.ptr, _p(y), R, T, int(f), _p(_need(out, name="out")), _stream(stream)))
     return out
 
@@ -263,6 +299,14 @@ def filter_zero_grad(ctx, arr, balls, model: Model, y_ref, ball_off=None, strict
         else:
             m_out = {k: torch.empty_like(m_in[k]) for k in PARAMS}
             v_out = {k: torch.empty_like(v_in[k]) for k in PARAMS}
+    _check_balls(balls, cap)
+    _check_balls(out, cap, "out")
+    for name, b in (("moments[0]", m_in), ("moments[1]", v_in), ("moments_out[0]", m_out),
+                    ("moments_out[1]", v_out)):
+        _check_balls(b, cap, name)
+    _at_least(off_out, F + 1, "off_out")
+    _at_least(g_out, cap, "g_out")
+    _exactly(y_ref, F * arr["qx"].numel() * model.T, "y_ref")
     ref = lambda b: None if b is None else ctypes.byref(balls_struct(b))
     check(lib().sbp_filter_zero_grad(
         ctx.ptr, ctypes.byref(array_struct(arr)), ctypes.byref(balls_struct(balls)), _p(off), F, cap,
@@ -315,6 +359,10 @@ def step(ctx, arr, state: State, model: Model, y_ref, y_work, params: AdamParams
     """sbp_step: one iteration (simulate, residual+loss, adjoint, Adam).  Returns loss [F]."""
     if loss is None:
         loss = torch.empty(state.F, dtype=torch.float64, device=y_ref.device)
+    n = state.F * arr["qx"].numel() * model.T
+    _exactly(y_ref, n, "y_ref")
+    _at_least(y_work, n, "y_work")
+    _at_least(loss, state.F, "loss")
     check(lib().sbp_step(ctx.ptr, ctypes.byref(array_struct(arr)), ctypes.byref(state.struct()),
                          ctypes.byref(model.struct()), _p(_need(y_ref, name="y_ref")),
                          _p(_need(y_work, name="y_work")), ctypes.byref(params.struct()),
@@ -328,6 +376,9 @@ class StepGraph:
     def __init__(self, ctx, arr, state: State, model: Model, y_ref, y_work, params: AdamParams,
                  iters: int, step0: int = 1, stream=None):
         dev = y_ref.device
+        n = state.F * arr["qx"].numel() * model.T
+        _exactly(_need(y_ref, name="y_ref"), n, "y_ref")
+        _at_least(_need(y_work, name="y_work"), n, "y_work")
         self.step_dev = torch.tensor([int(step0)], dtype=torch.int32, device=dev)
         self.loss = torch.zeros(iters * state.F, dtype=torch.float64, device=dev)
         self.iters = iters
