@@ -16,7 +16,7 @@ import numpy as np
 import torch
 
 from ._abi import check, lib
-from .api import _need, _p, _stream
+from .api import _exactly, _need, _p, _stream
 
 
 def envelope_mesh(array) -> np.ndarray:
@@ -31,6 +31,8 @@ def mesh_inside(ctx, tri, x, y, z, margin=0.0, want_dist=False, stream=None):
     """sbp_mesh_inside: (uint8 flags, distances or None) for the points (x, y, z)."""
     _need(tri, name="tri")
     N = x.numel()
+    _exactly(_need(y, name="y"), N, "y")
+    _exactly(_need(z, name="z"), N, "z")
     flags = torch.empty(N, dtype=torch.uint8, device=x.device)
     dist = torch.empty(N, dtype=torch.float32, device=x.device) if want_dist else None
     check(lib().sbp_mesh_inside(ctx.ptr, _p(tri), int(tri.numel() // 9), _p(_need(x, name="x")),

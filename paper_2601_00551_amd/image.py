@@ -11,7 +11,7 @@ import torch
 
 from . import _abi, api
 from ._abi import check, lib
-from .api import _need, _p, _stream, balls_struct
+from .api import _at_least, _check_balls, _exactly, _need, _p, _stream, balls_struct
 
 
 def voxelize(ctx, balls, ball_off, model: api.Model, grid, B_cap=None, vox=None, stream=None):
@@ -21,6 +21,8 @@ def voxelize(ctx, balls, ball_off, model: api.Model, grid, B_cap=None, vox=None,
     if vox is None:
         vox = torch.empty(grid.ncell, dtype=torch.float32, device=dev)
     cap = balls["x"].numel() if B_cap is None else int(B_cap)
+    _check_balls(balls, cap)
+    _exactly(_need(vox, name="vox"), grid.ncell, "vox")
     check(lib().sbp_voxelize(ctx.ptr, ctypes.byref(balls_struct(balls)),
                              _p(_need(ball_off, torch.int64, "ball_off")), cap,
                              ctypes.byref(model.struct()), ctypes.byref(grid.struct()),
@@ -38,6 +40,7 @@ def metrics(ctx, img, ref, shape, scale, work=None, stream=None):
         raise ValueError("img and ref must hold nx*ny*nz values")
     if work is None:
         work = torch.empty(10 * n, dtype=torch.float32, device=img.device)
+    _at_least(_need(work, name="work"), 10 * n, "work")
     out = torch.empty(3, dtype=torch.float64, device=img.device)
     check(lib().sbp_image_metrics(ctx.ptr, _p(img), _p(ref), nx, ny, nz, float(scale),
                                   _p(_need(work, name="work")), _p(out), _stream(stream)))

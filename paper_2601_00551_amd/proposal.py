@@ -34,7 +34,7 @@ import torch
 
 from . import _abi, api, recon, synth
 from ._abi import MLP_HID, MLP_IN, MLP_NPARAM, MLP_NWORK, check, lib
-from .api import P0, PARAMS, XYZ, _need, _p, _stream, balls_struct
+from .api import P0, PARAMS, XYZ, _at_least, _check_balls, _exactly, _need, _p, _stream, balls_struct
 
 # flat FP32 parameter layout of the network (row-major [in][out], then bias)
 LAYOUT = [("W1", (32, MLP_HID)), ("b1", (MLP_HID,)), ("W2", (MLP_HID, MLP_HID)), ("b2", (MLP_HID,)),
@@ -93,6 +93,9 @@ class ProposalMLP:
             raise ValueError("X must be [M][31]")
         if out is None:
             out = torch.empty((M, 2), dtype=torch.float32, device=X.device)
+        _at_least(_need(out, name="out"), 2 * M, "out")
+        if acts is not None:
+            _at_least(acts, (32 + 3 * MLP_HID) * padded(M), "acts")
         check(lib().sbp_mlp_forward(self.ctx.ptr, _p(self.params), _p(self.work), _p(X), M,
                                     _p(_need(out, name="out")), _p(acts), _stream(stream)))
         return out
@@ -116,7 +119,9 @@ class ProposalMLP:
         b = self._buffers(M)
         out = torch.empty((M, 2), dtype=torch.float32, device=X.device)
         self.forward(X, out=out, acts=b["acts"], stream=stream)
-        check(lib().sbp_mlp_loss(self.ctx.ptr, _p(out), _p(_need(yg, name="yg")), _p(_need(yp, name="yp")),
+        _at_least(_need(yg, name="yg"), M, "yg")
+        _at_least(_need(yp, name="yp"), M, "yp")
+        check(lib().sbp_mlp_loss(self.ctx.ptr, _p(out), _p(yg), _p(yp),
                                  M, float(pos_weight), _p(b["loss"]), _p(b["dout"]), _p(b["dout_t"]),
                                  _stream(stream)))
         check(lib().sbp_mlp_backward(self.ctx.ptr, _p(self.work), _p(b["acts"]), _p(b["dout"]),
@@ -174,6 +179,8 @@ def grid_mass(ctx, balls, ball_off, grid: Grid, B_cap=None, mass=None, stream=No
     if mass is None:
         mass = torch.empty(grid.ncell, dtype=torch.float32, device=dev)
     cap = balls["x"].numel() if B_cap is None else int(B_cap)
+    _check_balls(balls, cap)
+    _exactly(_need(mass, name="mass"), grid.ncell, "mass")
     check(lib().sbp_grid_mass(ctx.ptr, ctypes.byref(balls_struct(balls)), _p(_need(ball_off, torch.int64, "ball_off")),
                               cap, ctypes.byref(grid.struct()), _p(_need(mass, name="mass")), _stream(stream)))
     return mass
@@ -185,6 +192,8 @@ def candidates(ctx, grid: Grid, mass, occ, a_probe, sites=None, stream=None):
     if sites is None:
         sites = {k: torch.empty(grid.ncell, dtype=torch.float32, device=dev) for k in PARAMS}
     cap = sites["x"].numel()
+    _check_balls(sites, cap, "sites")
+    _exactly(_need(mass, name="mass"), grid.ncell, "mass")
     cnt = ctypes.c_int64()
     check(lib().sbp_candidates(ctx.ptr, ctypes.byref(grid.struct()), _p(_need(mass, name="mass")), float(occ),
                                float(a_probe), ctypes.byref(balls_struct(sites)), cap, ctypes.byref(cnt),
@@ -197,6 +206,10 @@ def features(ctx, grid: Grid, mass, sites, M, g, half, X=None, stream=None):
     dev = mass.device
     if X is None:
         X = torch.empty((M, MLP_IN), dtype=torch.float32, device=dev)
+    _exactly(_need(mass, name="mass"), grid.ncell, "mass")
+    _check_balls(sites, M, "sites")
+    _check_balls({k: g[k] for k in ("x", "y", "z", "p0")}, M, "g")
+    _at_least(_need(X, name="X"), M * MLP_IN, "X")
     gb = _abi.SbpBalls(_p(g["x"]), _p(g["y"]), _p(g["z"]), _p(g["p0"]), None)
     check(lib().sbp_features(ctx.ptr, ctypes.byref(grid.struct()), _p(mass), ctypes.byref(balls_struct(sites)),
                              int(M), ctypes.byref(gb), float(half), _p(_need(X, name="X")), _stream(stream)))
@@ -205,6 +218,8 @@ def features(ctx, grid: Grid, mass, sites, M, g, half, X=None, stream=None):
 
 def append_proposals(ctx, state: api.State, sites, out, M, a_init, p0_scale=1.0, stream=None):
     """sbp_append_proposals: returns the new ball count of frame 0."""
+    _check_balls(sites, M, "sites")
+    _at_least(_need(out, name="out"), 2 * M, "out")
     cnt = ctypes.c_int64()
     check(lib().sbp_append_proposals(ctx.ptr, ctypes.byref(state.struct()), ctypes.byref(balls_struct(sites)),
                                      _p(_need(out, name="out")), int(M), float(a_init), float(p0_scale),

@@ -62,3 +62,27 @@ def test_exact_buffers_still_run(setup):
     g = api.adjoint_gradients(ctx, A, B, gmodel(T), y)
     assert all(torch.isfinite(g[k]).all() for k in PARAMS)
     assert api.decimate(ctx, y, 3).shape == (1, 7, 33)
+
+
+def test_image_and_proposal_buffers(setup):
+    from paper_2601_00551_amd import envelope, image, proposal
+    ctx, dev, A, B = setup
+    grid = proposal.Grid.cube(2.0, 0.5)
+    off = torch.tensor([0, B["x"].numel()], dtype=torch.int64, device=dev)
+    with pytest.raises(ValueError, match="vox"):
+        image.voxelize(ctx, B, off, api.Model(), grid, vox=torch.empty(grid.ncell - 1, device=dev))
+    n = grid.ncell
+    img = torch.zeros(n, device=dev)
+    with pytest.raises(ValueError, match="work"):
+        image.metrics(ctx, img, img, (grid.nx, grid.ny, grid.nz), 1.0, work=torch.empty(10 * n - 1, device=dev))
+    with pytest.raises(ValueError, match="mass"):
+        proposal.grid_mass(ctx, B, off, grid, mass=torch.empty(n + 1, device=dev))
+    tri = torch.zeros(9, device=dev)
+    x = torch.zeros(5, device=dev)
+    with pytest.raises(ValueError, match="y"):
+        envelope.mesh_inside(ctx, tri, x, torch.zeros(4, device=dev), x)
+    mlp = proposal.ProposalMLP(ctx)
+    X = torch.zeros(10, proposal.MLP_IN, device=dev)
+    with pytest.raises(ValueError, match="out"):
+        mlp.forward(X, out=torch.empty(10, 1, device=dev))
+    assert mlp.forward(X).shape == (10, 2)
