@@ -48,8 +48,10 @@ def test_partial_requires_grad(ctx):
     assert t["x"].grad is None and t["p0"].grad is not None and t["a"].grad is not None
 
 
-def test_gradcheck_fp64(ctx):
-    """Central finite differences of the FP64 GPU forward against its FP64 adjoint."""
+@pytest.mark.parametrize("sampling", [api.SAMPLING_BIN, api.SAMPLING_POINT])
+def test_gradcheck_fp64(ctx, sampling):
+    """Central finite differences of the FP64 GPU forward against its FP64 adjoint,
+    for bin means and point samples."""
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(203)
     arr, balls = small_scene(203, nb=6, nd=5, radius=9.0, half=1.5)
@@ -57,7 +59,7 @@ def test_gradcheck_fp64(ctx):
     A = to_dev(arr, dev, torch.float64)
     t = [torch.tensor(balls[k], dtype=torch.float64, device=dev, requires_grad=True) for k in PARAMS]
     w = torch.as_tensor(rng.normal(size=(1, 5, T)), device=dev)
-    fn = lambda *p: (simulate(*p, A, gmodel(T), sbp_ctx=ctx) * w).sum()
+    fn = lambda *p: (simulate(*p, A, gmodel(T, sampling=sampling), sbp_ctx=ctx) * w).sum()
     assert torch.autograd.gradcheck(fn, tuple(t), eps=1e-6, atol=1e-7, rtol=1e-5)
 
 

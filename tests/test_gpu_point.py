@@ -283,3 +283,37 @@ def test_uniform_point_is_rejected(ctx):
     arr, balls = small_scene(311, nb=50, nd=3)
     with pytest.raises(_abi.SbpError, match="GAUSS"):
         run_fwd(ctx, arr, balls, pm(100, profile=0))
+
+
+def test_point_step_graph_replays_match_eager(ctx):
+    """The captured iteration under point sampling: replays, with eager work
+    between them, track an eager run of the same iterations."""
+    dev = torch.device("cuda:0")
+    arr, balls = small_scene(341, nb=2000, nd=17)
+    T = 452
+    gt = dict(balls, p0=(balls["p0"] * 0.7).astype(np.float32))
+    y_ref = torch.as_tensor(oracle.simulate(gt, arr, pt(T)).astype(np.float32)[None], device=dev)
+    prm = api.AdamParams(lr=(0.001, 0.001, 0.001, 0.01, 0.001), step=1)
+    A = to_dev(arr, dev)
+    st_e = api.State(balls, device=dev)
+    st_g = api.State(balls, device=dev)
+    yw_e = torch.empty(1, 17, T, device=dev)
+    yw_g = torch.empty(1, 17, T, device=dev)
+    graph = api.StepGraph(ctx, A, st_g, pm(T), y_ref, yw_g, prm, iters=3, step0=1)
+    losses_e = []
+    step = 1
+    for rep in range(3):
+        for _ in range(3):
+            prm.step = step
+            losses_e.append(api.step(ctx, A, st_e, pm(T), y_ref, yw_e, prm)[0].item())
+            step += 1
+        graph.launch()
+        graph.stream.synchronize()
+        _ = (yw_e * 2).sum().item()
+        np.testing.assert_allclose(graph.loss.cpu().numpy(), losses_e[-3:], rtol=1e-4)
+        for k in PARAMS:
+            a = st_g.balls[k].cpu().numpy()
+            b = st_e.balls[k].cpu().numpy()
+            assert np.max(np.abs(a - b)) <= 1e-5 * max(1.0, np.abs(b).max()), (rep, k)
+    assert losses_e[-1] < losses_e[0]
+    graph.close()
