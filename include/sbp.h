@@ -75,7 +75,9 @@ extern "C" {
 
 /* Forward model of one temporal level k (section 4.3: dt_k = f_k dt, T_k = T/f_k).
  * Sample n of a transducer is the mean pressure over the time bin
- * [t0 + n f dt, t0 + (n+1) f dt).  a_softplus = 1 means the `a` arrays hold the
+ * [t0 + n f dt, t0 + (n+1) f dt) (sampling = SBP_SAMPLING_BIN), or the
+ * pressure at t0 + n f dt (SBP_SAMPLING_POINT, GAUSS profile only; its
+ * pyramid is sbp_decimate).  a_softplus = 1 means the `a` arrays hold the
  * unconstrained a~ and the size is a = softplus(a~) = log(1 + e^a~) (the
  * positivity-constrained refinement of section 4.3); gradients are then with
  * respect to a~. */
@@ -89,7 +91,7 @@ typedef struct sbp_model {
     int32_t profile;   /* SBP_PROFILE_* */
     int32_t directivity; /* SBP_DIR_* */
     int32_t a_softplus;  /* 0 or 1 */
-    int32_t sampling;    /* SBP_SAMPLING_* (0, the paper's bin means, unless stated) */
+    int32_t sampling;    /* SBP_SAMPLING_*; other values: SBP_E_DOMAIN */
 } sbp_model;
 
 /* Transducer array: D positions q and unit normals n (SoA, device, float). */
