@@ -3,7 +3,8 @@
 Every HIP source is compiled with packed-FP32 instructions disabled (the
 compiler otherwise forms v_pk_* FP32 ops on its own) and with hardware float
 atomics for global memory.  Objects are cached by content hash under _build/
-so that unchanged sources are not recompiled; the link always runs.
+so that unchanged sources are not recompiled (unless `fresh`); the link
+always runs.
 """
 import hashlib
 import os
@@ -41,10 +42,10 @@ def _digest(src):
     return h.hexdigest()[:16]
 
 
-def _compile(src, verbose):
+def _compile(src, verbose, fresh=False):
     os.makedirs(BUILD, exist_ok=True)
     obj = os.path.join(BUILD, os.path.basename(src) + "." + _digest(src) + ".o")
-    if not os.path.exists(obj):
+    if fresh or not os.path.exists(obj):
         cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj + ".tmp"]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -68,10 +69,12 @@ def build_rates(verbose: bool = False) -> str:
     return RATES_OUT
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
+def build(verbose: bool = False, jobs: int = 8, fresh: bool = False) -> str:
+    """Compile (every source when `fresh`, else the ones whose content changed)
+    and link libsbp.so, then the issue-rate benchmark."""
     srcs = sources()
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+        objs = list(ex.map(lambda s: _compile(s, verbose, fresh), srcs))
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", OUT + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -82,4 +85,4 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, fresh="--fresh" in sys.argv))
