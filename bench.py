@@ -34,6 +34,7 @@ OPS_ADJ_PAIR = 26        # per pair: S0..S2, dL/dp0, dL/da, radial and directivi
 OPS_FLT_EDGE = 8         # per edge (p0 only): u, u^2 k, exp, select, one weighted sum
 OPS_FLT_PAIR = 3
 OPS_FWD_EDGE_UNIFORM = 7  # per edge, UNIFORM profile: u, u^2, a^2 - u^2, clamp, scale, difference, accumulate
+OPS_FWD_SAMPLE_POINT = 8  # per sample, point sampling: u, u^2 k, exp, u e, scale, accumulate
 VALU_PEAK = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock = 3.93e13 lane-ops/s
 
 
@@ -340,6 +341,20 @@ def suite(args):
     ops_f = B * D * (OPS_GEOMETRY + E * OPS_FWD_EDGE_UNIFORM)
     print(json.dumps({"workload": wl.name.replace("uniform2M", "uniform2M-uniformballs"), "profile": "uniform",
                       "forward_ms": tf, "adjoint_ms": tb, "fwd_adj_pairs_per_s": B * D / ((tf + tb) * 1e-3),
+                      "forward_frac_alu": ops_f / (tf * 1e-3) / VALU_PEAK}), flush=True)
+
+    # large, GAUSS balls, point samples (the pressure at the sample times)
+    model = api.Model(c=c, dt=wl.dt, T=wl.T, f=1, sampling=api.SAMPLING_POINT)
+    autotune.apply_cached(ctx, args.tuning, model, D, B)
+    st = api.State(wl.init, device=dev)
+    y = api.simulate_signals(ctx, A, st.balls, model)
+    tf, tb = fwd_adj(A, st, model, y)
+    _, t_filter = filtered(A, wl.init, model, y)
+    S = 2.0 * 5.0 * 0.15 / (c * wl.dt)          # samples strictly inside a 0.15 mm ball's support
+    ops_f = B * D * (OPS_GEOMETRY + S * OPS_FWD_SAMPLE_POINT)
+    print(json.dumps({"workload": wl.name + "-point", "profile": "gauss", "sampling": "point",
+                      "forward_ms": tf, "adjoint_ms": tb, "filter_ms": t_filter,
+                      "fwd_adj_pairs_per_s": B * D / ((tf + tb) * 1e-3),
                       "forward_frac_alu": ops_f / (tf * 1e-3) / VALU_PEAK}), flush=True)
     ctx.close()
 
