@@ -200,17 +200,18 @@ def test_point_frames_and_edge_cases(ctx):
     assert np.all(run_fwd(ctx, a1, dead, pm(50, t0=rho / 1.5 - 0.1))[0].cpu().numpy() == 0)
 
 
-def test_point_f64_twins_match_oracle_tightly(ctx):
+@pytest.mark.parametrize("directivity", [1, 0])
+def test_point_f64_twins_match_oracle_tightly(ctx, directivity):
     arr, balls = small_scene(271, nb=700, nd=9)
     T = 450
     dev = torch.device("cuda:0")
-    m = pm(T)
+    m = pm(T, directivity=directivity)
     y = api.simulate_signals_f64(ctx, to_dev(arr, dev, torch.float64), to_dev(balls, dev, torch.float64), m)
-    assert rel_l2(y[0].cpu().numpy(), oracle.simulate(balls, arr, pt(T))) <= 1e-11
+    assert rel_l2(y[0].cpu().numpy(), oracle.simulate(balls, arr, pt(T, directivity=directivity))) <= 1e-11
     v = np.random.default_rng(4).normal(size=(9, T))
     g = api.adjoint_gradients_f64(ctx, to_dev(arr, dev, torch.float64), to_dev(balls, dev, torch.float64), m,
                                   torch.as_tensor(v, device=dev).reshape(1, 9, T).contiguous())
-    gr = oracle.vjp(balls, arr, pt(T), v)
+    gr = oracle.vjp(balls, arr, pt(T, directivity=directivity), v)
     for k in PARAMS:
         assert rel_l2(g[k].cpu().numpy(), gr[k]) <= 1e-10, k
 

@@ -361,7 +361,7 @@ def _fd_vjp(b, arr, tm, v, h_rel=1e-6):
 
 
 @pytest.mark.parametrize("profile,directivity,sampling", [
-    (GAUSS, COS, BIN), (UNIFORM, COS, BIN), (GAUSS, OMNI, BIN), (GAUSS, COS, POINT)])
+    (GAUSS, COS, BIN), (UNIFORM, COS, BIN), (GAUSS, OMNI, BIN), (GAUSS, COS, POINT), (GAUSS, OMNI, POINT)])
 def test_vjp_matches_finite_differences(profile, directivity, sampling):
     rng = np.random.default_rng(21 + profile + 2 * directivity + 4 * sampling)
     b, arr = random_setup(rng, nb=4, nd=5)
