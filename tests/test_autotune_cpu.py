@@ -60,3 +60,15 @@ def test_point_sampling_has_its_own_buckets(tmp_path, monkeypatch):
                                   "gfx950|p1d1s1|D512|T2048|B262144": point})
     assert autotune.apply_cached(ctx, path, M(1, sampling=1), 1024, 2_000_000) == point   # nearest
     assert autotune.apply_cached(ctx, path, M(1), 512, 200_000) == binned
+
+
+def test_cache_file_is_reread_after_it_changes(tmp_path, monkeypatch):
+    monkeypatch.setattr(autotune, "_arch", lambda: "gfx950")
+    a = dict(autotune.DEFAULTS, fwd_dets=1)
+    b = dict(autotune.DEFAULTS, fwd_dets=8, adj_dets=8)
+    path = write_cache(tmp_path, {"gfx950|p1d1|D1024|T4096|B2097152": a})
+    ctx = FakeCtx()
+    assert autotune.apply_cached(ctx, path, M(1), 1024, 2_000_000) == a
+    assert autotune.load(path) is autotune.load(path)            # parsed once per version
+    path = write_cache(tmp_path, {"gfx950|p1d1|D1024|T4096|B2097152": b, "gfx950|p0d1|D8|T8|B8": a})
+    assert autotune.apply_cached(ctx, path, M(1), 1024, 2_000_000) == b

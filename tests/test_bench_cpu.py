@@ -1,0 +1,40 @@
+"""Host logic of bench.py: the HBM-traffic figure is read from the committed
+counter summary only while the kernel sources still hash to the value
+recorded beside it, and the edge and op counts behind the roofline."""
+import json
+import os
+import shutil
+
+import pytest
+
+import bench
+
+
+def test_traffic_is_read_while_the_source_hash_matches():
+    for k in ("forward", "adjoint", "filter"):
+        t = bench.measured_traffic(k)
+        assert t is not None and t > 0, k
+
+
+def test_traffic_is_dropped_once_a_kernel_source_changes(tmp_path, monkeypatch):
+    root = tmp_path / "repo"
+    (root / "profiles").mkdir(parents=True)
+    shutil.copy(os.path.join(bench.ROOT, "profiles", "hbm_traffic_large.md"), root / "profiles")
+    for srcs in bench.KERNEL_SOURCES.values():
+        for f in srcs:
+            (root / os.path.dirname(f)).mkdir(parents=True, exist_ok=True)
+            shutil.copy(os.path.join(bench.ROOT, f), root / f)
+    monkeypatch.setattr(bench, "ROOT", str(root))
+    assert bench.measured_traffic("forward") is not None
+    with open(root / "paper_2601_00551_amd/csrc/forward.hip", "a") as fh:
+        fh.write("\n// edited\n")
+    assert bench.measured_traffic("forward") is None
+    assert bench.measured_traffic("adjoint") is not None      # its own sources are unchanged
+    with open(root / "paper_2601_00551_amd/csrc/sbp_internal.hpp", "a") as fh:
+        fh.write("\n// edited\n")
+    assert bench.measured_traffic("adjoint") is None and bench.measured_traffic("filter") is None
+
+
+def test_edges_per_pair():
+    # a 0.15 mm GAUSS ball (support 5 a) at 40 MHz and 1.5 mm/us: 40 bins, 41 edges
+    assert bench.edges_per_pair(0.75, 1.5 * 0.025) == pytest.approx(41.0)
