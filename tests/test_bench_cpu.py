@@ -38,3 +38,11 @@ def test_traffic_is_dropped_once_a_kernel_source_changes(tmp_path, monkeypatch):
 def test_edges_per_pair():
     # a 0.15 mm GAUSS ball (support 5 a) at 40 MHz and 1.5 mm/us: 40 bins, 41 edges
     assert bench.edges_per_pair(0.75, 1.5 * 0.025) == pytest.approx(41.0)
+
+
+def test_more_than_one_gpu_is_refused():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(bench.ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in (r.stdout + r.stderr)
