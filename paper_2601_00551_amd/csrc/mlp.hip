@@ -83,7 +83,9 @@ static int launch_sync(const float *P, uint16_t *W, hipStream_t st) {
 // [64 w, 64 w + 64) for all 64 rows (4 x 4 accumulator tiles), so per k-step
 // it reads 4 A fragments from LDS and 4 B fragments (W^T rows) from global
 // memory for 16 matrix-core products, and the weights' columns are read by one
-// wave only.
+// wave only.  The next k-step's B fragments and the layer's bias values are
+// loaded ahead of use, so their latency overlaps the products (with two waves
+// per SIMD there is little else to hide it; two steps ahead gained nothing).
 template <int K>
 __device__ inline void hidden_layer(const __bf16 *__restrict__ A, int lda, const __bf16 *__restrict__ Wt,
                                     const float *__restrict__ bias, __bf16 *__restrict__ O,
@@ -96,11 +98,22 @@ __device__ inline void hidden_layer(const __bf16 *__restrict__ A, int lda, const
     for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float bb4[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) bb4[ct] = bias[c0 + ct * 16 + (l & 15)];
+    bf16x8 bn[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) bn[ct] = frag(Wt + (c0 + ct * 16 + (l & 15)) * K + (l >> 4) * 8);
 #pragma unroll 2
     for (int ks = 0; ks < K / 32; ++ks) {
         bf16x8 a[4], bq[4];
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) bq[ct] = frag(Wt + (c0 + ct * 16 + (l & 15)) * K + ks * 32 + (l >> 4) * 8);
+        for (int ct = 0; ct < 4; ++ct) bq[ct] = bn[ct];
+        if (ks + 1 < K / 32) {
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct)
+                bn[ct] = frag(Wt + (c0 + ct * 16 + (l & 15)) * K + (ks + 1) * 32 + (l >> 4) * 8);
+        }
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) a[rt] = frag(A + (rt * 16 + (l & 15)) * lda + ks * 32 + (l >> 4) * 8);
 #pragma unroll
@@ -111,7 +124,7 @@ __device__ inline void hidden_layer(const __bf16 *__restrict__ A, int lda, const
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct) {
         const int col = c0 + ct * 16 + (l & 15);
-        const float bb = bias[col];
+        const float bb = bb4[ct];
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
             bf16x4 h4;
@@ -131,7 +144,9 @@ __device__ inline void hidden_layer(const __bf16 *__restrict__ A, int lda, const
     }
 }
 
-__global__ __launch_bounds__(256, 2) void k_mlp_fwd(const float *__restrict__ P, const __bf16 *__restrict__ W,
+constexpr int kFwdThreads = 256;     // the forward's workgroup size (its loops assume it)
+
+__global__ __launch_bounds__(kFwdThreads, 2) void k_mlp_fwd(const float *__restrict__ P, const __bf16 *__restrict__ W,
                                                  const float *__restrict__ X, int64_t M, int64_t Mp,
                                                  float *__restrict__ out, __bf16 *__restrict__ acts) {
     __shared__ __align__(16) __bf16 s_x[kTM * kLdIn];
@@ -140,12 +155,24 @@ __global__ __launch_bounds__(256, 2) void k_mlp_fwd(const float *__restrict__ P,
     const int tid = threadIdx.x;
     const int wrow = (tid >> 6) * 16;
     const int64_t m_base = (int64_t)blockIdx.x * kTM;
-    // inputs -> bf16 tile (feature 31 and rows beyond M are zero)
-    for (int i = tid; i < kTM * kIn; i += blockDim.x) {
-        const int r = i / kIn, k = i % kIn;
-        const int64_t m = m_base + r;
-        const float v = (m < M && k < SBP_MLP_IN) ? X[m * SBP_MLP_IN + k] : 0.0f;
-        s_x[r * kLdIn + k] = (__bf16)v;
+    // inputs -> bf16 tile (feature 31 and rows beyond M are zero): every
+    // thread loads all its values (indices clamped into X, M >= 1) before it
+    // uses any, one latency instead of one per value
+    constexpr int kXPer = kTM * kIn / kFwdThreads;
+    float xv[kXPer];
+#pragma unroll
+    for (int j = 0; j < kXPer; ++j) {
+        const int i = tid + j * kFwdThreads;
+        const int64_t m = m_base + i / kIn;
+        const int k = i % kIn;
+        xv[j] = X[(m < M ? m : M - 1) * SBP_MLP_IN + (k < SBP_MLP_IN ? k : SBP_MLP_IN - 1)];
+    }
+#pragma unroll
+    for (int j = 0; j < kXPer; ++j) {
+        const int i = tid + j * kFwdThreads;
+        const int k = i % kIn;
+        const bool real = m_base + i / kIn < M && k < SBP_MLP_IN;
+        s_x[(i / kIn) * kLdIn + k] = (__bf16)(real ? xv[j] : 0.0f);
     }
     __syncthreads();
     if (acts)   // transposed copy for the weight gradients, rows contiguous
@@ -162,8 +189,11 @@ __global__ __launch_bounds__(256, 2) void k_mlp_fwd(const float *__restrict__ P,
     __syncthreads();
     hidden_layer<kH>(s_b, kLd, W + wW3t, P + oB3, s_a, a3, Mp, m_base, M);
     __syncthreads();
-    // output layer: one 16x16 tile per wave, columns 0..1 are real
+    // output layer: one 16x16 tile per wave, columns 0..1 are real; the bias
+    // is loaded ahead and the four results stored back to back
     const int l = tid & 63;
+    const int col = l & 15;
+    const float bb = P[oB4 + (col < SBP_MLP_OUT ? col : 0)];
     floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int ks = 0; ks < kH / 32; ++ks) {
@@ -171,14 +201,17 @@ __global__ __launch_bounds__(256, 2) void k_mlp_fwd(const float *__restrict__ P,
         const bf16x8 b = frag(W + wW4t + (l & 15) * kH + ks * 32 + (l >> 4) * 8);
         acc = mfma(a, b, acc);
     }
-    const int col = l & 15;
     if (col < SBP_MLP_OUT) {
-        const float bb = P[oB4 + col];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t m = m_base + wrow + (l >> 4) * 4 + i;
-            if (m < M) out[m * SBP_MLP_OUT + col] = acc[i] + bb;
-        }
+        const int64_t m0 = m_base + wrow + (l >> 4) * 4;
+        float o0 = acc[0] + bb, o1 = acc[1] + bb, o2 = acc[2] + bb, o3 = acc[3] + bb;
+        // four live registers: otherwise one register is refilled between the
+        // stores and each store waits for the previous one to complete
+        asm volatile("" : "+v"(o0), "+v"(o1), "+v"(o2), "+v"(o3));
+        float *po = out + m0 * SBP_MLP_OUT + col;
+        if (m0 < M) po[0] = o0;
+        if (m0 + 1 < M) po[SBP_MLP_OUT] = o1;
+        if (m0 + 2 < M) po[2 * SBP_MLP_OUT] = o2;
+        if (m0 + 3 < M) po[3 * SBP_MLP_OUT] = o3;
     }
 }
 
@@ -542,7 +575,7 @@ int sbp_mlp_forward(sbp_ctx *ctx, const float *params, const uint16_t *work, con
     if (!ctx) return fail(SBP_E_ARG, "ctx is NULL");
     if (M == 0) return SBP_OK;
     const int64_t Mp = padded(M);
-    hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)(Mp / kTM)), dim3(256), 0, (hipStream_t)stream, params,
+    hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)(Mp / kTM)), dim3(kFwdThreads), 0, (hipStream_t)stream, params,
                        (const __bf16 *)work, X, M, Mp, out, (__bf16 *)acts);
     SBP_HIP(hipGetLastError());
     return SBP_OK;
