@@ -410,7 +410,8 @@ __global__ __launch_bounds__(512, AdjMinBlocks<R>::v) void k_adjoint(ArrayP<R> a
                                                  int ds, int TT, int bpt, int nsl, int dsl,
                                                  Level lc, const R *__restrict__ v, R vscale,
                                                  uint32_t mask, BallsP<R> grad,
-                                                 R *__restrict__ part, int64_t pstride) {
+                                                 R *__restrict__ part, int64_t pstride,
+                                                 const int32_t *__restrict__ order) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     R *rows = reinterpret_cast<R *>(lds_raw);
     __shared__ int64_t s_off[SBP_MAX_FRAMES + 1];
@@ -442,11 +443,12 @@ __global__ __launch_bounds__(512, AdjMinBlocks<R>::v) void k_adjoint(ArrayP<R> a
         bool act[kMaxBpt];
 #pragma unroll
         for (int jb = 0; jb < kMaxBpt; ++jb) {
-            const int64_t i = base + (int64_t)jb * nth + tid;
-            act[jb] = jb < bpt && i < end;
+            const int64_t i0 = base + (int64_t)jb * nth + tid;
+            act[jb] = jb < bpt && i0 < end;
 #pragma unroll
             for (int k = 0; k < 5; ++k) acc[jb][k] = R(0);
             if (act[jb]) {
+                const int64_t i = order ? (int64_t)order[i0] : i0;
                 b[jb] = load_ball<R, PROF>(balls.x[i], balls.y[i], balls.z[i], balls.p0[i],
                                            balls.a[i], lc);
                 act[jb] = b[jb].live;
@@ -486,8 +488,9 @@ __global__ __launch_bounds__(512, AdjMinBlocks<R>::v) void k_adjoint(ArrayP<R> a
         }
 #pragma unroll
         for (int jb = 0; jb < kMaxBpt; ++jb) {
-            const int64_t i = base + (int64_t)jb * nth + tid;
-            if (!(jb < bpt && i < end)) continue;
+            const int64_t i0 = base + (int64_t)jb * nth + tid;
+            if (!(jb < bpt && i0 < end)) continue;
+            const int64_t i = order ? (int64_t)order[i0] : i0;
             // dead balls (a <= 0) get exact zeros
             if (part) {
                 if (FULL) {
@@ -583,7 +586,7 @@ template <typename R, int PROF, int DIR, bool FULL>
 static int run_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
                        const int64_t *ball_off, int F, int64_t B_cap, const Level &lc, const R *v,
                        R vscale, uint32_t mask, const BallsP<R> &grad, void *ws, size_t ws_bytes,
-                       hipStream_t st) {
+                       hipStream_t st, const int32_t *order) {
     auto kern = k_adjoint<R, PROF, DIR, FULL>;
     const size_t reserve = 2 * (SBP_MAX_FRAMES + 1) * sizeof(int64_t) + 256;
     const size_t avail = c->lds_max > reserve ? c->lds_max - reserve : 0;
@@ -618,7 +621,8 @@ static int run_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
     if (grid > max_items) grid = (int)max_items;
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, arr, balls, ball_off, F, ds,
-                       (int)TT, pl.bpt, pl.nsl, pl.dsl, lc, v, vscale, mask, grad, part, B_cap);
+                       (int)TT, pl.bpt, pl.nsl, pl.dsl, lc, v, vscale, mask, grad, part, B_cap,
+                       order);
     SBP_HIP(hipGetLastError());
     if (part) {
         int64_t nb = (B_cap + 255) / 256;
@@ -634,48 +638,49 @@ template <typename R, bool FULL>
 static int dispatch_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
                             const int64_t *ball_off, int F, int64_t B_cap, const sbp_model *m,
                             const R *v, R vscale, uint32_t mask, const BallsP<R> &grad, void *ws,
-                            size_t ws_bytes, hipStream_t st) {
+                            size_t ws_bytes, hipStream_t st, const int32_t *order) {
     const Level lc = make_level(m);
     if (profile_code(m) == GPOINT) {
         if (m->directivity == SBP_DIR_COS)
             return run_adjoint<R, GPOINT, COS, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v,
-                                                     vscale, mask, grad, ws, ws_bytes, st);
+                                                     vscale, mask, grad, ws, ws_bytes, st, order);
         return run_adjoint<R, GPOINT, OMNI, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v, vscale,
-                                                  mask, grad, ws, ws_bytes, st);
+                                                  mask, grad, ws, ws_bytes, st, order);
     }
     if (m->profile == SBP_PROFILE_GAUSS) {
         if (m->directivity == SBP_DIR_COS)
             return run_adjoint<R, GAUSS, COS, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v,
-                                                    vscale, mask, grad, ws, ws_bytes, st);
+                                                    vscale, mask, grad, ws, ws_bytes, st, order);
         return run_adjoint<R, GAUSS, OMNI, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v, vscale,
-                                                 mask, grad, ws, ws_bytes, st);
+                                                 mask, grad, ws, ws_bytes, st, order);
     }
     if (m->directivity == SBP_DIR_COS)
         return run_adjoint<R, UNIFORM, COS, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v, vscale,
-                                                  mask, grad, ws, ws_bytes, st);
+                                                  mask, grad, ws, ws_bytes, st, order);
     return run_adjoint<R, UNIFORM, OMNI, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v, vscale,
-                                               mask, grad, ws, ws_bytes, st);
+                                               mask, grad, ws, ws_bytes, st, order);
 }
 
 template <typename R>
 int launch_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
                    int F, int64_t B_cap, const sbp_model *m, const R *v, R vscale,
-                   uint32_t mask, const BallsP<R> &grad, void *ws, size_t ws_bytes, hipStream_t st) {
+                   uint32_t mask, const BallsP<R> &grad, void *ws, size_t ws_bytes, hipStream_t st,
+                   const int32_t *order) {
     if (B_cap == 0) return SBP_OK;
     if ((mask & ~SBP_P0) == 0)
         return dispatch_adjoint<R, false>(c, arr, balls, ball_off, F, B_cap, m, v, vscale, mask,
-                                          grad, ws, ws_bytes, st);
+                                          grad, ws, ws_bytes, st, order);
     return dispatch_adjoint<R, true>(c, arr, balls, ball_off, F, B_cap, m, v, vscale, mask, grad,
-                                     ws, ws_bytes, st);
+                                     ws, ws_bytes, st, order);
 }
 
 template int launch_adjoint<float>(Ctx *, const ArrayP<float> &, const BallsP<float> &,
                                    const int64_t *, int, int64_t, const sbp_model *, const float *,
                                    float, uint32_t, const BallsP<float> &, void *, size_t,
-                                   hipStream_t);
+                                   hipStream_t, const int32_t *);
 template int launch_adjoint<double>(Ctx *, const ArrayP<double> &, const BallsP<double> &,
                                     const int64_t *, int, int64_t, const sbp_model *,
                                     const double *, double, uint32_t, const BallsP<double> &,
-                                    void *, size_t, hipStream_t);
+                                    void *, size_t, hipStream_t, const int32_t *);
 
 }  // namespace sbp

@@ -414,16 +414,26 @@ int sbp_filter_zero_grad(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *in
     if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
     if ((rc = set_device(ctx->c))) return rc;
     // scratch: [filter gradient (if g_out is NULL)][compaction workspace][adjoint slices]
+    //          [visiting order]
     const size_t g_bytes = g_out ? 0 : (((size_t)B_cap * sizeof(float) + 255) & ~(size_t)255);
     const size_t c_bytes = (compact_ws_bytes(B_cap) + 255) & ~(size_t)255;
-    const size_t a_bytes = adjoint_ws_bytes(&ctx->c, arr->D, B_cap, F, SBP_P0, sizeof(float));
-    if ((rc = ensure_scratch(&ctx->c, g_bytes + c_bytes + a_bytes))) return rc;
+    const size_t a_bytes =
+        (adjoint_ws_bytes(&ctx->c, arr->D, B_cap, F, SBP_P0, sizeof(float)) + 255) & ~(size_t)255;
+    const size_t o_bytes = order_ws_bytes(F, B_cap);
+    if ((rc = ensure_scratch(&ctx->c, g_bytes + c_bytes + a_bytes + o_bytes))) return rc;
     float *g = g_out ? g_out : (float *)ctx->c.scratch;
     void *ws = (char *)ctx->c.scratch + g_bytes;
     hipStream_t st = (hipStream_t)stream;
+    // the p0-only gradient visits the balls cell by cell (same values, fewer
+    // LDS bank conflicts and divergent lanes)
+    int32_t *order = nullptr;
+    if (o_bytes &&
+        (rc = launch_order((char *)ws + c_bytes + a_bytes, ballsp<float>(in), off_in, F, B_cap,
+                           &order, st)))
+        return rc;
     BallsP<float> gp{nullptr, nullptr, nullptr, g, nullptr};
     rc = launch_adjoint<float>(&ctx->c, arrp<float>(arr), ballsp<float>(in), off_in, F, B_cap, model,
-                               y_ref, -2.0f, SBP_P0, gp, (char *)ws + c_bytes, a_bytes, st);
+                               y_ref, -2.0f, SBP_P0, gp, (char *)ws + c_bytes, a_bytes, st, order);
     if (rc) return rc;
     BallsP<float> mi, vi, mo, vo;
     if (any_mom) {

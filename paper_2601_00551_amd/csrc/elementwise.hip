@@ -382,4 +382,162 @@ int launch_compact(void *ws, const float *g, int strict, const BallsP<float> &in
     return SBP_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Spatial visiting order of a cloud.  The gather-form kernels give each lane
+// its own balls and sum every ball's terms in a fixed order, so the order in
+// which balls are assigned to lanes changes no result; it does change speed:
+// when a wave's balls are neighbours their times of flight are close, the
+// staged-row reads of one instruction fall on nearby LDS addresses (fewer
+// bank conflicts) and the directivity and window tests agree across the wave.
+// order[off[0] + k], k = 0 .. count-1, lists the balls of every frame sorted
+// by (frame, Morton code of a 2^bits-per-axis cell grid over the cloud's
+// bounding box); within a cell the order is whatever the atomics produce.
+constexpr int kOrdBoxBlocks = 256;
+constexpr int kOrdMaxKeys = 1 << 17;
+
+__global__ void k_ord_box(const BallsP<float> b, const int64_t *__restrict__ off, int F,
+                          float *__restrict__ part) {
+    __shared__ float s[6][kEw];
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const int64_t i0 = off[0], i1 = off[F];
+    for (int64_t i = i0 + (int64_t)blockIdx.x * kEw + threadIdx.x; i < i1;
+         i += (int64_t)gridDim.x * kEw) {
+        const float v[3] = {b.x[i], b.y[i], b.z[i]};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fminf(lo[k], v[k]);
+            hi[k] = fmaxf(hi[k], v[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        s[k][threadIdx.x] = lo[k];
+        s[3 + k][threadIdx.x] = hi[k];
+    }
+    __syncthreads();
+    for (int w = kEw / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                s[k][threadIdx.x] = fminf(s[k][threadIdx.x], s[k][threadIdx.x + w]);
+                s[3 + k][threadIdx.x] = fmaxf(s[3 + k][threadIdx.x], s[3 + k][threadIdx.x + w]);
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__device__ inline int ord_spread(int v, int bits) {
+    int r = 0;
+    for (int k = 0; k < bits; ++k) r |= ((v >> k) & 1) << (3 * k);
+    return r;
+}
+
+// Key of every ball (frame * 8^bits + Morton cell) and the per-key counts.
+__global__ void k_ord_key(const BallsP<float> b, const int64_t *__restrict__ off, int F, int bits,
+                          const float *__restrict__ part, int *__restrict__ key,
+                          int *__restrict__ cnt) {
+    __shared__ float s_box[6];
+    __shared__ int64_t s_off[SBP_MAX_FRAMES + 1];
+    if (threadIdx.x < 6) {
+        const bool mx = threadIdx.x >= 3;
+        float r = mx ? -INFINITY : INFINITY;
+        for (int j = 0; j < kOrdBoxBlocks; ++j) {
+            const float v = part[j * 6 + threadIdx.x];
+            r = mx ? fmaxf(r, v) : fminf(r, v);
+        }
+        s_box[threadIdx.x] = r;
+    }
+    for (int f = threadIdx.x; f <= F; f += kEw) s_off[f] = off[f];
+    __syncthreads();
+    const int n = 1 << bits;
+    float lo[3], sc[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = s_box[k];
+        const float ext = s_box[3 + k] - s_box[k];
+        sc[k] = ext > 0.0f ? (float)n / ext : 0.0f;
+    }
+    const int64_t i0 = s_off[0], i1 = s_off[F];
+    for (int64_t i = i0 + (int64_t)blockIdx.x * kEw + threadIdx.x; i < i1;
+         i += (int64_t)gridDim.x * kEw) {
+        int f = 0;
+        while (f + 1 < F && i >= s_off[f + 1]) ++f;
+        const float v[3] = {b.x[i], b.y[i], b.z[i]};
+        int m = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            // NaN and out-of-range coordinates land in an edge cell
+            const float q = fminf(fmaxf((v[k] - lo[k]) * sc[k], 0.0f), (float)(n - 1));
+            m |= ord_spread((int)q, bits) << k;
+        }
+        const int kk = (f << (3 * bits)) | m;
+        key[i - i0] = kk;
+        atomicAdd(&cnt[kk], 1);
+    }
+}
+
+__global__ void k_ord_scatter(const int64_t *__restrict__ off, int F, const int *__restrict__ key,
+                              unsigned long long *__restrict__ cursor, int32_t *__restrict__ order) {
+    const int64_t i0 = off[0], i1 = off[F];
+    for (int64_t i = i0 + (int64_t)blockIdx.x * kEw + threadIdx.x; i < i1;
+         i += (int64_t)gridDim.x * kEw) {
+        const unsigned long long pos = atomicAdd(&cursor[key[i - i0]], 1ull);
+        order[i0 + (int64_t)pos] = (int32_t)i;
+    }
+}
+
+int order_bits(int F, int64_t B_cap) {
+    if (F < 1 || B_cap < 1 || B_cap > INT32_MAX) return -1;
+    // about one wave of balls per cell, at most 2^17 keys in all
+    const double per = (double)B_cap / F / 64.0;
+    int bits = per > 1.0 ? (int)lround(log2(per) / 3.0) : 0;
+    if (bits > 5) bits = 5;
+    while (bits > 0 && ((int64_t)F << (3 * bits)) > kOrdMaxKeys) --bits;
+    return bits < 1 ? -1 : bits;
+}
+
+size_t order_ws_bytes(int F, int64_t B_cap) {
+    const int bits = order_bits(F, B_cap);
+    if (bits < 0) return 0;
+    const int64_t nk = (int64_t)F << (3 * bits);
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    return up((size_t)B_cap * 4) * 2 + up((size_t)nk * 4) + up((size_t)(nk + 1) * 8) +
+           up((size_t)kOrdBoxBlocks * 6 * 4);
+}
+
+int launch_order(void *ws, const BallsP<float> &b, const int64_t *off, int F, int64_t B_cap,
+                 int32_t **order, hipStream_t st) {
+    *order = nullptr;
+    const int bits = order_bits(F, B_cap);
+    if (bits < 0) return SBP_OK;
+    const int64_t nk = (int64_t)F << (3 * bits);
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    char *p = (char *)ws;
+    int32_t *ord = (int32_t *)p;
+    p += up((size_t)B_cap * 4);
+    int *key = (int *)p;
+    p += up((size_t)B_cap * 4);
+    int *cnt = (int *)p;
+    p += up((size_t)nk * 4);
+    int64_t *pre = (int64_t *)p;
+    p += up((size_t)(nk + 1) * 8);
+    float *part = (float *)p;
+    int rc;
+    if ((rc = launch_fill<int>(cnt, nk, 0, st))) return rc;
+    hipLaunchKernelGGL(k_ord_box, dim3(kOrdBoxBlocks), dim3(kEw), 0, st, b, off, F, part);
+    SBP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_ord_key, dim3(ew_grid(B_cap)), dim3(kEw), 0, st, b, off, F, bits,
+                       (const float *)part, key, cnt);
+    SBP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, st, (const int *)cnt, (int)nk, pre);
+    SBP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_ord_scatter, dim3(ew_grid(B_cap)), dim3(kEw), 0, st, off, F,
+                       (const int *)key, (unsigned long long *)pre, ord);
+    SBP_HIP(hipGetLastError());
+    *order = ord;
+    return SBP_OK;
+}
+
 }  // namespace sbp

@@ -219,7 +219,8 @@ size_t adjoint_ws_bytes(const Ctx *c, int D, int64_t B_cap, int F, uint32_t mask
 template <typename R>
 int launch_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
                    int F, int64_t B_cap, const sbp_model *m, const R *v, R vscale,
-                   uint32_t mask, const BallsP<R> &grad, void *ws, size_t ws_bytes, hipStream_t st);
+                   uint32_t mask, const BallsP<R> &grad, void *ws, size_t ws_bytes, hipStream_t st,
+                   const int32_t *order = nullptr);
 
 template <typename R>
 int launch_fill(R *p, int64_t n, R value, hipStream_t st);
@@ -237,6 +238,12 @@ int launch_compact(void *ws, const float *g, int strict, const BallsP<float> &in
                    int64_t *off_out, const BallsP<float> *m_in, const BallsP<float> *v_in,
                    const BallsP<float> *m_out, const BallsP<float> *v_out, hipStream_t st);
 int launch_incr(int32_t *p, hipStream_t st);
+// Spatial visiting order for the gather-form kernels (elementwise.hip):
+// order[off[0] + k] lists the frames' balls cell by cell; *order is set to
+// NULL (visit in storage order) when the cloud is too large for int32 indices.
+size_t order_ws_bytes(int F, int64_t B_cap);
+int launch_order(void *ws, const BallsP<float> &b, const int64_t *off, int F, int64_t B_cap,
+                 int32_t **order, hipStream_t st);
 int launch_reparam(float *a, float *m, float *v, const int64_t *ball_off, int F, int64_t B_cap,
                    int to_softplus, hipStream_t st);
 int launch_grow(Ctx *c, const sbp_state *in, const sbp_growth_rule *rule, sbp_state *out,

@@ -459,6 +459,38 @@ def test_filter_frames(ctx):
         assert np.array_equal(out[k][:oo[-1]].cpu().numpy(), balls[k][kept])
 
 
+@pytest.mark.parametrize("profile,directivity", COMBOS)
+def test_filter_visiting_order_changes_no_bit(ctx, profile, directivity):
+    """The filter visits the balls cell by cell (a spatial order built per
+    call), the adjoint in storage order; each ball's sum is the same either way,
+    so the filter's g is -2 times the p0-only adjoint of y_ref bit for bit
+    (frames of 3000, 0, 700 and 1 balls; then one frame of 900 balls at a
+    single point, a degenerate bounding box, plus a dead ball)."""
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(141 + profile + 2 * directivity)
+    arr = synth.hemisphere_array(23, 12.0, rng, tilt_deg=20)
+    m = gmodel(450, profile=profile, directivity=directivity)
+    parts = [synth.uniform_balls(rng, n, 4.0, 0.15, 0.0, 0.2) for n in (3000, 0, 700, 1)]
+    point = synth.uniform_balls(rng, 900, 4.0, 0.15, 0.0, 0.2)
+    for k in ("x", "y", "z"):
+        point[k][:] = point[k][0]
+    point["a"][5] = 0.0
+    cases = [(synth.concat_balls(parts), np.cumsum([0] + [len(p["x"]) for p in parts])),
+             (point, np.array([0, 900]))]
+    for balls, off in cases:
+        F = len(off) - 1
+        y_ref = rng.normal(size=(F, 23, 450)).astype(np.float32) * 1e-3
+        _, _, g, _ = api.filter_zero_grad(ctx, to_dev(arr, dev), to_dev(balls, dev), m,
+                                          torch.as_tensor(y_ref, device=dev),
+                                          ball_off=torch.tensor(off, device=dev))
+        ga = api.adjoint_gradients(ctx, to_dev(arr, dev), to_dev(balls, dev), m,
+                                   torch.as_tensor(y_ref, device=dev), mask=api.P0,
+                                   ball_off=torch.tensor(off, device=dev))
+        gf = g.cpu().numpy()
+        assert np.array_equal(gf, np.float32(-2.0) * ga["p0"].cpu().numpy())
+        assert np.count_nonzero(gf) > len(gf) // 4
+
+
 def test_grow_matches_oracle(ctx):
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(131)
