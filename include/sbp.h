@@ -271,6 +271,9 @@ int sbp_adjoint_gradients(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *b
  * offsets.  g_out (nullable, [B_cap]) receives g.  mom_in/mom_out (both
  * nullable; if one is given the other must be) compact the Adam moments the
  * same way.  `out` must not overlap `in`.  Capacity of `out`: B_cap.
+ * g is formed with the balls visited in a spatial order (a counting sort by
+ * Morton cell, built per call in the context's scratch, about 8 bytes per
+ * ball of B_cap); each g_i equals the storage-order value bit for bit.
  * Errors: SBP_E_ARG, SBP_E_DOMAIN, SBP_E_HIP, SBP_E_NOMEM. */
 int sbp_filter_zero_grad(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *in,
                          const int64_t *off_in, int32_t F, int64_t B_cap, const sbp_model *model,
