@@ -30,8 +30,15 @@
  *     thread-local message readable with sbp_last_error().  Arguments are
  *     validated on the host BEFORE anything is enqueued, in the order: pointers
  *     and sizes, model fields, then the context; so a failed call enqueues
- *     nothing.  NaN inputs propagate to NaN outputs; there are no device-side
- *     checks.  A context is used by one host thread and one stream at a time
+ *     nothing.
+ *   Non-finite ball parameters (invalid input): a ball whose stored x, y, z,
+ *     p0 or a (a~ under softplus) is NaN or infinite makes every sample of its
+ *     frame NaN in sbp_simulate_signals (and its _f64 twin); its gradients are
+ *     NaN in sbp_adjoint_gradients; sbp_filter_zero_grad gives it g = NaN and
+ *     drops it.  Other frames and balls are computed as if it were absent
+ *     (their fixed-point quantum included).  A non-finite cotangent value
+ *     reaches the gradients of the balls whose pulse covers it.
+ *   A context is used by one host thread and one stream at a time
  *     (its scratch memory is shared by the calls made through it); a captured
  *     graph owns its own workspace and may run on another stream.
  */
@@ -227,12 +234,14 @@ int sbp_decimate(sbp_ctx *ctx, const float *y, int64_t R, int32_t T, int32_t f,
  * pressure p0_i D_id u_n fhat(u_n) / (2 rho_id) itself, |u_n| < K a; the
  * adjoint and the filter follow the same model.
  * y is [F][D][model->T]; it is overwritten unless accumulate = 1.  Every bin
- * value is rounded to a multiple of a per-call power-of-two quantum (at most
- * 2^-31 of the largest possible bin value) and the multiples are summed
- * exactly, so the result is bitwise reproducible however the work is split.
- * The error is absolute: a ball whose bins are 10^k times smaller than the
- * bound (max |p0| a over the call's balls, taken at the support edge) keeps
- * about 31 - 3.3 k significant bits per bin.
+ * value is rounded to a multiple of a per-call power-of-two quantum q and the
+ * multiples are summed exactly, so the result is bitwise reproducible however
+ * the work is split.  q is the power of two with bound / 2^30 < q <= bound /
+ * 2^29, bound = max over the call's finite balls of |p0| a / (2 K c dt_k)
+ * (GAUSS bin means; |p0| a / (4 c dt_k) UNIFORM, |p0| / (2 K) point samples),
+ * the largest value any one ball can add to a sample.  The error is absolute:
+ * below two quanta per ball reaching a sample, so a ball whose bins are 10^k
+ * times smaller than the bound keeps about 29 - 3.3 k significant bits.
  * The context's scratch holds 8 bytes per output sample during the call.
  * Errors: SBP_E_ARG, SBP_E_DOMAIN, SBP_E_HIP, SBP_E_NOMEM. */
 int sbp_simulate_signals(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *balls,

@@ -108,10 +108,20 @@ def _array64(arr):
     return [_f64(arr[k]) for k in ("qx", "qy", "qz", "nx", "ny", "nz")]
 
 
+def _finite_balls(b) -> np.ndarray:
+    """Per ball: every one of x, y, z, p0, a is finite."""
+    ok = np.ones(b[0].shape[0], dtype=bool)
+    for a in b:
+        ok &= np.isfinite(a)
+    return ok
+
+
 def simulate(balls, array, tm: Time, det_idx=None) -> np.ndarray:
     """Simulated signals y[D][T_k] (or rows ``det_idx`` only), FP64.
 
-    Inputs may be FP32; they are widened to FP64 exactly.
+    Inputs may be FP32; they are widened to FP64 exactly.  Invalid input (a
+    convention of the library's interface, which the paper does not cover): if
+    any ball has a non-finite parameter, every sample is NaN.
     """
     b = _balls64(balls)
     q = _array64(array)
@@ -124,6 +134,9 @@ def simulate(balls, array, tm: Time, det_idx=None) -> np.ndarray:
         R = idx.shape[0]
     y = np.zeros((R, tm.T), dtype=np.float64)
     ct = _ctime(tm)
+    if not np.all(_finite_balls(b)):
+        y[:] = np.nan
+        return y
     _lib().orc_simulate(B, *[_ptr(a) for a in b], D, *[_ptr(a) for a in q], ctypes.byref(ct),
                         R, None if idx is None else _ptr(idx), _ptr(y))
     return y
@@ -132,7 +145,9 @@ def simulate(balls, array, tm: Time, det_idx=None) -> np.ndarray:
 def vjp(balls, array, tm: Time, v, ball_idx=None) -> dict:
     """Vector-Jacobian product: for each selected ball, sum_{d,n} v[d,n] dy[d,n]/dtheta.
 
-    Returns a dict of FP64 arrays keyed by x, y, z, p0, a.
+    Returns a dict of FP64 arrays keyed by x, y, z, p0, a.  A ball with a
+    non-finite parameter gets NaN in all five (interface convention for invalid
+    input, as in :func:`simulate`).
     """
     b = _balls64(balls)
     q = _array64(array)
@@ -149,6 +164,10 @@ def vjp(balls, array, tm: Time, v, ball_idx=None) -> dict:
     ct = _ctime(tm)
     _lib().orc_vjp(B, *[_ptr(a) for a in b], D, *[_ptr(a) for a in q], ctypes.byref(ct), _ptr(v),
                    J, None if idx is None else _ptr(idx), _ptr(g))
+    bad = ~_finite_balls(b)
+    if bad.any():
+        sel = np.arange(B) if idx is None else idx
+        g[:, bad[sel]] = np.nan
     return {k: g[i] for i, k in enumerate(PARAMS)}
 
 
@@ -186,13 +205,19 @@ def filter_zero_grad(balls, array, tm: Time, y_ref, strict: bool = True):
     propagate to g_i = dL/dp0_i, keep balls with g_i < 0 (strict, Algorithm 1;
     g_i <= 0 when ``strict`` is False, the equations of section 4.2), restore the
     saved p0 of the kept balls.  Returns (keep mask, g, compacted balls).
+
+    Invalid input (interface convention): a ball with a non-finite parameter
+    gets g = NaN and is dropped; the others are filtered as if it were absent.
     """
     saved = _f64(balls["p0"]).copy()
     zeroed = {k: _f64(balls[k]) for k in PARAMS}
     zeroed["p0"] = np.zeros_like(saved)
-    y_sim = simulate(zeroed, array, tm)
+    fin = _finite_balls(_balls64(balls))
+    sub = {k: zeroed[k][fin] for k in PARAMS}
+    y_sim = simulate(sub, array, tm)
     _, v = residual_loss(y_sim, y_ref)
-    g = vjp(zeroed, array, tm, v)["p0"]
+    g = np.full(len(saved), np.nan)
+    g[fin] = vjp(sub, array, tm, v)["p0"]
     keep = g < 0.0 if strict else g <= 0.0
     out = {k: np.asarray(balls[k])[keep] for k in PARAMS}
     out["p0"] = saved[keep]

@@ -491,7 +491,14 @@ __global__ __launch_bounds__(512, AdjMinBlocks<R>::v) void k_adjoint(ArrayP<R> a
             const int64_t i0 = base + (int64_t)jb * nth + tid;
             if (!(jb < bpt && i0 < end)) continue;
             const int64_t i = order ? (int64_t)order[i0] : i0;
-            // dead balls (a <= 0) get exact zeros
+            // dead balls (a <= 0) get exact zeros, balls with a non-finite
+            // parameter NaN
+            {
+                if (!ball_finite(balls.x[i], balls.y[i], balls.z[i], balls.p0[i], balls.a[i])) {
+#pragma unroll
+                    for (int k = 0; k < 5; ++k) acc[jb][k] = R(__builtin_nan(""));
+                }
+            }
             if (part) {
                 if (FULL) {
 #pragma unroll

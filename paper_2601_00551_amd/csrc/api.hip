@@ -196,13 +196,13 @@ static int check_tuning(const sbp_tuning *t) {
 // One iteration, shared by sbp_step and the graph capture.
 static int step_body(Ctx *c, const sbp_array *arr, sbp_state *s, const sbp_model *model,
                      const float *y_ref, float *y_work, const sbp_adam_params *p,
-                     const int32_t *step_dev, double *loss, double *partial, unsigned *bound,
+                     const int32_t *step_dev, double *loss, double *partial, unsigned *misc,
                      void *fwd_ws, size_t fwd_ws_bytes, void *adj_ws, size_t adj_ws_bytes,
                      hipStream_t st) {
     const ArrayP<float> a = arrp<float>(arr);
     const BallsP<float> b = ballsp<float>(&s->balls);
     const BallsP<float> g = ballsp<float>(&s->grad);
-    int rc = launch_forward<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 0, bound,
+    int rc = launch_forward<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 0, misc,
                                    fwd_ws, fwd_ws_bytes, st);
     if (rc) return rc;
     const int64_t n = (int64_t)arr->D * model->T;
@@ -240,7 +240,7 @@ int sbp_ctx_create(sbp_ctx **out, int device) {
     if (prop.maxSharedMemoryPerMultiProcessor > lds) lds = prop.maxSharedMemoryPerMultiProcessor;
     ctx->c.lds_max = lds;
     ctx->c.tuning = sbp_tuning{4, 512, 4, 0, 4, 512, 4, 0, 0, 0};
-    if (hipMalloc((void **)&ctx->c.misc, 256) != hipSuccess) {
+    if (hipMalloc((void **)&ctx->c.misc, kMiscBytes) != hipSuccess) {
         (void)hipGetLastError();
         delete ctx;
         return fail(SBP_E_NOMEM, "could not allocate the context's device words");
@@ -342,7 +342,8 @@ int sbp_simulate_signals_f64(sbp_ctx *ctx, const sbp_array_f64 *arr, const sbp_b
     if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
     if ((rc = set_device(ctx->c))) return rc;
     return launch_forward<double>(&ctx->c, arrp<double>(arr), ballsp<double>(balls), ball_off, F,
-                                  B_cap, model, y, accumulate, nullptr, nullptr, 0, (hipStream_t)stream);
+                                  B_cap, model, y, accumulate, ctx->c.misc, nullptr, 0,
+                                  (hipStream_t)stream);
 }
 
 int sbp_residual_loss(sbp_ctx *ctx, const float *y_sim, const float *y_ref, int64_t n_per_frame,
@@ -496,11 +497,11 @@ int sbp_step_graph_create(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state,
     hipStream_t st = (hipStream_t)stream;
     sbp_graph *g = new sbp_graph();
     g->device = ctx->c.device;
-    // graph workspace: [residual partial sums][bound word][forward integer sums][adjoint slices]
+    // graph workspace: [residual partial sums][device words][forward integer sums][adjoint slices]
     const size_t ws_res = (residual_ws_bytes(state->F) + 255) & ~(size_t)255;
     const size_t ws_fwd = forward_ws_bytes(state->F, arr->D, model->T, sizeof(float));
     const size_t ws_adj = adjoint_ws_bytes(&ctx->c, arr->D, state->B_cap, state->F, p->mask, sizeof(float));
-    if (hipMalloc(&g->ws, ws_res + 256 + ws_fwd + ws_adj) != hipSuccess) {
+    if (hipMalloc(&g->ws, ws_res + kMiscBytes + ws_fwd + ws_adj) != hipSuccess) {
         delete g;
         (void)hipGetLastError();
         return fail(SBP_E_NOMEM, "could not allocate the graph workspace");
@@ -515,8 +516,8 @@ int sbp_step_graph_create(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state,
     for (int it = 0; it < iters && body == SBP_OK; ++it) {
         body = step_body(&ctx->c, arr, state, model, y_ref, y_work, p, step_dev,
                          loss + (int64_t)it * state->F, (double *)g->ws,
-                         (unsigned *)((char *)g->ws + ws_res), (char *)g->ws + ws_res + 256, ws_fwd,
-                         (char *)g->ws + ws_res + 256 + ws_fwd, ws_adj, st);
+                         (unsigned *)((char *)g->ws + ws_res), (char *)g->ws + ws_res + kMiscBytes,
+                         ws_fwd, (char *)g->ws + ws_res + kMiscBytes + ws_fwd, ws_adj, st);
         if (body == SBP_OK) body = launch_incr(step_dev, st);
     }
     e = hipStreamEndCapture(st, &g->graph);

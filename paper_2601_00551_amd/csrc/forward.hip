@@ -53,25 +53,60 @@ template <> struct FwdAcc<double> {
 
 // max over live balls of |p0| * a (a after softplus; |p0| alone under point
 // sampling, where the peak pressure does not scale with a), as float bits in
-// *slot (zeroed before the launch; non-negative floats order like their bits).
+// misc[kMiscBound] (zeroed before the launch; non-negative floats order like
+// their bits).  A ball with a non-finite parameter (or bound term) sets its
+// frame's flag misc[kMiscFlags + f] instead, so that the other frames keep a
+// finite quantum and the flagged frames are written as NaN.
 __global__ void k_amp_bound(BallsP<float> balls, const int64_t *__restrict__ ball_off, int F,
-                            int a_softplus, int point, unsigned *slot) {
+                            int a_softplus, int point, unsigned *misc) {
     __shared__ float s_red[8];
-    const int64_t count = ball_off[F];
+    __shared__ int64_t s_off[SBP_MAX_FRAMES + 1];
+    for (int i = threadIdx.x; i <= F; i += blockDim.x) s_off[i] = ball_off[i];
+    __syncthreads();
+    const int64_t count = s_off[F];
     float m = 0.0f;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x) {
-        float a = balls.a[i];
-        if (a_softplus) a = softplus_dev(a);
-        if (a > 0.0f) m = fmaxf(m, point ? fabsf(balls.p0[i]) : fabsf(balls.p0[i]) * a);
+        const float p = balls.p0[i];
+        const float ar = balls.a[i];
+        const float a = a_softplus ? softplus_dev(ar) : ar;
+        const float t = point ? fabsf(p) : fabsf(p) * a;
+        if (!ball_finite(balls.x[i], balls.y[i], balls.z[i], p, ar) || !isfinite(t)) {
+            atomicOr(misc + kMiscFlags + frame_of(s_off, F, i), 1u);
+            continue;
+        }
+        if (a > 0.0f) m = fmaxf(m, t);
     }
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_down(m, o, 64));
     if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = m;
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, s_red[w]);
-        atomicMax(slot, __float_as_uint(m));
+        atomicMax(misc + kMiscBound, __float_as_uint(m));
     }
+}
+
+// FP64 twin: the per-frame flags only (the FP64 rows need no quantum).
+__global__ void k_nonfinite_flags(BallsP<double> balls, const int64_t *__restrict__ ball_off, int F,
+                                  unsigned *misc) {
+    __shared__ int64_t s_off[SBP_MAX_FRAMES + 1];
+    for (int i = threadIdx.x; i <= F; i += blockDim.x) s_off[i] = ball_off[i];
+    __syncthreads();
+    const int64_t count = s_off[F];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (!ball_finite(balls.x[i], balls.y[i], balls.z[i], balls.p0[i], balls.a[i]))
+            atomicOr(misc + kMiscFlags + frame_of(s_off, F, i), 1u);
+    }
+}
+
+// FP64 twin: every sample of a flagged frame becomes NaN (grid.y = frame).
+__global__ void k_poison_frames(const unsigned *__restrict__ misc, int64_t nper, double *__restrict__ y) {
+    if (misc[kMiscFlags + blockIdx.y] == 0) return;
+    double *yf = y + (int64_t)blockIdx.y * nper;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nper;
+         i += (int64_t)gridDim.x * blockDim.x)
+        yf[i] = __builtin_nan("");
 }
 
 // Bins per unrolled block of the FP32 loops (the FP64 twin keeps the plain
@@ -334,15 +369,19 @@ __device__ inline float fixed_scale(const unsigned *slot, int profile, const Lev
     return ldexpf(1.0f, k);
 }
 
-// y = (accumulate ? y : 0) + q * sum, for every sample of the launch.
-__global__ void k_fwd_convert(const unsigned long long *__restrict__ gacc, int64_t n,
-                              const unsigned *__restrict__ bound, int profile, Level lc,
+// y = (accumulate ? y : 0) + q * sum, for every sample of the launch (grid.y =
+// frame); a flagged frame gets NaN.
+__global__ void k_fwd_convert(const unsigned long long *__restrict__ gacc, int64_t nper,
+                              const unsigned *__restrict__ misc, int profile, Level lc,
                               int accumulate, float *__restrict__ y) {
-    const float inv_scale = 1.0f / fixed_scale(bound, profile, lc);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+    const bool bad = misc[kMiscFlags + blockIdx.y] != 0;
+    const float inv_scale = 1.0f / fixed_scale(misc + kMiscBound, profile, lc);
+    const unsigned long long *g = gacc + (int64_t)blockIdx.y * nper;
+    float *yf = y + (int64_t)blockIdx.y * nper;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nper;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const float v = FwdAcc<float>::value(gacc[i], inv_scale);
-        y[i] = accumulate ? y[i] + v : v;
+        const float v = bad ? __builtin_nanf("") : FwdAcc<float>::value(g[i], inv_scale);
+        yf[i] = accumulate ? yf[i] + v : v;
     }
 }
 
@@ -476,9 +515,10 @@ size_t forward_ws_bytes(int F, int D, int T, size_t elem) {
 template <typename R>
 int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
                    int F, int64_t B_cap, const sbp_model *m, R *y, int accumulate,
-                   unsigned *bound_slot, void *ws, size_t ws_bytes, hipStream_t st) {
+                   unsigned *misc, void *ws, size_t ws_bytes, hipStream_t st) {
     const Level lc = make_level(m);
-    const int64_t ns = (int64_t)F * arr.D * m->T;
+    const int64_t nper = (int64_t)arr.D * m->T;
+    const int64_t ns = (int64_t)F * nper;
     if (B_cap == 0 || sizeof(R) != sizeof(float)) {
         if (!accumulate) {
             int rc = launch_fill<R>(y, ns, R(0), st);
@@ -486,26 +526,33 @@ int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const i
         }
         if (B_cap == 0) return SBP_OK;
     }
+    if (!misc) return fail(SBP_E_ARG, "forward needs the context's device words");
+    // bound word and frame flags start at zero
+    int rc = launch_fill<int32_t>((int32_t *)misc, kMiscFlags + SBP_MAX_FRAMES, 0, st);
+    if (rc) return rc;
+    int64_t nbb = (B_cap + 255) / 256;
+    if (nbb > 1024) nbb = 1024;
     unsigned long long *gacc = nullptr;
     const unsigned *bound = nullptr;
     if (sizeof(R) == sizeof(float)) {
         if (!ws || ws_bytes < (size_t)ns * sizeof(unsigned long long))
             return fail(SBP_E_NOMEM, "forward workspace too small");
         gacc = (unsigned long long *)ws;
-        int rc = launch_fill<uint64_t>((uint64_t *)gacc, ns, 0, st);
+        rc = launch_fill<uint64_t>((uint64_t *)gacc, ns, 0, st);
         if (rc) return rc;
-        rc = launch_fill<int32_t>((int32_t *)bound_slot, 1, 0, st);
-        if (rc) return rc;
-        int64_t nb = (B_cap + 255) / 256;
-        if (nb > 1024) nb = 1024;
-        hipLaunchKernelGGL(k_amp_bound, dim3((int)nb), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_amp_bound, dim3((int)nbb), dim3(256), 0, st,
                            BallsP<float>{(float *)balls.x, (float *)balls.y, (float *)balls.z,
                                          (float *)balls.p0, (float *)balls.a},
-                           ball_off, F, m->a_softplus, (int)(profile_code(m) == GPOINT), bound_slot);
+                           ball_off, F, m->a_softplus, (int)(profile_code(m) == GPOINT), misc);
         SBP_HIP(hipGetLastError());
-        bound = bound_slot;
+        bound = misc + kMiscBound;
+    } else {
+        hipLaunchKernelGGL(k_nonfinite_flags, dim3((int)nbb), dim3(256), 0, st,
+                           BallsP<double>{(double *)balls.x, (double *)balls.y, (double *)balls.z,
+                                          (double *)balls.p0, (double *)balls.a},
+                           ball_off, F, misc);
+        SBP_HIP(hipGetLastError());
     }
-    int rc;
     if (profile_code(m) == GPOINT) {
         if (m->directivity == SBP_DIR_COS)
             rc = run_forward<R, GPOINT, COS>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, gacc, st);
@@ -522,11 +569,17 @@ int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const i
         else
             rc = run_forward<R, UNIFORM, OMNI>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, gacc, st);
     }
-    if (rc || !gacc) return rc;
-    int64_t nb = (ns + 255) / 256;
-    if (nb > 4096) nb = 4096;
-    hipLaunchKernelGGL(k_fwd_convert, dim3((int)nb), dim3(256), 0, st, (const unsigned long long *)gacc,
-                       ns, bound, profile_code(m), lc, accumulate, (float *)y);
+    if (rc) return rc;
+    int64_t nb = (nper + 255) / 256;
+    if (nb > 4096 / F) nb = 4096 / F > 0 ? 4096 / F : 1;
+    if (!gacc) {
+        hipLaunchKernelGGL(k_poison_frames, dim3((int)nb, F), dim3(256), 0, st, (const unsigned *)misc,
+                           nper, (double *)y);
+        SBP_HIP(hipGetLastError());
+        return SBP_OK;
+    }
+    hipLaunchKernelGGL(k_fwd_convert, dim3((int)nb, F), dim3(256), 0, st, (const unsigned long long *)gacc,
+                       nper, (const unsigned *)misc, profile_code(m), lc, accumulate, (float *)y);
     SBP_HIP(hipGetLastError());
     return SBP_OK;
 }

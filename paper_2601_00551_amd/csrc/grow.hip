@@ -58,15 +58,6 @@ __device__ inline int ordered_key(float x) {
 }
 __device__ inline float ordered_val(int k) { return __int_as_float(k >= 0 ? k : (k ^ 0x7fffffff)); }
 
-__device__ inline int frame_of(const int64_t *s_off, int F, int64_t i) {
-    int lo = 0, hi = F - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_off[mid] <= i) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 __device__ inline double dup_key(const GrowIn &in, int64_t i) {
     const double gx = in.gx[i], gy = in.gy[i], gz = in.gz[i];
     double k = gx * gx + gy * gy;

@@ -296,7 +296,7 @@ int sbp_features(sbp_ctx *ctx, const sbp_grid *grid, const float *mass, const sb
     if (!ctx) return fail(SBP_E_ARG, "ctx is NULL");
     if (M == 0) return SBP_OK;
     hipStream_t st = (hipStream_t)stream;
-    unsigned *scales = ctx->c.misc + 4;
+    unsigned *scales = ctx->c.misc + kMiscScales;
     int rc = launch_fill<int32_t>((int32_t *)scales, 3, 0, st);
     if (rc) return rc;
     const int64_t ncell = (int64_t)grid->nx * grid->ny * grid->nz;

@@ -180,8 +180,39 @@ struct Ctx {
     sbp_tuning tuning{};
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
-    unsigned *misc = nullptr;  // 256 persistent bytes: the forward's per-launch bound
+    unsigned *misc = nullptr;  // kMiscBytes persistent bytes (layout below)
 };
+
+// Persistent device words of a context (and of a captured graph): word
+// kMiscBound holds the forward's fixed-point bound, words kMiscScales.. the
+// proposal features' three scales, words kMiscFlags + f one flag per frame
+// (set when a ball of frame f has a non-finite parameter).
+constexpr size_t kMiscBytes = 512;
+constexpr int kMiscBound = 0;
+constexpr int kMiscScales = 4;
+constexpr int kMiscFlags = 64;
+static_assert((kMiscFlags + SBP_MAX_FRAMES) * sizeof(unsigned) <= kMiscBytes, "misc words");
+
+// A ball with a non-finite stored parameter (centre, peak, or the size array
+// as stored, a or a~) poisons its frame: the forward writes NaN to every
+// sample of that frame and the adjoint writes NaN to every gradient of that
+// ball.
+template <typename R>
+__device__ inline bool ball_finite(R x, R y, R z, R p, R a) {
+    return isfinite(x) && isfinite(y) && isfinite(z) && isfinite(p) && isfinite(a);
+}
+
+// Frame of ball i given the frame offsets (off[0] <= i < off[F]): the largest
+// f with off[f] <= i (empty frames are skipped over).
+__device__ inline int frame_of(const int64_t *off, int F, int64_t i) {
+    int lo = 0, hi = F;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
 
 int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
@@ -204,13 +235,14 @@ struct BallsP {
     R *x, *y, *z, *p0, *a;
 };
 
-// bound_slot: one device word the FP32 path uses for its fixed-point quantum;
-// ws: its per-sample integer sums (forward_ws_bytes; none for FP64).
+// misc: kMiscBytes of device words (the fixed-point bound of the FP32 path and
+// the per-frame non-finite flags); ws: the FP32 path's per-sample integer sums
+// (forward_ws_bytes; none for FP64).
 size_t forward_ws_bytes(int F, int D, int T, size_t elem);
 template <typename R>
 int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
                    int F, int64_t B_cap, const sbp_model *m, R *y, int accumulate,
-                   unsigned *bound_slot, void *ws, size_t ws_bytes, hipStream_t st);
+                   unsigned *misc, void *ws, size_t ws_bytes, hipStream_t st);
 
 // vscale multiplies v (the filter passes y_ref with vscale = -2).  ws holds the
 // per-slice partial gradients when the launch splits the transducers into

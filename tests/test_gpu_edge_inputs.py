@@ -1,0 +1,163 @@
+"""Inputs at the edges of the forward's number range, against the oracle.
+
+* Wide dynamic range: peak pressures spanning four decades in one call.  The
+  FP32 forward rounds every bin value to a multiple of one per-call quantum q
+  (a power of two with q <= 2^-29 of the largest possible edge value, the
+  bound max |p0| a / (2 K c dt) for GAUSS bin means), so a sample's error is at
+  most a couple of quanta per ball that reaches it, however dim those balls.
+* Non-finite parameters (the interface's convention for invalid input): a ball
+  with a NaN or infinite stored centre, peak or size (a, or a~ under softplus)
+  makes every sample of its frame NaN, gets NaN gradients, and is dropped by
+  the filter; the other frames and balls are unaffected (in particular an
+  infinite peak does not coarsen the other frames' quantum).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from _util import PARAMS, gmodel, otime, rel_l2, to_dev
+from paper_2601_00551_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx(gpu):
+    c = api.Context(0)
+    yield c
+    c.close()
+
+
+def contributions(balls, arr, tm):
+    """Number of balls whose support reaches each bin, [D][T] (brute force)."""
+    D, T = len(arr["qx"]), tm.T
+    cnt = np.zeros((D, T), dtype=np.int64)
+    cdt = tm.c * tm.dt * tm.f
+    x = [np.asarray(balls[k], dtype=np.float64) for k in ("x", "y", "z")]
+    w = tm.K * np.asarray(balls["a"], dtype=np.float64)
+    for d in range(D):
+        rho = np.sqrt((x[0] - arr["qx"][d]) ** 2 + (x[1] - arr["qy"][d]) ** 2 + (x[2] - arr["qz"][d]) ** 2)
+        lo = np.floor((rho - w - tm.c * tm.t0) / cdt).astype(np.int64)
+        hi = np.floor((rho + w - tm.c * tm.t0) / cdt).astype(np.int64)
+        for a_, b_ in zip(np.clip(lo, 0, T), np.clip(hi + 1, 0, T)):
+            cnt[d, a_:b_] += 1
+    return cnt
+
+
+def test_forward_wide_dynamic_range(ctx):
+    """p0 over four decades: bright balls in one corner, dim ones elsewhere,
+    so that many samples hold dim pulses only."""
+    rng = np.random.default_rng(4040)
+    arr = synth.hemisphere_array(10, 14.0, rng, tilt_deg=15.0)
+    bright = synth.uniform_balls(rng, 40, 1.0, 0.15)
+    bright["z"] = (bright["z"] + 3.0).astype(np.float32)
+    bright["p0"] = rng.uniform(0.5, 1.0, 40).astype(np.float32)
+    dim = synth.uniform_balls(rng, 3000, 3.0, 0.15)
+    dim["z"] = (dim["z"] - 3.0).astype(np.float32)
+    dim["p0"] = (10.0 ** rng.uniform(-4.0, -3.0, 3000)).astype(np.float32)
+    balls = synth.concat_balls([bright, dim])
+    T = 900
+    tm = otime(T)
+    y = to_np(api.simulate_signals(ctx, to_dev(arr, dev()), to_dev(balls, dev()), gmodel(T)))[0]
+    ref = oracle.simulate(balls, arr, tm)
+    assert rel_l2(y, ref) <= 1e-5
+    # the quantum the header documents
+    bound = float(np.max(np.abs(balls["p0"]).astype(np.float64) * balls["a"])) / (2 * tm.K * tm.c * tm.dt)
+    q = 2.0 ** (np.frexp(bound)[1] - 30)
+    assert q <= 2.0 ** -29 * bound
+    n_b = contributions(bright, arr, tm)
+    n_d = contributions(dim, arr, tm)
+    dim_only = (n_b == 0) & (n_d > 0)
+    assert dim_only.sum() > 2000
+    err = np.abs(y - ref)
+    assert np.all(err[dim_only] <= 2.0 * n_d[dim_only] * q + 1e-7 * np.abs(ref[dim_only]))
+    # dim-only samples on their own: still well inside the signal tolerance
+    assert rel_l2(y[dim_only], ref[dim_only]) <= 1e-4
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def nonfinite_scene():
+    rng = np.random.default_rng(777)
+    arr = synth.hemisphere_array(12, 12.0, rng, tilt_deg=20.0)
+    parts = [synth.uniform_balls(rng, n, 3.0, 0.15) for n in (300, 250, 280, 310, 260)]
+    parts[1]["p0"][17] = np.nan
+    parts[2]["x"][3] = np.nan
+    parts[3]["p0"][100] = np.inf
+    parts[4]["a"][0] = -np.inf
+    balls = synth.concat_balls(parts)
+    off = np.cumsum([0] + [len(p["x"]) for p in parts])
+    return rng, arr, balls, off
+
+
+@pytest.mark.parametrize("softplus", [0, 1])
+def test_nonfinite_balls_poison_their_frame_only(ctx, softplus):
+    rng, arr, balls, off = nonfinite_scene()
+    F, T = len(off) - 1, 400
+    b = dict(balls)
+    if softplus:
+        with np.errstate(invalid="ignore"):
+            b["a"] = oracle.softplus_inv(balls["a"]).astype(np.float32)
+        b["a"][off[4]] = -np.inf    # the stored a~ is what must be finite
+    toff = torch.as_tensor(off, device=dev())
+    m = gmodel(T, a_softplus=softplus)
+    y = to_np(api.simulate_signals(ctx, to_dev(arr, dev()), to_dev(b, dev()), m, ball_off=toff))
+    v = rng.normal(size=(F, 12, T)).astype(np.float32)
+    g = api.adjoint_gradients(ctx, to_dev(arr, dev()), to_dev(b, dev()), m,
+                              torch.as_tensor(v, device=dev()), ball_off=toff)
+    g = {k: to_np(t) for k, t in g.items()}
+    for f in range(F):
+        part = {k: balls[k][off[f]:off[f + 1]] for k in PARAMS}
+        ref = oracle.simulate(part, arr, otime(T))
+        if f == 0:
+            assert np.all(np.isfinite(y[0])) and rel_l2(y[0], ref) <= 1e-5
+        else:
+            assert np.all(np.isnan(y[f])) and np.all(np.isnan(ref)), f
+        rg = oracle.vjp(part, arr, otime(T), v[f])
+        bad = ~np.isfinite(rg["p0"])
+        assert bad.sum() == (0 if f == 0 else 1), f
+        for k in PARAMS:
+            gk = g[k][off[f]:off[f + 1]]
+            if softplus and k == "a":
+                ok = ~bad
+                rg_a = rg["a"][ok] * oracle.sigmoid(b["a"][off[f]:off[f + 1]][ok])
+                assert rel_l2(gk[ok], rg_a) <= 1e-4, (f, k)
+            else:
+                assert rel_l2(gk[~bad], rg[k][~bad]) <= 1e-4, (f, k)
+            assert np.all(np.isnan(gk[bad])), (f, k)
+    # the FP64 twin follows the same convention
+    y64 = to_np(api.simulate_signals_f64(ctx, to_dev(arr, dev(), torch.float64),
+                                         to_dev(b, dev(), torch.float64), m, ball_off=toff))
+    assert np.all(np.isfinite(y64[0])) and np.all(np.isnan(y64[1:]))
+
+
+def test_nonfinite_balls_are_filtered_out(ctx):
+    rng, arr, balls, off = nonfinite_scene()
+    F, T = len(off) - 1, 400
+    gt = synth.uniform_balls(rng, 200, 3.0, 0.15)
+    y_ref = oracle.simulate(gt, arr, otime(T)).astype(np.float32)
+    toff = torch.as_tensor(off, device=dev())
+    yr = torch.as_tensor(np.stack([y_ref] * F), device=dev())
+    out, off_out, g, _ = api.filter_zero_grad(ctx, to_dev(arr, dev()), to_dev(balls, dev()), gmodel(T), yr,
+                                              ball_off=toff)
+    g = to_np(g)
+    counts = []
+    for f in range(F):
+        part = {k: balls[k][off[f]:off[f + 1]] for k in PARAMS}
+        keep, go, _ = oracle.filter_zero_grad(part, arr, otime(T), y_ref)
+        gf = g[off[f]:off[f + 1]]
+        fin = np.isfinite(go)
+        assert np.array_equal(np.isnan(gf), ~fin), f
+        assert rel_l2(gf[fin], go[fin]) <= 1e-4, f
+        band = np.abs(go[fin]) <= 1e-6 * np.abs(go[fin]).max()
+        assert np.array_equal((gf[fin] < 0)[~band], keep[fin][~band]), f
+        assert not keep[~fin].any()
+        counts.append(int((gf < 0).sum()))
+    assert list(to_np(off_out)) == list(np.cumsum([0] + counts))
