@@ -43,9 +43,9 @@ def edges_per_pair(a_sup, cdt):
     return 2.0 * a_sup / cdt + 1.0
 
 
-KERNEL_SOURCES = {"k_forward": ("paper_2601_00551_amd/csrc/forward.hip", "paper_2601_00551_amd/csrc/sbp_internal.hpp"),
+KERNEL_SOURCES = {"k_forward_gz": ("paper_2601_00551_amd/csrc/forward.hip", "paper_2601_00551_amd/csrc/sbp_internal.hpp"),
                   "k_adjoint": ("paper_2601_00551_amd/csrc/adjoint.hip", "paper_2601_00551_amd/csrc/sbp_internal.hpp")}
-KERNEL_NAMES = {"forward": "k_forward<float, 1, 1>", "adjoint": "k_adjoint<float, 1, 1, true>",
+KERNEL_NAMES = {"forward": "k_forward_gz<1>", "adjoint": "k_adjoint<float, 1, 1, true>",
                 "filter": "k_adjoint<float, 1, 1, false>"}
 
 

@@ -233,16 +233,21 @@ int sbp_decimate(sbp_ctx *ctx, const float *y, int64_t R, int32_t T, int32_t f,
  * Under model->sampling = SBP_SAMPLING_POINT (GAUSS) sample n is instead the
  * pressure p0_i D_id u_n fhat(u_n) / (2 rho_id) itself, |u_n| < K a; the
  * adjoint and the filter follow the same model.
- * y is [F][D][model->T]; it is overwritten unless accumulate = 1.  Every bin
- * value is rounded to a multiple of a per-call power-of-two quantum q and the
- * multiples are summed exactly, so the result is bitwise reproducible however
- * the work is split.  q is the power of two with bound / 2^30 < q <= bound /
- * 2^29, bound = max over the call's finite balls of |p0| a / (2 K c dt_k)
- * (GAUSS bin means; |p0| a / (4 c dt_k) UNIFORM, |p0| / (2 K) point samples),
- * the largest value any one ball can add to a sample.  The error is absolute:
- * below two quanta per ball reaching a sample, so a ball whose bins are 10^k
- * times smaller than the bound keeps about 29 - 3.3 k significant bits.
- * The context's scratch holds 8 bytes per output sample during the call.
+ * y is [F][D][model->T]; it is overwritten unless accumulate = 1.  Every
+ * value a ball adds is rounded to the nearest multiple of a per-call
+ * power-of-two quantum q and the multiples are summed exactly, so the result
+ * is bitwise reproducible however the work is split.  The values are bin
+ * values (UNIFORM), point samples, or, for GAUSS bin means, the pulse's
+ * antiderivative at the bin edges (a sample is then the difference of its two
+ * edges' sums).  q is the power of two with bound / 2^30 < q <= bound / 2^29,
+ * bound = max over the call's finite balls of |p0| a / (2 K c dt_k) (GAUSS;
+ * |p0| a / (4 c dt_k) UNIFORM, |p0| / (2 K) point samples), the largest value
+ * any one ball can add.  The rounding error is absolute and unbiased: at most
+ * half a quantum per ball reaching a sample (one quantum for GAUSS bin means,
+ * two roundings), so a ball whose values are 10^k times smaller than the
+ * bound keeps about 29 - 3.3 k significant bits.
+ * The context's scratch holds 8 bytes per output sample (plus one per
+ * transducer row) and 24 bytes per ball of B_cap during the call.
  * Errors: SBP_E_ARG, SBP_E_DOMAIN, SBP_E_HIP, SBP_E_NOMEM. */
 int sbp_simulate_signals(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *balls,
                          const int64_t *ball_off, int32_t F, int64_t B_cap,

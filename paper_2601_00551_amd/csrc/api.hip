@@ -323,7 +323,7 @@ int sbp_simulate_signals(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *ba
     if (accumulate != 0 && accumulate != 1) return fail(SBP_E_ARG, "accumulate must be 0 or 1");
     if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
     if ((rc = set_device(ctx->c))) return rc;
-    const size_t wsb = forward_ws_bytes(F, arr->D, model->T, sizeof(float));
+    const size_t wsb = forward_ws_bytes(F, arr->D, model->T, B_cap, sizeof(float));
     if ((rc = ensure_scratch(&ctx->c, wsb))) return rc;
     return launch_forward<float>(&ctx->c, arrp<float>(arr), ballsp<float>(balls), ball_off, F,
                                  B_cap, model, y, accumulate, ctx->c.misc, ctx->c.scratch, wsb,
@@ -470,7 +470,7 @@ int sbp_step(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state, const sbp_mod
     if ((rc = set_device(ctx->c))) return rc;
     // scratch: [residual partial sums][forward integer sums][adjoint slices]
     const size_t r_bytes = (residual_ws_bytes(state->F) + 255) & ~(size_t)255;
-    const size_t f_bytes = forward_ws_bytes(state->F, arr->D, model->T, sizeof(float));
+    const size_t f_bytes = forward_ws_bytes(state->F, arr->D, model->T, state->B_cap, sizeof(float));
     const size_t a_bytes = adjoint_ws_bytes(&ctx->c, arr->D, state->B_cap, state->F, p->mask, sizeof(float));
     if ((rc = ensure_scratch(&ctx->c, r_bytes + f_bytes + a_bytes))) return rc;
     char *sc = (char *)ctx->c.scratch;
@@ -499,7 +499,7 @@ int sbp_step_graph_create(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state,
     g->device = ctx->c.device;
     // graph workspace: [residual partial sums][device words][forward integer sums][adjoint slices]
     const size_t ws_res = (residual_ws_bytes(state->F) + 255) & ~(size_t)255;
-    const size_t ws_fwd = forward_ws_bytes(state->F, arr->D, model->T, sizeof(float));
+    const size_t ws_fwd = forward_ws_bytes(state->F, arr->D, model->T, state->B_cap, sizeof(float));
     const size_t ws_adj = adjoint_ws_bytes(&ctx->c, arr->D, state->B_cap, state->F, p->mask, sizeof(float));
     if (hipMalloc(&g->ws, ws_res + kMiscBytes + ws_fwd + ws_adj) != hipSuccess) {
         delete g;

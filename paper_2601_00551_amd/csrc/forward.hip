@@ -10,16 +10,19 @@
 //
 // LDS accumulation.  gfx950 serialises LDS FP32 atomic adds (about 0.3 lanes
 // per clock per CU, against ~7 for 64-bit integer adds), so the FP32 path
-// accumulates in exact 64-bit fixed point: each bin value is truncated to an
+// accumulates in exact 64-bit fixed point: each bin value is rounded to an
 // integer multiple of a power-of-two quantum q = 2^-k chosen per launch from
 // a bound on |bin value| over all balls (|p0| a / (2 K c dt) for GAUSS,
 // |p0| a / (4 c dt) for UNIFORM, using rho > support half-width), so that a
 // single value never exceeds 2^30 q.  Flushed rows are added, still as
 // integers, to a global int64 accumulator per sample, which one pass turns
 // into FP32 at the end: every sum is exact, so the signals do not depend on
-// how the work was split or scheduled (bitwise reproducible).  The per-value
-// error is below q <= 2^-30 of that bound.  The FP64 path keeps
-// FP64 rows (LDS FP64 adds are not serialised) and flushes with FP64 atomics.
+// how the work was split or scheduled (bitwise reproducible).  Each value is
+// rounded to the nearest multiple of q (q <= 2^-29 of that bound): at most
+// q / 2 per value, with no bias, so the errors of the many balls that reach a
+// sample add like a random walk instead of in one direction.  The FP64 path
+// keeps FP64 rows (LDS FP64 adds are not serialised) and flushes with FP64
+// atomics.
 //
 // Work items are (frame, transducer group, time tile, chunk of block*bpt
 // balls) in that order.  A persistent workgroup takes one contiguous range of
@@ -38,7 +41,10 @@ template <typename R> struct FwdAcc;
 template <> struct FwdAcc<float> {
     using T = unsigned long long;
     __device__ static void add(T *p, float v_scaled) {
-        const int iv = (int)v_scaled;   // toward zero: |error| < one quantum
+        // to the nearest integer, floor(v + 1/2), in one instruction: |error|
+        // <= half a quantum, without the bias truncation toward zero has
+        int iv;
+        asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(iv) : "v"(v_scaled));
         atomicAdd(p, (unsigned long long)(long long)iv);
     }
     __device__ static float value(T s, float inv_scale) {
@@ -457,6 +463,293 @@ __global__ __launch_bounds__(512, 4) void k_forward(ArrayP<R> arr, BallsP<R> bal
     if (cur_f >= 0) flush_rows<R>(rows, dg, TT, T, cur_gt / nt, cur_gt % nt, D, cur_f, y, gacc);
 }
 
+// ---------------------------------------------------------------------------
+// GAUSS bin means in FP32: edge form.
+//
+// Sample n of a pair is p0 G (psi(u_n) - psi(u_{n+1})) with G = D / (2 rho c
+// dt_k), so a transducer's row is the difference of neighbouring entries of
+// its edge row W_m = -sum_i p0_i G_i psi_i(u_m), m = 0 .. T:
+//     y_n = W_{n+1} - W_n.
+// A pair adds one value per edge strictly inside its support,
+//     W = p0 a^2 G (e - e_K),  e = 2^(q0 u^2),  e_K = exp(-K^2 / 2),
+// which is >= 0 for p0 >= 0.  The values are rounded to the nearest multiple
+// of the same quantum as the bin values (|W| <= |p0| a^2 / (2 rho c dt_k),
+// below the bound since rho > K a) and summed exactly; the last pass takes the
+// differences exactly on the integers.  Per edge this is the exponent (two
+// FMAs), one exp2, one FMA, the conversion and one LDS add: two operations
+// fewer than a bin value (a difference and its sign word), and one LDS add
+// fewer per pair.  When no ball of a wave has p0 < 0 the 64-bit value needs no
+// sign word.  Each sample carries two roundings per ball instead of one.
+//
+// The per-ball constants come from one pass over the cloud (k_fwd_prep),
+// which also takes the fixed-point bound and the non-finite flags, so the
+// pair loop reads six floats per ball and computes no size-dependent constant.
+struct FwdPrepP {
+    float *x, *y, *z, *w, *q0, *pa2;
+};
+
+constexpr int kPrepBlock = 256;
+
+// w = K a (the support half-width, rounded from the FP64 product),
+// q0 = -log2(e) / (2 a^2), pa2 = p0 a^2; a ball that adds nothing (a <= 0,
+// p0 = 0) or has a non-finite parameter gets pa2 = 0, and the latter flags
+// its frame.  misc[kMiscBound] receives max |p0| a over the finite live balls
+// (zeroed before the launch).
+__global__ __launch_bounds__(kPrepBlock) void k_fwd_prep(BallsP<float> balls,
+                                                         const int64_t *__restrict__ ball_off,
+                                                         int F, Level lc, unsigned *misc,
+                                                         FwdPrepP out) {
+    __shared__ float s_red[kPrepBlock / 64];
+    __shared__ int64_t s_off[SBP_MAX_FRAMES + 1];
+    for (int i = threadIdx.x; i <= F; i += blockDim.x) s_off[i] = ball_off[i];
+    __syncthreads();
+    const int64_t count = s_off[F];
+    float m = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float x = balls.x[i], y = balls.y[i], z = balls.z[i];
+        const float p = balls.p0[i];
+        const float ar = balls.a[i];
+        const float a = lc.a_softplus ? softplus_dev(ar) : ar;
+        const float t = fabsf(p) * a;
+        float w = 0.0f, q0 = 0.0f, pa2 = 0.0f;
+        if (!ball_finite(x, y, z, p, ar) || !isfinite(t) || !isfinite(p * a * a)) {
+            atomicOr(misc + kMiscFlags + frame_of(s_off, F, i), 1u);
+        } else if (a > 0.0f) {
+            m = fmaxf(m, t);
+            w = (float)(lc.K_d * (double)a);
+            q0 = -1.4426950408889634f / (2.0f * a * a);
+            pa2 = p * a * a;
+        }
+        out.x[i] = x;
+        out.y[i] = y;
+        out.z[i] = z;
+        out.w[i] = w;
+        out.q0[i] = q0;
+        out.pa2[i] = pa2;
+    }
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_down(m, o, 64));
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, s_red[w]);
+        atomicMax(misc + kMiscBound, __float_as_uint(m));
+    }
+}
+
+// Adds an edge value (already scaled) to an LDS row entry.  NN: the value is
+// known to be > -1/2, so its nearest integer is >= 0 and the high word is 0.
+template <bool NN>
+__device__ inline void edge_add(unsigned long long *p, float v) {
+    int iv;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(iv) : "v"(v));
+    if (NN)
+        atomicAdd(p, (unsigned long long)(unsigned)iv);
+    else
+        atomicAdd(p, (unsigned long long)(long long)iv);
+}
+
+// N consecutive inside edges from u = ub: edge k has exponent
+// q0 (ub - k c)^2 = X0 + k (X1 + k X2) and adds namp (e_k - e_K).
+template <bool NN, int N>
+__device__ inline void gz_edges(unsigned long long *p, float ub, float q0, float X2, float Y1,
+                                float namp, float nampK) {
+    const float X0 = q0 * ub * ub;
+    const float X1 = Y1 * ub;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const float X = k == 0 ? X0 : fmaf((float)k, fmaf((float)k, X2, X1), X0);
+        edge_add<NN>(p + k, fmaf(namp, __builtin_amdgcn_exp2f(X), nampK));
+    }
+}
+
+// Adds the pair's inside edges that fall in the tile [tlo, thi) to
+// row[m - tlo]; `scale` is the inverse of the fixed-point quantum.
+template <int DIR, bool NN>
+__device__ inline void gz_pair(float bx, float by, float bz, float w, float q0, float pa2,
+                               float qx, float qy, float qz, float nx, float ny, float nz,
+                               const Level &lc, int tlo, int thi, float scale,
+                               unsigned long long *__restrict__ row) {
+    PairG<float> g;
+    if (!pair_geometry<float, DIR>(bx, by, bz, w, qx, qy, qz, nx, ny, nz, lc, g)) return;
+    // edges strictly inside the support: floor((s - w) / c dt) + 1 .. floor((s + w) / c dt)
+    const double lo = fmax(floor((g.s - (double)w) * lc.inv_cdt) + 1.0, (double)tlo);
+    const double hi = fmin(floor((g.s + (double)w) * lc.inv_cdt), (double)(thi - 1));
+    if (!(lo <= hi)) return;
+    int m = (int)lo;
+    int cnt = (int)hi - m + 1;
+    const float namp = pa2 * g.dir * lc.inv2cdt * g.inv_rho * scale;
+    const float nampK = -namp * lc.eK;
+    const float c = lc.cdt_f;
+    const float X2 = q0 * c * c;
+    const float Y1 = -2.0f * q0 * c;
+    unsigned long long *p = row - tlo + m;
+    // blocks of eight edges, the block's first offset formed exactly (FP64
+    // difference, FP32 result), then the remainder as blocks of 4, 2 and 1
+    for (; cnt >= 8; cnt -= 8, p += 8, m += 8)
+        gz_edges<NN, 8>(p, (float)(g.s - (double)m * lc.cdt), q0, X2, Y1, namp, nampK);
+    if (cnt & 4) {
+        gz_edges<NN, 4>(p, (float)(g.s - (double)m * lc.cdt), q0, X2, Y1, namp, nampK);
+        p += 4;
+        m += 4;
+    }
+    if (cnt & 2) {
+        gz_edges<NN, 2>(p, (float)(g.s - (double)m * lc.cdt), q0, X2, Y1, namp, nampK);
+        p += 2;
+        m += 2;
+    }
+    if (cnt & 1) gz_edges<NN, 1>(p, (float)(g.s - (double)m * lc.cdt), q0, X2, Y1, namp, nampK);
+}
+
+// The edge-form forward: work items and flushes as in k_forward, over edge
+// rows of T + 1 entries.
+template <int DIR>
+__global__ __launch_bounds__(512, 4) void k_forward_gz(ArrayP<float> arr, FwdPrepP pb,
+                                                       const int64_t *__restrict__ ball_off, int F,
+                                                       int G, int dg, int TT, int nt, int bpt,
+                                                       Level lc, const unsigned *__restrict__ bound,
+                                                       unsigned long long *__restrict__ gacc) {
+    using A = unsigned long long;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    A *rows = reinterpret_cast<A *>(lds_raw);
+    __shared__ int64_t s_off[SBP_MAX_FRAMES + 1];
+    __shared__ int64_t s_ipre[SBP_MAX_FRAMES + 1];
+    const int tid = threadIdx.x;
+    const int nth = blockDim.x;
+    const int TE = lc.T + 1;
+    const int64_t CH = (int64_t)nth * bpt;
+    const int64_t GT = (int64_t)G * nt;
+    const float scale = fixed_scale(bound, GAUSS, lc);
+    for (int i = tid; i <= F; i += nth) s_off[i] = ball_off[i];
+    for (int i = tid; i < dg * TT; i += nth) rows[i] = A(0);
+    __syncthreads();
+    if (tid == 0) {
+        s_ipre[0] = 0;
+        for (int f = 0; f < F; ++f) {
+            const int64_t nb = s_off[f + 1] - s_off[f];
+            s_ipre[f + 1] = s_ipre[f] + ((nb + CH - 1) / CH) * GT;
+        }
+    }
+    __syncthreads();
+    const int64_t I = s_ipre[F];
+    const int64_t i0 = I * (int64_t)blockIdx.x / gridDim.x;
+    const int64_t i1 = I * (int64_t)(blockIdx.x + 1) / gridDim.x;
+    const int D = arr.D;
+    int f = 0, cur_f = -1, cur_gt = -1;
+    for (int64_t it = i0; it < i1; ++it) {
+        while (it >= s_ipre[f + 1]) ++f;
+        const int64_t nch = (s_ipre[f + 1] - s_ipre[f]) / GT;
+        const int64_t local = it - s_ipre[f];
+        const int gt = __builtin_amdgcn_readfirstlane((int)(local / nch));
+        const int64_t ck = local - (int64_t)gt * nch;
+        if (f != cur_f || gt != cur_gt) {
+            if (cur_f >= 0)
+                flush_rows<float>(rows, dg, TT, TE, cur_gt / nt, cur_gt % nt, D, cur_f, nullptr, gacc);
+            cur_f = f;
+            cur_gt = gt;
+        }
+        const int g = gt / nt;
+        const int tlo = (gt - g * nt) * TT;
+        const int thi = min(tlo + TT, TE);
+        const int64_t base = s_off[f] + ck * CH;
+        const int64_t end = min(base + CH, s_off[f + 1]);
+        for (int jb = 0; jb < bpt; ++jb) {
+            const int64_t i = base + (int64_t)jb * nth + tid;
+            float bx = 0.0f, by = 0.0f, bz = 0.0f, w = 0.0f, q0 = 0.0f, pa2 = 0.0f;
+            if (i < end) {
+                bx = pb.x[i];
+                by = pb.y[i];
+                bz = pb.z[i];
+                w = pb.w[i];
+                q0 = pb.q0[i];
+                pa2 = pb.pa2[i];
+            }
+            const bool nn = __all(pa2 >= 0.0f);   // wave-uniform
+            if (pa2 == 0.0f) continue;
+            for (int dl = 0; dl < dg; ++dl) {
+                const int d = __builtin_amdgcn_readfirstlane(g * dg + dl);
+                if (d >= D) break;
+                A *row = rows + (int64_t)dl * TT;
+                if (nn)
+                    gz_pair<DIR, true>(bx, by, bz, w, q0, pa2, arr.qx[d], arr.qy[d], arr.qz[d],
+                                       arr.nx[d], arr.ny[d], arr.nz[d], lc, tlo, thi, scale, row);
+                else
+                    gz_pair<DIR, false>(bx, by, bz, w, q0, pa2, arr.qx[d], arr.qy[d], arr.qz[d],
+                                        arr.nx[d], arr.ny[d], arr.nz[d], lc, tlo, thi, scale, row);
+            }
+        }
+    }
+    if (cur_f >= 0) flush_rows<float>(rows, dg, TT, TE, cur_gt / nt, cur_gt % nt, D, cur_f, nullptr, gacc);
+}
+
+// y[f][d][n] = (accumulate ? y : 0) + q (W[f][d][n+1] - W[f][d][n]); a flagged
+// frame gets NaN.  grid.y = frame, workgroups stride over the transducers.
+__global__ void k_fwd_convert_edges(const unsigned long long *__restrict__ gacc, int D, int T,
+                                    const unsigned *__restrict__ misc, Level lc, int accumulate,
+                                    float *__restrict__ y) {
+    const bool bad = misc[kMiscFlags + blockIdx.y] != 0;
+    const float inv_scale = 1.0f / fixed_scale(misc + kMiscBound, GAUSS, lc);
+    for (int d = blockIdx.x; d < D; d += gridDim.x) {
+        const int64_t r = (int64_t)blockIdx.y * D + d;
+        const unsigned long long *w = gacc + r * (T + 1);
+        float *yr = y + r * T;
+        for (int n = threadIdx.x; n < T; n += blockDim.x) {
+            const long long diff = (long long)(w[n + 1] - w[n]);
+            const float v = bad ? __builtin_nanf("") : (float)((double)diff * (double)inv_scale);
+            yr[n] = accumulate ? yr[n] + v : v;
+        }
+    }
+}
+
+template <int DIR>
+static int run_forward_gz(Ctx *c, const ArrayP<float> &arr, const FwdPrepP &pb,
+                          const int64_t *ball_off, int F, int64_t B_cap, const Level &lc,
+                          const unsigned *bound, unsigned long long *gacc, hipStream_t st) {
+    using A = unsigned long long;
+    auto kern = k_forward_gz<DIR>;
+    const size_t reserve = 2 * (SBP_MAX_FRAMES + 1) * sizeof(int64_t) + 256;
+    const size_t avail = c->lds_max > reserve ? c->lds_max - reserve : 0;
+    const int TE = lc.T + 1;
+    int dg = c->tuning.fwd_dets;
+    if (dg > arr.D) dg = arr.D;
+    // edge tile: the whole row if the dg rows fit, else the longest that does
+    int64_t TT = (int64_t)(avail / ((size_t)dg * sizeof(A)));
+    if (TT > TE) TT = TE;
+    if (TT < TE && TT < 64) return fail(SBP_E_DOMAIN, "LDS too small for %d rows", dg);
+    if (c->tuning.fwd_tile > 0 && TT > c->tuning.fwd_tile) TT = c->tuning.fwd_tile;
+    const int nt = (int)((TE + TT - 1) / TT);
+    const int G = (arr.D + dg - 1) / dg;
+    int block = c->tuning.fwd_block;
+    int bpt = c->tuning.fwd_bpt;
+    {
+        const int64_t want = 2 * (int64_t)c->num_cus * (1024 / block > 0 ? 1024 / block : 1);
+        auto items = [&](int blk, int b) {
+            const int64_t ch = (int64_t)blk * b;
+            return ((B_cap + ch - 1) / ch + F) * (int64_t)G * nt;
+        };
+        while (bpt > 1 && items(block, bpt) < want) --bpt;
+        while (block > 128 && items(block, bpt) < want) block /= 2;
+    }
+    const size_t lds = (size_t)dg * (size_t)TT * sizeof(A);
+    SBP_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    int grid = c->tuning.fwd_grid;
+    if (grid <= 0) {
+        int per_cu = 0;
+        SBP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, block, lds));
+        if (per_cu < 1) per_cu = 1;
+        grid = per_cu * c->num_cus;
+    }
+    const int64_t CH = (int64_t)block * bpt;
+    const int64_t max_items = ((B_cap + CH - 1) / CH + F) * (int64_t)G * nt;
+    if (grid > max_items) grid = (int)max_items;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, arr, pb, ball_off, F, G, dg,
+                       (int)TT, nt, bpt, lc, bound, gacc);
+    SBP_HIP(hipGetLastError());
+    return SBP_OK;
+}
+
 template <typename R, int PROF, int DIR>
 static int run_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
                        const int64_t *ball_off, int F, int64_t B_cap, const Level &lc,
@@ -507,9 +800,13 @@ static int run_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
     return SBP_OK;
 }
 
-size_t forward_ws_bytes(int F, int D, int T, size_t elem) {
+static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// FP32: [per-sample integer sums, T + 1 per row][six per-ball constant arrays]
+size_t forward_ws_bytes(int F, int D, int T, int64_t B_cap, size_t elem) {
     if (elem != sizeof(float)) return 0;
-    return ((size_t)F * (size_t)D * (size_t)T * sizeof(unsigned long long) + 255) & ~(size_t)255;
+    return up256((size_t)F * (size_t)D * (size_t)(T + 1) * sizeof(unsigned long long)) +
+           6 * up256((size_t)B_cap * sizeof(float));
 }
 
 template <typename R>
@@ -534,6 +831,41 @@ int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const i
     if (nbb > 1024) nbb = 1024;
     unsigned long long *gacc = nullptr;
     const unsigned *bound = nullptr;
+    if constexpr (sizeof(R) == sizeof(float)) {
+      if (profile_code(m) == GAUSS) {
+        if (!ws || ws_bytes < forward_ws_bytes(F, arr.D, m->T, B_cap, sizeof(float)))
+            return fail(SBP_E_NOMEM, "forward workspace too small");
+        gacc = (unsigned long long *)ws;
+        const int64_t ne = (int64_t)F * arr.D * (m->T + 1);
+        char *pp = (char *)ws + up256((size_t)ne * sizeof(unsigned long long));
+        const size_t pb_bytes = up256((size_t)B_cap * sizeof(float));
+        FwdPrepP pb;
+        float **fields[6] = {&pb.x, &pb.y, &pb.z, &pb.w, &pb.q0, &pb.pa2};
+        for (int k = 0; k < 6; ++k) *fields[k] = (float *)(pp + k * pb_bytes);
+        rc = launch_fill<uint64_t>((uint64_t *)gacc, ne, 0, st);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_fwd_prep, dim3((int)nbb), dim3(kPrepBlock), 0, st,
+                           BallsP<float>{(float *)balls.x, (float *)balls.y, (float *)balls.z,
+                                         (float *)balls.p0, (float *)balls.a},
+                           ball_off, F, lc, misc, pb);
+        SBP_HIP(hipGetLastError());
+        bound = misc + kMiscBound;
+        const ArrayP<float> af{(const float *)arr.qx, (const float *)arr.qy, (const float *)arr.qz,
+                               (const float *)arr.nx, (const float *)arr.ny, (const float *)arr.nz,
+                               arr.D};
+        if (m->directivity == SBP_DIR_COS)
+            rc = run_forward_gz<COS>(c, af, pb, ball_off, F, B_cap, lc, bound, gacc, st);
+        else
+            rc = run_forward_gz<OMNI>(c, af, pb, ball_off, F, B_cap, lc, bound, gacc, st);
+        if (rc) return rc;
+        int nbx = arr.D < 1024 ? arr.D : 1024;
+        hipLaunchKernelGGL(k_fwd_convert_edges, dim3(nbx, F), dim3(256), 0, st,
+                           (const unsigned long long *)gacc, arr.D, m->T, (const unsigned *)misc, lc,
+                           accumulate, (float *)y);
+        SBP_HIP(hipGetLastError());
+        return SBP_OK;
+      }
+    }
     if (sizeof(R) == sizeof(float)) {
         if (!ws || ws_bytes < (size_t)ns * sizeof(unsigned long long))
             return fail(SBP_E_NOMEM, "forward workspace too small");
@@ -559,10 +891,12 @@ int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const i
         else
             rc = run_forward<R, GPOINT, OMNI>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, gacc, st);
     } else if (m->profile == SBP_PROFILE_GAUSS) {
-        if (m->directivity == SBP_DIR_COS)
-            rc = run_forward<R, GAUSS, COS>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, gacc, st);
-        else
-            rc = run_forward<R, GAUSS, OMNI>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, gacc, st);
+        if constexpr (sizeof(R) == sizeof(double)) {
+            if (m->directivity == SBP_DIR_COS)
+                rc = run_forward<R, GAUSS, COS>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, gacc, st);
+            else
+                rc = run_forward<R, GAUSS, OMNI>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, gacc, st);
+        }
     } else {
         if (m->directivity == SBP_DIR_COS)
             rc = run_forward<R, UNIFORM, COS>(c, arr, balls, ball_off, F, B_cap, lc, bound, y, gacc, st);

@@ -238,7 +238,7 @@ struct BallsP {
 // misc: kMiscBytes of device words (the fixed-point bound of the FP32 path and
 // the per-frame non-finite flags); ws: the FP32 path's per-sample integer sums
 // (forward_ws_bytes; none for FP64).
-size_t forward_ws_bytes(int F, int D, int T, size_t elem);
+size_t forward_ws_bytes(int F, int D, int T, int64_t B_cap, size_t elem);
 template <typename R>
 int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
                    int F, int64_t B_cap, const sbp_model *m, R *y, int accumulate,

@@ -14,7 +14,7 @@ def _recorded(kernel):
     import hashlib
     import re
     text = open(os.path.join(bench.ROOT, "profiles", "hbm_traffic_large.md")).read()
-    entry = json.loads(re.search(r"```json\n(.*?)\n```", text, flags=re.S).group(1))[bench.KERNEL_NAMES[kernel]]
+    entry = json.loads(re.search(r"```json\n(.*?)\n```", text, flags=re.S).group(1)).get(bench.KERNEL_NAMES[kernel])
     h = hashlib.sha256()
     for f in bench.KERNEL_SOURCES[bench.KERNEL_NAMES[kernel].split("<")[0]]:
         with open(os.path.join(bench.ROOT, f), "rb") as fh:
@@ -28,7 +28,9 @@ def test_traffic_is_read_while_the_source_hash_matches():
     for k in ("forward", "adjoint", "filter"):
         entry, digest = _recorded(k)
         t = bench.measured_traffic(k)
-        if digest == entry["source_hash"]:
+        if entry is None:          # no counters taken on this kernel yet
+            assert t is None, k
+        elif digest == entry["source_hash"]:
             assert t == entry["read_bytes"] + entry["write_bytes"] and t > 0, k
         else:
             assert t is None, k

@@ -1,10 +1,13 @@
 """Inputs at the edges of the forward's number range, against the oracle.
 
 * Wide dynamic range: peak pressures spanning four decades in one call.  The
-  FP32 forward rounds every bin value to a multiple of one per-call quantum q
-  (a power of two with q <= 2^-29 of the largest possible edge value, the
-  bound max |p0| a / (2 K c dt) for GAUSS bin means), so a sample's error is at
-  most a couple of quanta per ball that reaches it, however dim those balls.
+  FP32 forward rounds every value it adds to the nearest multiple of one
+  per-call quantum q (a power of two with q <= 2^-29 of the bound
+  max |p0| a / (2 K c dt) on any one ball's values).  GAUSS bin means are
+  formed as differences of edge values, so a sample carries at most two
+  roundings per ball that reaches it: its error is at most q per such ball,
+  however dim those balls, and the roundings are unbiased and add like
+  independent uniform errors (variance q^2 / 12 each).
 * Non-finite parameters (the interface's convention for invalid input): a ball
   with a NaN or infinite stored centre, peak or size (a, or a~ under softplus)
   makes every sample of its frame NaN, gets NaN gradients, and is dropped by
@@ -69,11 +72,17 @@ def test_forward_wide_dynamic_range(ctx):
     n_b = contributions(bright, arr, tm)
     n_d = contributions(dim, arr, tm)
     dim_only = (n_b == 0) & (n_d > 0)
-    assert dim_only.sum() > 2000
+    assert dim_only.sum() > 1500          # 1668 samples hear dim balls only
     err = np.abs(y - ref)
-    assert np.all(err[dim_only] <= 2.0 * n_d[dim_only] * q + 1e-7 * np.abs(ref[dim_only]))
-    # dim-only samples on their own: still well inside the signal tolerance
-    assert rel_l2(y[dim_only], ref[dim_only]) <= 1e-4
+    # two half quanta per ball, plus the FP32 evaluation of the dim values
+    # (below 1e-3 q here) and the final rounding of the sample to FP32
+    assert np.all(err[dim_only] <= 1.01 * n_d[dim_only] * q + 2.0 ** -24 * np.abs(ref[dim_only]))
+    # unbiased: the error's root-mean-square over the dim-only samples is that
+    # of independent roundings (an emulation of exact edge values rounded this
+    # way gives 0.94 times sqrt(2 sum n_d / 12) q; truncation toward zero of
+    # bin values gives 3.6 times sqrt(sum n_d / 12) q)
+    rms_bound = np.sqrt(2.0 * n_d[dim_only].sum() / 12.0) * q
+    assert np.linalg.norm((y - ref)[dim_only]) <= 1.5 * rms_bound
 
 
 def dev():
