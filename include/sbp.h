@@ -253,6 +253,23 @@ int sbp_simulate_signals(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *ba
                          const int64_t *ball_off, int32_t F, int64_t B_cap,
                          const sbp_model *model, float *y, int32_t accumulate, void *stream);
 
+/* sbp_simulate_signals for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, same result bit for bit, but the call's
+ * workspace is a fixed device array of 128 MiB per GPU, held from the first
+ * sbp_ctx_create on that GPU until the process ends, instead of the
+ * context's scratch; the call makes no allocation of any kind.  Limit: the
+ * workspace the call needs, 8 (T + 1) F D + 24 B_cap bytes (each part rounded
+ * up to 256 bytes) plus 512, must fit in 128 MiB, else SBP_E_CAPACITY before
+ * anything is enqueued.  Every call on one GPU, through any context, shares
+ * that GPU's array: the call clears what it needs zeroed, but calls that
+ * overlap on one GPU (other streams, other threads) race and must not be
+ * issued.  Errors: as sbp_simulate_signals, plus SBP_E_CAPACITY. */
+int sbp_simulate_signals_noalloc(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *balls,
+                                 const int64_t *ball_off, int32_t F, int64_t B_cap,
+                                 const sbp_model *model, float *y, int32_t accumulate,
+                                 void *stream);
+
 /* Data-fidelity loss of section 4.2 / 4.3: with e = y_sim - y_ref,
  * loss[f] = sum over frame f of e^2 (a sum, no 1/N), computed in FP64, and
  * (if v_out is not NULL) v_out = 2 e = dL/dy_sim.  v_out may alias y_sim.

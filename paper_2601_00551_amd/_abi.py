@@ -97,6 +97,7 @@ SIGNATURES = {
     "sbp_downsample": (ctypes.c_int, [P, P, I64, I32, I32, P, P]),
     "sbp_decimate": (ctypes.c_int, [P, P, I64, I32, I32, P, P]),
     "sbp_simulate_signals": (ctypes.c_int, [P, PA, PB, P, I32, I64, PM, P, I32, P]),
+    "sbp_simulate_signals_noalloc": (ctypes.c_int, [P, PA, PB, P, I32, I64, PM, P, I32, P]),
     "sbp_residual_loss": (ctypes.c_int, [P, P, P, I64, I32, P, P, P]),
     "sbp_adjoint_gradients": (ctypes.c_int, [P, PA, PB, P, I32, I64, PM, P, U32, PB, P]),
     "sbp_filter_zero_grad": (ctypes.c_int, [P, PA, PB, P, I32, I64, PM, P, I32, PB, P, P,

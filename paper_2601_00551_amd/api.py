@@ -181,8 +181,9 @@ def context(device: int = 0) -> Context:
 # ---------------------------------------------------------------- calls ----
 
 def simulate_signals(ctx, arr, balls, model: Model, ball_off=None, y=None, accumulate=False,
-                     B_cap=None, stream=None, dtype=torch.float32):
-    """sbp_simulate_signals: returns y [F, D, T]."""
+                     B_cap=None, stream=None, dtype=torch.float32, noalloc=False):
+    """sbp_simulate_signals (sbp_simulate_signals_noalloc with noalloc=True,
+    FP32 only): returns y [F, D, T]."""
     dev = balls["x"].device
     off = default_off(balls, dev) if ball_off is None else _need(ball_off, torch.int64, "ball_off")
     F = off.numel() - 1
@@ -193,7 +194,11 @@ def simulate_signals(ctx, arr, balls, model: Model, ball_off=None, y=None, accum
     cap = balls["x"].numel() if B_cap is None else int(B_cap)
     _check_balls(balls, cap)
     _at_least(off, 1, "ball_off")
+    if noalloc and dtype != torch.float32:
+        raise ValueError("the allocation-free forward is FP32 only")
     fn = lib().sbp_simulate_signals if dtype == torch.float32 else lib().sbp_simulate_signals_f64
+    if noalloc:
+        fn = lib().sbp_simulate_signals_noalloc
     check(fn(ctx.ptr, ctypes.byref(array_struct(arr, dtype)), ctypes.byref(balls_struct(balls, dtype)),
              _p(off), F, cap, ctypes.byref(model.struct()), _p(y), int(bool(accumulate)), _stream(stream)))
     return y

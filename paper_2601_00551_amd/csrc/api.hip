@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "sbp_internal.hpp"
 
@@ -29,6 +30,39 @@ int fail(int code, const char *fmt, ...) {
 
 int hip_fail(hipError_t e, const char *what) {
     return fail(SBP_E_HIP, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+// ------------------------------------------------ fixed device workspace --
+// The workspace of sbp_simulate_signals_noalloc: a file-scope device array,
+// one copy per GPU for the life of the process, so that the call allocates
+// nothing.  In host code `scratch` names a host-side stand-in, not device
+// memory; its device address on each GPU is looked up once per device (with
+// that device current) when a context is created there, kept in
+// g_fixed_ws[device] and in the context, and only that address is handed to
+// kernels.  Every call on one GPU shares the array: the call clears what must
+// start at zero, and calls that overlap on one GPU race.
+constexpr size_t kFixedWsBytes = (size_t)128 << 20;
+constexpr int kFixedWsDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kFixedWsBytes];
+static std::mutex g_fixed_ws_mu;
+static void *g_fixed_ws[kFixedWsDevices];
+
+// Device address of `scratch` on `device`, which must be current.
+static int fixed_ws_address(int device, void **out) {
+    *out = nullptr;
+    if (device >= kFixedWsDevices)
+        return fail(SBP_E_ARG, "device %d: the fixed workspace supports devices 0..%d", device,
+                    kFixedWsDevices - 1);
+    std::lock_guard<std::mutex> lock(g_fixed_ws_mu);
+    if (!g_fixed_ws[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(SBP_E_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_fixed_ws[device] = p;
+    }
+    *out = g_fixed_ws[device];
+    return SBP_OK;
 }
 
 int ensure_scratch(Ctx *c, size_t bytes) {
@@ -245,6 +279,12 @@ int sbp_ctx_create(sbp_ctx **out, int device) {
         delete ctx;
         return fail(SBP_E_NOMEM, "could not allocate the context's device words");
     }
+    int rc = fixed_ws_address(device, &ctx->c.fixed_ws);
+    if (rc) {
+        (void)hipFree(ctx->c.misc);
+        delete ctx;
+        return rc;
+    }
     *out = ctx;
     return SBP_OK;
 }
@@ -328,6 +368,33 @@ int sbp_simulate_signals(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *ba
     return launch_forward<float>(&ctx->c, arrp<float>(arr), ballsp<float>(balls), ball_off, F,
                                  B_cap, model, y, accumulate, ctx->c.misc, ctx->c.scratch, wsb,
                                  (hipStream_t)stream);
+}
+
+int sbp_simulate_signals_noalloc(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *balls,
+                                 const int64_t *ball_off, int32_t F, int64_t B_cap,
+                                 const sbp_model *model, float *y, int32_t accumulate,
+                                 void *stream) {
+    int rc;
+    if ((rc = check_array(arr)) || (rc = check_frames(ball_off, F, B_cap)) ||
+        (rc = check_balls(balls, "balls", B_cap)))
+        return rc;
+    if (!y) return fail(SBP_E_ARG, "y is NULL");
+    if (accumulate != 0 && accumulate != 1) return fail(SBP_E_ARG, "accumulate must be 0 or 1");
+    if ((rc = check_model(model))) return rc;
+    const size_t wsb = forward_ws_bytes(F, arr->D, model->T, B_cap, sizeof(float));
+    if (wsb > kFixedWsBytes - kMiscBytes)
+        return fail(SBP_E_CAPACITY,
+                    "this call needs %zu bytes of workspace; the fixed workspace holds %zu "
+                    "(8 (T + 1) F D + 24 B_cap bytes, rounded, must fit)",
+                    wsb, kFixedWsBytes - kMiscBytes);
+    if ((rc = check_ctx(ctx))) return rc;
+    if (!ctx->c.fixed_ws) return fail(SBP_E_HIP, "the context has no fixed workspace address");
+    if ((rc = set_device(ctx->c))) return rc;
+    // [device words (bound, frame flags)][forward integer sums and ball constants]
+    char *base = (char *)ctx->c.fixed_ws;
+    return launch_forward<float>(&ctx->c, arrp<float>(arr), ballsp<float>(balls), ball_off, F,
+                                 B_cap, model, y, accumulate, (unsigned *)base, base + kMiscBytes,
+                                 wsb, (hipStream_t)stream);
 }
 
 int sbp_simulate_signals_f64(sbp_ctx *ctx, const sbp_array_f64 *arr, const sbp_balls_f64 *balls,

@@ -181,6 +181,7 @@ struct Ctx {
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
     unsigned *misc = nullptr;  // kMiscBytes persistent bytes (layout below)
+    void *fixed_ws = nullptr;  // this device's fixed workspace (device address), see api.hip
 };
 
 // Persistent device words of a context (and of a captured graph): word

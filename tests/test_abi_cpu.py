@@ -56,10 +56,10 @@ def _balls():
     return _abi.SbpBalls(FAKE.value, FAKE.value, FAKE.value, FAKE.value, FAKE.value)
 
 
-def _sim(ctx=None, arr=None, balls=None, off=FAKE, F=1, cap=10, model=None, y=FAKE, acc=0):
-    lib = _abi.lib()
-    return lib.sbp_simulate_signals(ctx, ctypes.byref(arr or _array()), ctypes.byref(balls or _balls()),
-                                    off, F, cap, ctypes.byref(model or _model()), y, acc, None)
+def _sim(ctx=None, arr=None, balls=None, off=FAKE, F=1, cap=10, model=None, y=FAKE, acc=0,
+         fn="sbp_simulate_signals"):
+    return getattr(_abi.lib(), fn)(ctx, ctypes.byref(arr or _array()), ctypes.byref(balls or _balls()),
+                                   off, F, cap, ctypes.byref(model or _model()), y, acc, None)
 
 
 def last():
@@ -87,9 +87,25 @@ def last():
     (dict(balls=_abi.SbpBalls(FAKE.value, None, FAKE.value, FAKE.value, FAKE.value)), _abi.SBP_E_ARG),
     (dict(), _abi.SBP_E_ARG),          # everything valid but the NULL context
 ])
-def test_simulate_validation(kw, code):
-    assert _sim(**kw) == code
+@pytest.mark.parametrize("fn", ["sbp_simulate_signals", "sbp_simulate_signals_noalloc"])
+def test_simulate_validation(kw, code, fn):
+    assert _sim(fn=fn, **kw) == code
     assert last()
+
+
+def test_noalloc_rejects_workspace_beyond_its_fixed_size():
+    """The allocation-free forward's fixed workspace is 128 MiB per GPU: a call
+    needing more (8 (T + 1) F D + 24 B_cap bytes) is refused on the host,
+    before the context is looked at, with the sizes in the message."""
+    fn = "sbp_simulate_signals_noalloc"
+    # 1024 transducers x 20000 samples: 164 MB of per-sample sums
+    assert _sim(fn=fn, arr=_array(D=1024), model=_model(T=20000)) == _abi.SBP_E_CAPACITY
+    assert "the fixed workspace holds %d" % ((128 << 20) - 512) in last(), last()
+    # 6,000,000 balls: 144 MB of per-ball constants
+    assert _sim(fn=fn, cap=6_000_000) == _abi.SBP_E_CAPACITY
+    # the large workload of the benchmark fits: 1024 x 4097 x 8 + 24 x 2,000,000 bytes
+    assert _sim(fn=fn, arr=_array(D=1024), model=_model(T=4096), cap=2_000_000) == _abi.SBP_E_ARG
+    assert "ctx" in last()
 
 
 def test_uniform_profile_ignores_gauss_K():
