@@ -155,9 +155,14 @@ typedef struct sbp_state {
  * a > a_split into two children at -/+ a/2 along the axis of the largest
  * |position gradient| (size a / 2^(1/3), same p0); duplicate the
  * floor(dup_frac * n) non-split survivors of largest |grad r| (ties: lower
- * index) with a clone offset by -dup_offset * a * grad r / |grad r|.  Output per
- * frame: survivors in input order with split balls replaced in place by their
- * two children, then the clones in input order.  New balls get zero moments. */
+ * index) with a clone offset by -dup_offset * a * grad r / |grad r| (a ball
+ * with zero position gradient gets a clone on itself).  Output per frame:
+ * survivors in input order with split balls replaced in place by their two
+ * children, then the clones in input order.  New balls get zero moments.  The
+ * thresholds are float32 fields and the rule is defined on those values: the
+ * destroy threshold is destroy_frac * max p0 rounded to float32, and
+ * floor(dup_frac * n) is taken exactly from the float32 dup_frac (0.7 is
+ * 0.699999988, so ten candidates give six clones). */
 typedef struct sbp_growth_rule {
     float destroy_frac;
     float a_min;

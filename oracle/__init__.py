@@ -260,9 +260,11 @@ def sigmoid(x):
 class GrowthRule:
     """Thresholds of the plain growth rule (the paper gives none; section 4.1).
 
-    Thresholds are given as FP32 values and every decision is taken in FP32, the
-    precision of the stored ball parameters (the duplicate count is
-    floor(n * dup_frac) in FP64 with dup_frac rounded to FP32 first).
+    The interface passes the thresholds as float32 fields, so the rule is
+    defined on their float32 values, compared with the float32 ball
+    parameters: the destroy threshold is destroy_frac * max p0 rounded to
+    float32, and the duplicate count floor(n * dup_frac) is exact for the
+    float32 dup_frac (0.7 is 0.699999988: ten candidates give six clones).
     """
     destroy_frac: float = 0.02     # destroy if p0 < destroy_frac * max p0 (per frame)
     a_min: float = 0.02            # destroy if a < a_min (mm)

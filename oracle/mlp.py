@@ -4,9 +4,17 @@ The network is 31 -> 256 -> 256 -> 256 -> 2 with ReLU.  The GPU kernels feed
 the matrix cores BF16 operands: inputs and weights are rounded to BF16, and
 each hidden activation is rounded to BF16 after bias and ReLU.  This reference
 applies the same roundings (round to nearest even, written out on the float32
-bit pattern) and computes everything else in FP64; gradients treat the
-roundings as the identity (straight-through), i.e. they are the exact
-gradients of the unrounded network evaluated at the rounded values.
+bit pattern) and computes everything else in FP64.
+
+The backward treats the forward's roundings as the identity (straight-through:
+the gradients of the unrounded network evaluated at the rounded values) and,
+by default, rounds the operands it feeds to products as BF16 operands too:
+the gradient with respect to each hidden activation, dL/dh_l, is rounded to
+BF16 (before the ReLU mask, with which rounding commutes), and the output
+gradient is rounded to BF16 where it multiplies h3 into the last layer's
+weight gradient.  The output gradient itself stays unrounded where it is
+back-propagated into dL/dh3 and summed into the last bias.  round_grads=False
+gives the plain straight-through gradients.
 
 Flat parameter layout (row-major [in][out] weights, then the bias):
 W1 [32][256], b1, W2 [256][256], b2, W3 [256][256], b3, W4 [256][2], b4.
@@ -81,19 +89,21 @@ def loss(out, yg, yp, pos_weight):
     return float(L), d
 
 
-def backward(cache, dout):
+def backward(cache, dout, round_grads=True):
     """Gradient of the loss with respect to the flat parameters."""
     x, h1, h2, h3, W = cache
+    r = bf16_round if round_grads else (lambda v: v)
+    dout = np.asarray(dout, dtype=np.float64)
     g = {}
-    g["W4"] = h3.T @ dout
+    g["W4"] = h3.T @ r(dout)
     g["b4"] = dout.sum(0)
-    d3 = (dout @ W["W4"].T) * (h3 > 0)
+    d3 = r(dout @ W["W4"].T) * (h3 > 0)
     g["W3"] = h2.T @ d3
     g["b3"] = d3.sum(0)
-    d2 = (d3 @ W["W3"].T) * (h2 > 0)
+    d2 = r(d3 @ W["W3"].T) * (h2 > 0)
     g["W2"] = h1.T @ d2
     g["b2"] = d2.sum(0)
-    d1 = (d2 @ W["W2"].T) * (h1 > 0)
+    d1 = r(d2 @ W["W2"].T) * (h1 > 0)
     g["W1"] = x.T @ d1
     g["b1"] = d1.sum(0)
     return pack(g)

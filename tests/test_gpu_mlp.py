@@ -1,14 +1,13 @@
 """GPU parity of the growth-proposal network and its feature kernels against
 the CPU reference (oracle/mlp.py, oracle/proposal.py), through the C-ABI.
 
-Tolerances.  Both sides round inputs, weights and hidden activations to BF16;
-the GPU accumulates in FP32 in the matrix cores' order, so an activation that
-lies within FP32 rounding of a BF16 rounding boundary can land one BF16 ulp
-(2^-8 relative) apart.  That is rare, hence outputs within 1e-3 relative L2.
-The backward additionally rounds the back-propagated gradients to BF16 before
-each matrix-core product (the reference keeps them in FP64): about 2^-9
-relative per element, averaging down over the reductions, hence gradients
-within 1e-2 relative L2 per parameter block."""
+Tolerances.  Both sides round inputs, weights and hidden activations to BF16,
+and in the backward the back-propagated gradients fed to the matrix cores
+(dL/dh per hidden layer, the output gradient in the last weight gradient);
+the GPU accumulates in FP32 in the matrix cores' order, so a value that lies
+within FP32 rounding of a BF16 rounding boundary can land one BF16 ulp (2^-8
+relative) apart.  That is rare, hence outputs and gradients within 1e-3
+relative L2 (per parameter block)."""
 import numpy as np
 import pytest
 import torch
@@ -97,7 +96,7 @@ def test_loss_and_backward_match_oracle(ctx, M):
     gref = om.backward(cache, d)
     got, ref = _blocks(g), _blocks(gref)
     for k in ref:
-        assert rel_l2(got[k], ref[k]) <= 1e-2, (k, rel_l2(got[k], ref[k]))
+        assert rel_l2(got[k], ref[k]) <= 1e-3, (k, rel_l2(got[k], ref[k]))
 
 
 def test_adam_matches_oracle(ctx):

@@ -529,6 +529,35 @@ def test_grow_matches_oracle(ctx):
     assert e.value.code == api._abi.SBP_E_CAPACITY
 
 
+@pytest.mark.parametrize("case", ["by_hand", "zero_gradient", "float32_frac"])
+def test_grow_hand_cases_match_oracle(ctx, case):
+    """The hand-countable growth scenes of the oracle pins (clone order after
+    the survivors, clone offset against the gradient, the tie at the cut,
+    zero-gradient clones, k read from the float32 dup_frac), on the GPU."""
+    import test_oracle_pins as tp
+    dev = torch.device("cuda:0")
+    b, g = tp._frac_scene() if case == "float32_frac" else tp._grow_scene()
+    b = {k: np.asarray(v, np.float32) for k, v in b.items()}
+    if case == "zero_gradient":
+        g = {k: np.zeros(8, np.float32) for k in g}
+    kw = {"by_hand": dict(destroy_frac=0.05, a_min=0.02, a_split=0.4, dup_frac=0.4, dup_offset=0.5),
+          "zero_gradient": dict(destroy_frac=0.05, a_min=0.02, a_split=1.0, dup_frac=0.5, dup_offset=0.5),
+          "float32_frac": dict(destroy_frac=0.0, a_min=0.0, a_split=1.0, dup_frac=0.7, dup_offset=0.5)}[case]
+    st = api.State(b, device=dev)
+    for k in PARAMS:
+        st.grad[k].copy_(torch.as_tensor(g[k], device=dev))
+        st.m[k].fill_(1.0)
+    out, cnt = api.grow(ctx, st, api.GrowthRule(**kw), capacity=32)
+    ref, roff, born, src = oracle.grow(b, g, oracle.GrowthRule(**kw))
+    assert cnt == roff[-1] and list(out.ball_off.cpu().numpy()) == list(roff)
+    for k in PARAMS:
+        np.testing.assert_allclose(out.balls[k][:cnt].cpu().numpy(), ref[k], rtol=0, atol=2e-6 * 14, err_msg=k)
+        mg = out.m[k][:cnt].cpu().numpy()
+        assert np.array_equal(mg == 0.0, born), k
+    if case == "float32_frac":
+        assert born.sum() == 6      # floor(10 * 0.699999988) of the ten candidates
+
+
 def test_step_graph_replays_match_eager(ctx):
     """Replays of the captured iteration, with eager work and synchronisations
     between them, track an eager run of the same iterations."""

@@ -146,7 +146,7 @@ def test_backward_matches_torch_autograd_with_rounding():
     yp = rng.uniform(size=33)
     out, cache = om.forward(p, X)
     L, d = om.loss(out, yg, yp, 2.0)
-    g = om.backward(cache, d)
+    g = om.backward(cache, d, round_grads=False)
 
     def st(t):  # value rounded to bf16, gradient passed straight through
         r = t.detach().to(torch.float32).to(torch.bfloat16).to(torch.float64)
@@ -168,6 +168,71 @@ def test_backward_matches_torch_autograd_with_rounding():
     assert float(Lt) == pytest.approx(L, rel=1e-12)
     ref = np.concatenate([P[name].grad.numpy().ravel() for name, _ in om.SHAPES])
     np.testing.assert_allclose(g, ref, rtol=1e-10, atol=1e-13)
+
+
+def test_backward_gradient_rounding_matches_torch_bfloat16_hooks():
+    """The rounded back-propagation against autograd on the same torch FP64
+    network, with torch's own bfloat16 conversion applied by gradient hooks to
+    dL/dh3, dL/dh2 and dL/dh1 (the operands of the next products) and to the
+    output gradient in the last layer's weight gradient."""
+    rng = np.random.default_rng(16)
+    p = _random_params(17)
+    X = rng.normal(size=(41, 31))
+    yg = (rng.uniform(size=41) > 0.5).astype(float)
+    yp = rng.uniform(size=41)
+    out, cache = om.forward(p, X)
+    _, d = om.loss(out, yg, yp, 1.5)
+    g = om.unpack(om.backward(cache, d))
+
+    def tbf(t):
+        return t.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+
+    def st(t):
+        return t + (tbf(t.detach()) - t).detach()
+
+    P = {k: torch.tensor(v, requires_grad=True) for k, v in om.unpack(p).items()}
+    x = torch.zeros(41, 32, dtype=torch.float64)
+    x[:, :31] = st(torch.tensor(X))
+    hs, h = [], x
+    for i in (1, 2, 3):
+        h = st(torch.relu(h @ st(P[f"W{i}"]) + P[f"b{i}"]))
+        h.register_hook(tbf)
+        hs.append(h)
+    o = h @ st(P["W4"]) + P["b4"]
+    o.backward(torch.tensor(d))
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3", "b4"):
+        np.testing.assert_allclose(g[name], P[name].grad.numpy(), rtol=1e-10, atol=1e-14, err_msg=name)
+    gw4 = hs[2].detach().T @ tbf(torch.tensor(d))
+    np.testing.assert_allclose(g["W4"], gw4.numpy(), rtol=1e-10, atol=1e-14)
+    # and the rounding is not vacuous here: the straight-through gradients differ
+    g0 = om.unpack(om.backward(cache, d, round_grads=False))
+    assert not np.allclose(g0["W1"], g["W1"], rtol=1e-6, atol=0)
+
+
+def test_backward_rounding_is_exact_on_bf16_representable_gradients():
+    """Small-integer weights and inputs with an output gradient of powers of two
+    keep every back-propagated value exactly representable in BF16: the
+    rounded and the plain back-propagation agree with autograd exactly."""
+    rng = np.random.default_rng(18)
+    P = {name: rng.integers(-1, 2, size=shape).astype(np.float64) for name, shape in om.SHAPES}
+    for k, dens in (("W1", 0.2), ("W2", 0.02), ("W3", 0.02)):
+        P[k] *= rng.uniform(size=P[k].shape) < dens       # sparse: activations stay below 256
+    p = om.pack(P)
+    X = rng.integers(-1, 2, size=(12, 31)).astype(np.float64)
+    out, cache = om.forward(p, X)
+    assert max(np.abs(h).max() for h in cache[1:4]) < 256 and np.abs(cache[3]).max() > 0
+    d = 2.0 ** rng.integers(-6, -2, size=(12, 2)) * rng.choice([-1.0, 1.0], size=(12, 2))
+    g = om.backward(cache, d)
+    np.testing.assert_array_equal(g, om.backward(cache, d, round_grads=False))
+    Pt = {k: torch.tensor(v, requires_grad=True) for k, v in P.items()}
+    x = torch.zeros(12, 32, dtype=torch.float64)
+    x[:, :31] = torch.tensor(X)
+    h = x
+    for i in (1, 2, 3):
+        h = torch.relu(h @ Pt[f"W{i}"] + Pt[f"b{i}"])
+    (h @ Pt["W4"] + Pt["b4"]).backward(torch.tensor(d))
+    ref = np.concatenate([Pt[name].grad.numpy().ravel() for name, _ in om.SHAPES])
+    np.testing.assert_array_equal(g, ref)
 
 
 # ----------------------------------------------------------- grid cases --

@@ -486,6 +486,94 @@ def test_residual_loss_sum():
     np.testing.assert_allclose(v, 2 * (a - b))
 
 
+def _grow_scene():
+    """Eight hand-made balls (one frame) for the growth pins.
+
+    index  p0    a     grad r        fate (rule below)
+      0    0.9   0.2   (3, 0, 4)     candidate, |g| = 5
+      1    0.01  0.2   (9, 9, 9)     destroyed: p0 < 0.05 * 0.9
+      2    0.8   0.5   (0, -2, 1)    split along y (a > 0.4)
+      3    0.7   0.2   (0, 0, 0)     candidate, |g| = 0
+      4    0.6   0.2   (0, 6, 8)     candidate, |g| = 10
+      5    0.5   0.01  (1, 1, 1)     destroyed: a < 0.02
+      6    0.4   0.2   (5, 0, 0)     candidate, |g| = 5 (ties with 0)
+      7    0.3   0.2   (1, 0, 0)     candidate, |g| = 1
+    """
+    b = {"x": np.arange(8, dtype=np.float64), "y": 10.0 + np.arange(8), "z": -np.arange(8, dtype=np.float64),
+         "p0": np.array([0.9, 0.01, 0.8, 0.7, 0.6, 0.5, 0.4, 0.3], np.float32),
+         "a": np.array([0.2, 0.2, 0.5, 0.2, 0.2, 0.01, 0.2, 0.2], np.float32)}
+    g = np.array([[3, 0, 4], [9, 9, 9], [0, -2, 1], [0, 0, 0], [0, 6, 8], [1, 1, 1], [5, 0, 0], [1, 0, 0]],
+                 np.float32)
+    grads = {"x": g[:, 0], "y": g[:, 1], "z": g[:, 2], "p0": np.zeros(8, np.float32), "a": np.zeros(8, np.float32)}
+    return b, grads
+
+
+def test_growth_duplicates_by_hand():
+    """Five candidates (0, 3, 4, 6, 7); dup_frac 0.4 gives floor(2.0000000298) =
+    2 clones: ball 4 (|g| = 10) and, of the tie 0 / 6 at |g| = 5, the lower
+    index 0.  Output: survivors in input order with ball 2 replaced by its two
+    children, then the clones in input order (0, then 4), each moved
+    dup_offset * a = 0.1 against its gradient direction."""
+    b, g = _grow_scene()
+    rule = oracle.GrowthRule(destroy_frac=0.05, a_min=0.02, a_split=0.4, dup_frac=0.4, dup_offset=0.5)
+    out, off, born, src = oracle.grow(b, g, rule)
+    assert list(src) == [0, 2, 2, 3, 4, 6, 7, 0, 4]
+    assert list(born) == [False, True, True, False, False, False, False, True, True]
+    assert list(off) == [0, 9]
+    # split of ball 2 along y (|g_y| = 2 is the largest): children at y -/+ a/2
+    np.testing.assert_allclose(out["y"][1:3], [12.0 - 0.25, 12.0 + 0.25], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(out["x"][1:3], [2.0, 2.0], rtol=0, atol=0)
+    np.testing.assert_allclose(out["a"][1:3], 0.5 / 2.0 ** (1.0 / 3.0), rtol=1e-15)
+    # clone of ball 0: (0, 10, 0) - 0.5 * 0.2 * (3, 0, 4) / 5
+    a0 = float(np.float32(0.2))
+    np.testing.assert_allclose([out["x"][7], out["y"][7], out["z"][7]],
+                               [-0.5 * a0 * 0.6, 10.0, -0.5 * a0 * 0.8], rtol=0, atol=1e-12)
+    # clone of ball 4: (4, 14, -4) - 0.5 * 0.2 * (0, 6, 8) / 10
+    np.testing.assert_allclose([out["x"][8], out["y"][8], out["z"][8]],
+                               [4.0, 14.0 - 0.5 * a0 * 0.6, -4.0 - 0.5 * a0 * 0.8], rtol=0, atol=1e-12)
+    assert out["p0"][7] == np.float32(0.9) and out["a"][8] == np.float32(0.2)
+
+
+def test_growth_zero_gradient_clones_sit_on_their_ball():
+    """With every gradient zero all keys tie: the clones go to the lowest
+    candidate indices and sit exactly on their balls."""
+    b, g = _grow_scene()
+    g = {k: np.zeros(8, np.float32) for k in g}
+    # candidates 0, 2 (not split: a_split above every a), 3, 4, 6, 7; k = 3
+    rule = oracle.GrowthRule(destroy_frac=0.05, a_min=0.02, a_split=1.0, dup_frac=0.5, dup_offset=0.5)
+    out, off, born, src = oracle.grow(b, g, rule)
+    assert list(src) == [0, 2, 3, 4, 6, 7, 0, 2, 3]
+    for ax in ("x", "y", "z"):
+        np.testing.assert_array_equal(out[ax][6:], np.asarray(b[ax], np.float64)[[0, 2, 3]])
+
+
+def _frac_scene():
+    rng = np.random.default_rng(5)
+    n = 10
+    b = {"x": rng.normal(size=n).astype(np.float32), "y": rng.normal(size=n).astype(np.float32),
+         "z": rng.normal(size=n).astype(np.float32), "p0": np.full(n, 0.5, np.float32),
+         "a": np.full(n, 0.1, np.float32)}
+    g = {k: rng.normal(size=n).astype(np.float32) for k in oracle.PARAMS}
+    return b, g
+
+
+def test_growth_clone_count_reads_dup_frac_as_its_float32_value():
+    """The rule's thresholds are float32 fields: k = floor(n * dup_frac) with
+    dup_frac the float32 value, taken exactly.  0.7 is 0.699999988 in float32,
+    so ten candidates give 6 clones; 0.4 is 0.400000006, so five give 2."""
+    b, g = _frac_scene()
+    n = 10
+    for frac, want in ((0.7, 6), (0.3, 3), (0.25, 2), (1.0, 10), (0.09, 0)):
+        rule = oracle.GrowthRule(destroy_frac=0.0, a_min=0.0, a_split=1.0, dup_frac=frac, dup_offset=0.5)
+        _, off, born, _ = oracle.grow(b, g, rule)
+        assert born.sum() == want and off[-1] == n + want, (frac, born.sum())
+    # destroy threshold: p0 < float32(destroy_frac * max p0), a tie at the threshold survives
+    b["p0"] = np.array([1.0, 0.25, 0.2499999, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5, 0.5], np.float32)
+    rule = oracle.GrowthRule(destroy_frac=0.25, a_min=0.0, a_split=1.0, dup_frac=0.0, dup_offset=0.5)
+    _, off, _, src = oracle.grow(b, g, rule)
+    assert 1 in src and 2 not in src and off[-1] == 9
+
+
 def test_growth_rule_self_consistency():
     """Growth thresholds are not given by the paper (parity unpinned): check
     counts, placement and ordering of the deterministic rule."""
