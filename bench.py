@@ -24,23 +24,56 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# --- algorithmic VALU lane-operations (FP32-equivalent issue slots; a
-# transcendental counts 2: exp2, rcp and sqrt issue at half the FMA rate on
-# gfx950, as `bench.py --rates` measures) -----------------------------------
-OPS_GEOMETRY = 27        # per pair: offset, rho (sqrt), 1/rho, e_hat, cosine, window, amplitude
-OPS_FWD_EDGE = 10        # per edge: u, u^2 k, exp, support clamp, scale, bin difference, accumulate
-OPS_ADJ_EDGE = 11        # per edge: u, u^2 k, exp, support select, three weighted sums
-OPS_ADJ_PAIR = 26        # per pair: S0..S2, dL/dp0, dL/da, radial and directivity terms
-OPS_FLT_EDGE = 8         # per edge (p0 only): u, u^2 k, exp, select, one weighted sum
+# --- algorithmic work per (ball, transducer) pair, in FP32 lane-operation
+# issue slots; a transcendental counts 2 (exp2, rcp and sqrt issue at half the
+# FMA rate on gfx950, as `bench.py --rates` measures).  Counted from the
+# method's arithmetic, not from the kernels' instruction streams. ------------
+OPS_GEOMETRY = 22        # per pair: offset, rho (sqrt), 1/rho, e_hat, cosine, window, amplitude (18 + 2 transcendentals)
+# forward, the bin-mean formula of section 4.2 / 4.3 (one bin per support bin,
+# E + 1 per pair): u, u^2 / (2 a^2), exp, minus e_K, scale, bin difference,
+# accumulate (6 + 1 transcendental)
+OPS_FWD_BIN = 8
+# forward as computed (edge form: one value per support edge, E per pair):
+# exponent as a quadratic in the edge offset (2), exp2, scale, accumulate
+OPS_FWD_EDGE = 6
+# adjoint as computed: per support edge one staged read and the moment sums
+# (w e, three sums, the exponential's two-multiply recurrence); per block of
+# 16 edges an exact restart (two exp2) and folding the block's moments; per
+# pair S0..S2 and the five gradients (with the cosine term)
+OPS_ADJ_EDGE = 6
+OPS_ADJ_BLOCK = 17
+OPS_ADJ_PAIR = 25
+# filter as computed (p0 only, nested sum): per edge one FMA and one multiply;
+# per block two exp2 and the block's offsets; per pair the p0 gradient
+OPS_FLT_EDGE = 2
+OPS_FLT_BLOCK = 8
 OPS_FLT_PAIR = 3
+ADJ_BLOCK_EDGES = 16
 OPS_FWD_EDGE_UNIFORM = 7  # per edge, UNIFORM profile: u, u^2, a^2 - u^2, clamp, scale, difference, accumulate
 OPS_FWD_SAMPLE_POINT = 8  # per sample, point sampling: u, u^2 k, exp, u e, scale, accumulate
 VALU_PEAK = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock = 3.93e13 lane-ops/s
+# 64-bit LDS atomic adds, lane-operations per clock per CU, measured by
+# `bench.py --rates` (profiles/issue_rates.md): consecutive addresses (no two
+# lanes on one bank or address), and pseudo-random addresses in a 4096-entry row
+LDS_U64_CONFLICT_FREE = 8.60
+LDS_U64_RANDOM = 6.23
+LDS_PEAK = 256 * 2.4e9 * LDS_U64_CONFLICT_FREE
 
 
 def edges_per_pair(a_sup, cdt):
-    """Expected edges of a pair: the support spans 2 a_sup / (c dt) bins, plus one."""
-    return 2.0 * a_sup / cdt + 1.0
+    """Expected support edges of a pair (strictly inside |u| < a_sup): the
+    support spans 2 a_sup / (c dt) edge intervals."""
+    return 2.0 * a_sup / cdt
+
+
+def algorithmic_ops(E):
+    """Lane-operation slots per pair of the three VALU-bound kernels for E
+    expected support edges."""
+    blocks = -(-E // ADJ_BLOCK_EDGES)
+    return {"forward": OPS_GEOMETRY + (E + 1) * OPS_FWD_BIN,
+            "forward_as_computed": OPS_GEOMETRY + E * OPS_FWD_EDGE,
+            "adjoint": OPS_GEOMETRY + OPS_ADJ_PAIR + E * OPS_ADJ_EDGE + blocks * OPS_ADJ_BLOCK,
+            "filter": OPS_GEOMETRY + OPS_FLT_PAIR + E * OPS_FLT_EDGE + blocks * OPS_FLT_BLOCK}
 
 
 KERNEL_SOURCES = {"k_forward_gz": ("paper_2601_00551_amd/csrc/forward.hip", "paper_2601_00551_amd/csrc/sbp_internal.hpp"),
@@ -77,6 +110,9 @@ def cpu_baseline(wl, model_kw, n_balls_sample, rng_seed=0):
     of n_balls_sample balls against every transducer at the full record."""
     import numpy as np
     import oracle
+    from oracle import build as oracle_build
+    # the oracle compiled for this host's CPU (-O3 -march=native), as timed
+    oracle.use_library(oracle_build.build(native=True))
     rng = np.random.default_rng(rng_seed)
     idx = np.sort(rng.choice(len(wl.init["x"]), size=n_balls_sample, replace=False))
     balls = {k: v[idx] for k, v in wl.init.items()}
@@ -104,7 +140,7 @@ def cpu_baseline(wl, model_kw, n_balls_sample, rng_seed=0):
     finally:
         oracle.set_threads(prev)
     return {"value": pairs / (t2 - t0), "unit": "pairs/s", "cores": cores, "cpu_model": cpu_model_name(),
-            "kind": "oracle",
+            "kind": "oracle", "build": "gcc -O3 -march=native -fopenmp",
             "sample": f"{n_balls_sample} of the {len(wl.init['x'])} balls x all {D} transducers, "
                       f"T={model_kw['T']}: oracle forward {t1 - t0:.2f} s + VJP {t2 - t1:.2f} s",
             "single_thread": {"value": n1 * D / (t4 - t3), "unit": "pairs/s",
@@ -338,7 +374,7 @@ def suite(args):
     tf, tb = fwd_adj(A, st, model, y)
     B, D = len(wl.init["x"]), len(wl.array["qx"])
     E = edges_per_pair(0.15, c * wl.dt)
-    ops_f = B * D * (OPS_GEOMETRY + E * OPS_FWD_EDGE_UNIFORM)
+    ops_f = B * D * (OPS_GEOMETRY + (E + 1) * OPS_FWD_EDGE_UNIFORM)     # E + 1 bins
     print(json.dumps({"workload": wl.name.replace("uniform2M", "uniform2M-uniformballs"), "profile": "uniform",
                       "forward_ms": tf, "adjoint_ms": tb, "fwd_adj_pairs_per_s": B * D / ((tf + tb) * 1e-3),
                       "forward_frac_alu": ops_f / (tf * 1e-3) / VALU_PEAK}), flush=True)
@@ -365,7 +401,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--balls", type=int, default=2_000_000)
-    ap.add_argument("--cpu-sample", type=int, default=12000, help="balls in the oracle sample (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=40000, help="balls in the oracle sample (0 = skip)")
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2601_00551_amd", "tuning.json"))
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (the reference for HBM counters)")
@@ -499,13 +535,23 @@ def main():
     avg = {n: float(np.mean(times[n])) for n in names}
     kept = float(np.mean(counts["kept"]))
     E = edges_per_pair(5.0 * 0.15, c * dt)
-    alg = {
-        "forward": kept * D * (OPS_GEOMETRY + E * OPS_FWD_EDGE),
-        "adjoint": kept * D * (OPS_GEOMETRY + OPS_ADJ_PAIR + (E + 1) * OPS_ADJ_EDGE),
-        "filter": float(np.mean(n_in[:-1])) * D * (OPS_GEOMETRY + OPS_FLT_PAIR + (E + 1) * OPS_FLT_EDGE),
-    }
+    per_pair = algorithmic_ops(E)
+    pairs = {"forward": kept * D, "adjoint": kept * D, "filter": float(np.mean(n_in[:-1])) * D}
+    kernels = {}
+    for n in ("forward", "adjoint", "filter"):
+        ach = pairs[n] * per_pair[n] / (avg[n] * 1e-3)
+        kernels[n] = {"ms": round(avg[n], 4), "pairs": pairs[n], "ops_per_pair": per_pair[n],
+                      "achieved_TOPs": ach / 1e12, "frac": ach / VALU_PEAK,
+                      "traffic": measured_traffic(n)}
+    f_comp = pairs["forward"] * per_pair["forward_as_computed"] / (avg["forward"] * 1e-3)
+    kernels["forward"]["as_computed"] = {"ops_per_pair": per_pair["forward_as_computed"],
+                                         "achieved_TOPs": f_comp / 1e12, "frac": f_comp / VALU_PEAK}
+    lds = pairs["forward"] * E / (avg["forward"] * 1e-3)      # one LDS add per support edge
+    kernels["forward"]["lds_atomics"] = {
+        "per_pair": E, "achieved_per_s": lds, "peak_per_s": LDS_PEAK, "frac": lds / LDS_PEAK,
+        "frac_of_random_address_rate": lds / (256 * 2.4e9 * LDS_U64_RANDOM)}
     dominant = max(("forward", "adjoint", "filter"), key=lambda n: avg[n])
-    achieved = alg[dominant] / (avg[dominant] * 1e-3)
+    achieved = kernels[dominant]["achieved_TOPs"] * 1e12
     fwd_adj = kept * D / ((avg["forward"] + avg["adjoint"]) * 1e-3)
     line = {
         "metric": "fwd+adjoint ball-detector pairs/s",
@@ -529,6 +575,7 @@ def main():
         "roofline": {"bound": "alu", "kernel": dominant, "achieved": achieved / 1e12,
                      "peak": VALU_PEAK / 1e12, "unit": "TOP/s", "frac": achieved / VALU_PEAK,
                      "traffic": measured_traffic(dominant), "traffic_unit": "bytes/launch"},
+        "kernels": kernels,
         "tuning": tuned,
         "wall_s": wall,
     }

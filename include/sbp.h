@@ -54,7 +54,7 @@ extern "C" {
 /* ------------------------------------------------------------ codes ----- */
 #define SBP_OK 0
 #define SBP_E_ARG (-1)      /* null pointer, negative or inconsistent size, F < 1 */
-#define SBP_E_DOMAIN (-2)   /* c <= 0, dt <= 0, f < 1, T < 1, unknown enum, K <= 0 */
+#define SBP_E_DOMAIN (-2)   /* c <= 0, dt <= 0, f < 1, T < 1, unknown enum, K outside (0, 12] */
 #define SBP_E_HIP (-3)      /* a HIP runtime error; message in sbp_last_error() */
 #define SBP_E_NOMEM (-4)    /* the context could not grow its scratch memory */
 #define SBP_E_CAPACITY (-5) /* an output would exceed the caller's capacity */
@@ -92,7 +92,8 @@ typedef struct sbp_model {
     double c;          /* speed of sound, mm/us, > 0 */
     double dt;         /* base sample interval, us, > 0 */
     double t0;         /* time of the first bin edge, us */
-    double gauss_K;    /* GAUSS truncation in units of a, > 0 (5 is the default) */
+    double gauss_K;    /* GAUSS truncation in units of a, 0 < K <= 12 (5 is the default;
+                          the tail beyond 12 a is below e^-72 of the peak) */
     int32_t T;         /* samples at this level, >= 1 */
     int32_t f;         /* downsampling factor of this level, >= 1 */
     int32_t profile;   /* SBP_PROFILE_* */

@@ -59,12 +59,22 @@ class _CTime(ctypes.Structure):
                 ("sampling", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+
+def use_library(path: str) -> None:
+    """Load the C part from another build of sbp_oracle.c (e.g. the
+    -march=native copy); takes effect before the first call."""
+    global _LIB, _LIB_PATH
+    _LIB, _LIB_PATH = None, path
+
+
 def _lib():
     global _LIB
     if _LIB is None:
-        path = os.path.join(_HERE, "liboracle.so")
+        path = _LIB_PATH
         if not os.path.exists(path):
-            raise RuntimeError("oracle/liboracle.so is not built (run oracle/build.py)")
+            raise RuntimeError(f"{path} is not built (run oracle/build.py)")
         lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         lib.orc_simulate.argtypes = [ctypes.c_int64] + [P] * 5 + [ctypes.c_int32] + [P] * 6 + \

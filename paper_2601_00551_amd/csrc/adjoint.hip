@@ -88,44 +88,6 @@ __device__ inline void block_moments(const R *__restrict__ wb, int n, R e, R gq,
     }
 }
 
-// The plain Gaussian sum Z = sum_{j<n} w_j e_j of one block in nested form.
-// With r_j = e_j / e_{j+1} (r_{j+1} = r_j / h),
-//     Z = e_{n-1} (...((w_0 r_0 + w_1) r_1 + w_2) r_2 ... + w_{n-1}),
-// one fma and one multiply per edge where the explicit e_j of block_moments
-// take three operations.  Returns the bracket; r enters as r_0, hinv = 1 / h.
-template <typename R>
-__device__ inline R block_nested(const R *__restrict__ wb, int n, R r, R hinv) {
-    R acc = R(0);
-    auto edge = [&](R w, bool first) {
-        acc = first ? w : fma(acc, r, w);
-        if (!first) r *= hinv;
-    };
-    if (BlockUnroll<R>::on && n == kRestart) {
-#pragma unroll
-        for (int g0 = 0; g0 < kRestart; g0 += kGroup) {
-            R w[kGroup];
-#pragma unroll
-            for (int k = 0; k < kGroup; ++k) w[k] = wb[g0 + k];
-#pragma unroll
-            for (int k = 0; k < kGroup; ++k) edge(w[k], g0 + k == 0);
-        }
-        return acc;
-    }
-    acc = wb[0];
-    int k = 1;
-    if (BlockUnroll<R>::on) {
-        for (; k + kGroup <= n; k += kGroup) {
-            R w[kGroup];
-#pragma unroll
-            for (int i = 0; i < kGroup; ++i) w[i] = wb[k + i];
-#pragma unroll
-            for (int i = 0; i < kGroup; ++i) edge(w[i], false);
-        }
-    }
-    for (; k < n; ++k) edge(wb[k], false);
-    return acc;
-}
-
 // Point sampling (GPOINT): sample m carries p0 D g(u_m) / (2 rho) with
 // g(u) = u e(u), e(u) = exp(-u^2 / (2 a^2)) for |u| < K a.  The staged row
 // holds w_m = vscale v_m (not differenced), and
@@ -222,18 +184,9 @@ __device__ inline void adj_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx,
     // UNIFORM), W = sum w
     R P = R(0), W = R(0), A1 = R(0), A2 = R(0);
     constexpr bool MOM = FULL || PROF == UNIFORM;
-    // the p0-only Gaussian sum needs no moments: nested form
-    constexpr bool NEST = PROF == GAUSS && !FULL;
-    const R hinv = NEST ? ex2(R(-2) * b.q0 * c * c) : R(1);
     for (int m0 = mb; m0 <= me; m0 += kRestart) {
         const R u0 = (R)(g.s - (double)m0 * lc.cdt);
         const int n = min(kRestart, me - m0 + 1);
-        if (NEST) {
-            const R un = (R)(g.s - (double)(m0 + n - 1) * lc.cdt);
-            const R r0 = ex2(-b.q0 * c * (c - R(2) * u0));
-            P = fma(ex2(un * un * b.q0), block_nested<R>(wr + m0, n, r0, hinv), P);
-            continue;
-        }
         R e = R(1), gq = R(1);
         if (PROF == GAUSS) {
             e = ex2(u0 * u0 * b.q0);

@@ -105,6 +105,8 @@ Level make_level(const sbp_model *m) {
 
 // ----------------------------------------------------------- validation --
 
+constexpr double kMaxGaussK = 12.0;
+
 static int check_model(const sbp_model *m) {
     if (!m) return fail(SBP_E_ARG, "model is NULL");
     if (!(m->c > 0.0) || !std::isfinite(m->c)) return fail(SBP_E_DOMAIN, "c must be > 0");
@@ -121,8 +123,11 @@ static int check_model(const sbp_model *m) {
         return fail(SBP_E_DOMAIN, "unknown sampling %d", m->sampling);
     if (m->sampling == SBP_SAMPLING_POINT && m->profile != SBP_PROFILE_GAUSS)
         return fail(SBP_E_DOMAIN, "point sampling is implemented for the GAUSS profile only");
-    if (m->profile == SBP_PROFILE_GAUSS && (!(m->gauss_K > 0.0) || !std::isfinite(m->gauss_K)))
-        return fail(SBP_E_DOMAIN, "gauss_K must be > 0");
+    // the Gaussian recurrences' first ratio reaches exp(K^2 / 2) for balls with
+    // a = c dt_k / K: K <= 12 keeps it inside the FP32 range
+    if (m->profile == SBP_PROFILE_GAUSS &&
+        (!(m->gauss_K > 0.0) || !(m->gauss_K <= kMaxGaussK)))
+        return fail(SBP_E_DOMAIN, "gauss_K must be in (0, %g]", kMaxGaussK);
     return SBP_OK;
 }
 

@@ -1,10 +1,11 @@
 // Issue-rate microbenchmark for the roofline of the VALU-bound kernels:
 // lane-operations per second on this device for FP32 FMA and multiply, the
 // FP32 transcendentals the physics kernels use (exp2, reciprocal, square
-// root), FP64 FMA, and LDS 64/32-bit integer atomic adds and 32/64/128-bit
-// reads at pseudo-random addresses inside one row (the access pattern of the
-// forward's accumulation and of the adjoint's staged rows; wide reads count
-// every dword as one lane-operation).
+// root), FP64 FMA, and LDS 64/32-bit integer and FP64 atomic adds and
+// 32/64/128-bit reads at pseudo-random addresses inside one row (the access
+// pattern of the forward's accumulation and of the adjoint's staged rows; wide
+// reads count every dword as one lane-operation), and atomic adds at
+// consecutive addresses (no bank conflict) and with four lanes per address.
 //
 // Every lane runs eight independent chains so that latency is hidden; the
 // grid fills every CU with eight 256-thread workgroups.  Output: one JSON
@@ -94,6 +95,36 @@ __global__ __launch_bounds__(256) void k_lds(unsigned long long *out, int iters)
     atomicAdd(out, s);
 }
 
+// Atomic adds with a wave-uniform random base and a lane pattern: CONSEC, lane
+// l at base + l (consecutive entries: no two lanes share a bank or an
+// address); CLUSTER4, four lanes per entry (base + l / 4).  Every address is
+// taken modulo the 4096-entry row.
+enum { PAT_CONSEC, PAT_CLUSTER4 };
+
+template <typename T, int PAT>
+__global__ __launch_bounds__(256) void k_lds_pattern(unsigned long long *out, int iters) {
+    __shared__ T row[4096];
+    for (int i = threadIdx.x; i < 4096; i += blockDim.x) row[i] = (T)0;
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t h = (blockIdx.x * 256u + threadIdx.x) * 2654435761u + 12345u;
+    uint32_t hw = __builtin_amdgcn_readfirstlane((blockIdx.x * 4u + (threadIdx.x >> 6)) * 2246822519u + 777u);
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            h = h * 1664525u + 1013904223u;
+            hw = hw * 1664525u + 1013904223u;
+            const uint32_t base = (hw >> 16) & 4095u;
+            const uint32_t idx = (base + (PAT == PAT_CONSEC ? lane : lane >> 2)) & 4095u;
+            atomicAdd(&row[idx], (T)(h & 7u));
+        }
+    }
+    __syncthreads();
+    unsigned long long s = 0;
+    for (int i = threadIdx.x; i < 4096; i += blockDim.x) s += (unsigned long long)row[i];
+    atomicAdd(out, s);
+}
+
 // Aligned random reads of W dwords per lane (the row holds 4096 dwords).
 template <int W>
 __global__ __launch_bounds__(256) void k_lds_wide(unsigned long long *out, int iters) {
@@ -160,6 +191,11 @@ int main() {
     const double nl = (double)blocks * threads * li * 8;
     if (run("lds_add_u64_random", [&] { hipLaunchKernelGGL((k_lds<unsigned long long, false>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_u32_random", [&] { hipLaunchKernelGGL((k_lds<unsigned int, false>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
+    if (run("lds_add_u64_consecutive", [&] { hipLaunchKernelGGL((k_lds_pattern<unsigned long long, PAT_CONSEC>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
+    if (run("lds_add_u64_four_lanes_per_entry", [&] { hipLaunchKernelGGL((k_lds_pattern<unsigned long long, PAT_CLUSTER4>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
+    if (run("lds_add_u32_consecutive", [&] { hipLaunchKernelGGL((k_lds_pattern<unsigned int, PAT_CONSEC>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
+    if (run("lds_add_f64_random", [&] { hipLaunchKernelGGL((k_lds<double, false>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
+    if (run("lds_add_f64_consecutive", [&] { hipLaunchKernelGGL((k_lds_pattern<double, PAT_CONSEC>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_read_b32_random", [&] { hipLaunchKernelGGL((k_lds<unsigned int, true>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_read_b64_random", [&] { hipLaunchKernelGGL(k_lds_wide<2>, dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl * 2)) return 1;
     if (run("lds_read_b128_random", [&] { hipLaunchKernelGGL(k_lds_wide<4>, dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl * 4)) return 1;

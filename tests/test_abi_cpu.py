@@ -75,6 +75,8 @@ def last():
     (dict(model=_model(profile=7)), _abi.SBP_E_DOMAIN),
     (dict(model=_model(directivity=-1)), _abi.SBP_E_DOMAIN),
     (dict(model=_model(gauss_K=0.0)), _abi.SBP_E_DOMAIN),
+    (dict(model=_model(gauss_K=12.5)), _abi.SBP_E_DOMAIN),
+    (dict(model=_model(gauss_K=float("inf"))), _abi.SBP_E_DOMAIN),
     (dict(model=_model(a_softplus=2)), _abi.SBP_E_DOMAIN),
     (dict(model=_model(t0=float("nan"))), _abi.SBP_E_DOMAIN),
     (dict(F=0), _abi.SBP_E_ARG),

@@ -62,7 +62,7 @@ def test_traffic_is_dropped_once_a_kernel_source_changes(tmp_path, monkeypatch):
 
 def test_edges_per_pair():
     # a 0.15 mm GAUSS ball (support 5 a) at 40 MHz and 1.5 mm/us: 40 bins, 41 edges
-    assert bench.edges_per_pair(0.75, 1.5 * 0.025) == pytest.approx(41.0)
+    assert bench.edges_per_pair(0.75, 1.5 * 0.025) == pytest.approx(40.0)
 
 
 def test_more_than_one_gpu_is_refused():

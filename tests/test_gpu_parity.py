@@ -433,6 +433,33 @@ def test_filter_matches_oracle(ctx):
             assert keep_g[:7].all()
 
 
+def test_filter_gradient_at_the_largest_truncation(ctx):
+    """K = 12 (the largest the interface takes) at a 16x decimated rate, balls
+    down to a fifth of c dt_k: the Gaussian recurrences' first ratios reach
+    exp(K^2 / 2) there.  The filter's p0-only gradient, the full adjoint's p0
+    gradient of v = -2 y_ref, and the oracle agree, and every value is finite."""
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(1212)
+    arr = synth.hemisphere_array(23, 12.0, rng, tilt_deg=20)
+    init = synth.uniform_balls(rng, 3000, 3.0, 0.1, 0.0, 0.2)
+    init["a"] = rng.uniform(0.02, 0.3, 3000).astype(np.float32)
+    gt = dict(init, p0=rng.uniform(0.5, 1.0, 3000).astype(np.float32))
+    T, f, K = 64, 16, 12.0
+    tm = otime(T, f=f, K=K)
+    y_ref = oracle.simulate(gt, arr, tm).astype(np.float32)
+    m = gmodel(T, f=f, K=K)
+    _, _, g, _ = api.filter_zero_grad(ctx, to_dev(arr, dev), to_dev(init, dev), m,
+                                      torch.as_tensor(y_ref[None], device=dev))
+    g = g.cpu().numpy()
+    _, g_o, _ = oracle.filter_zero_grad(init, arr, tm, y_ref)
+    full = run_adj(ctx, arr, init, m, -2.0 * y_ref, mask=api.P0)["p0"]
+    assert np.all(np.isfinite(g)) and np.all(np.isfinite(full))
+    assert rel_l2(g, g_o) <= GRAD_TOL and rel_l2(full, g_o) <= GRAD_TOL
+    with pytest.raises(api._abi.SbpError) as e:
+        run_fwd(ctx, arr, init, gmodel(T, f=f, K=12.5))
+    assert e.value.code == api._abi.SBP_E_DOMAIN
+
+
 def test_filter_frames(ctx):
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(121)
