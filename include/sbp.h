@@ -183,7 +183,7 @@ typedef struct sbp_tuning {
     int32_t fwd_grid;     /* persistent workgroups, 0 = as many as fit on the device */
     int32_t adj_dets;     /* transducer rows staged in LDS per pass, 1..16 */
     int32_t adj_block;    /* threads per workgroup: 64, 128, 256 or 512 */
-    int32_t adj_bpt;      /* balls per thread, 1..4 */
+    int32_t adj_bpt;      /* balls per thread, 1..3 */
     int32_t adj_grid;     /* persistent workgroups, 0 = as many as fit on the device */
     int32_t fwd_tile;     /* samples per LDS time tile, 0 = as many as fit, else >= 64 */
     int32_t adj_tile;     /* edges per LDS time tile, 0 = as many as fit, else >= 64 */

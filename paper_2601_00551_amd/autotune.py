@@ -17,13 +17,13 @@ import os
 
 FWD_SPACE = {"fwd_dets": (1, 2, 4, 8), "fwd_block": (256, 512), "fwd_bpt": (1, 2, 4),
              "fwd_tile": (0, 2048, 1024)}
-ADJ_SPACE = {"adj_dets": (2, 4, 8), "adj_block": (128, 256, 512), "adj_bpt": (1, 2, 4),
+ADJ_SPACE = {"adj_dets": (2, 4, 8), "adj_block": (128, 256, 512), "adj_bpt": (1, 2, 3),
              "adj_tile": (0, 2048)}
 # The launch-shape cache shipped with the package (tuned on an MI355X).
 DEFAULT_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 
 DEFAULTS = {"fwd_dets": 4, "fwd_block": 512, "fwd_bpt": 4, "fwd_grid": 0, "adj_dets": 4,
-            "adj_block": 512, "adj_bpt": 4, "adj_grid": 0, "fwd_tile": 0, "adj_tile": 0}
+            "adj_block": 512, "adj_bpt": 3, "adj_grid": 0, "fwd_tile": 0, "adj_tile": 0}
 
 
 def _bucket(n: int) -> int:

@@ -2,7 +2,8 @@
 
 Every HIP source is compiled with packed-FP32 instructions disabled (the
 compiler otherwise forms v_pk_* FP32 ops on its own) and with hardware float
-atomics for global memory.  Objects are cached by content hash under _build/
+atomics for global memory; the compiler's kernel resource-usage remarks are
+checked so that no forward or adjoint kernel uses scratch memory.  Objects are cached by content hash under _build/
 so that unchanged sources are not recompiled (unless `fresh`); the link
 always runs.
 """
@@ -42,14 +43,58 @@ def _digest(src):
     return h.hexdigest()[:16]
 
 
+# Kernels of the physics path (forward, adjoint, filter) must not use scratch
+# memory: the build fails if the compiler's resource-usage remarks report a
+# private segment or spilled VGPRs for any of their instantiations (SGPR spills
+# go to VGPR lanes, not to memory, and are allowed).
+PHYSICS_KERNELS = ("k_forward", "k_adjoint")
+REMARKS = "-Rpass-analysis=kernel-resource-usage"
+
+
+def resource_usage(text):
+    """{mangled kernel name: {field: int}} from the compiler's
+    kernel-resource-usage remarks."""
+    out, cur = {}, None
+    for line in text.splitlines():
+        if "remark:" not in line:
+            continue
+        body = line.split("remark:", 1)[1].split("[-Rpass", 1)[0].strip()
+        if body.startswith("Function Name:"):
+            cur = body.split(":", 1)[1].strip()
+            out[cur] = {}
+        elif cur is not None and ":" in body:
+            key, val = body.rsplit(":", 1)
+            try:
+                out[cur][key.strip()] = int(val.strip())
+            except ValueError:
+                pass
+    return out
+
+
+def check_no_scratch(usage, src):
+    bad = [f"{name}: ScratchSize {u.get('ScratchSize [bytes/lane]', 0)} B/lane, "
+           f"VGPRs Spill {u.get('VGPRs Spill', 0)}"
+           for name, u in usage.items()
+           if any(k in name for k in PHYSICS_KERNELS)
+           and (u.get("ScratchSize [bytes/lane]", 0) > 0 or u.get("VGPRs Spill", 0) > 0)]
+    if bad:
+        raise RuntimeError(f"{os.path.basename(src)}: physics kernels use scratch memory:\n  " +
+                           "\n  ".join(bad))
+
+
 def _compile(src, verbose, fresh=False):
     os.makedirs(BUILD, exist_ok=True)
     obj = os.path.join(BUILD, os.path.basename(src) + "." + _digest(src) + ".o")
     if fresh or not os.path.exists(obj):
-        cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj + ".tmp"]
+        cmd = [HIPCC] + FLAGS + [REMARKS, "-c", src, "-o", obj + ".tmp"]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        sys.stderr.write("".join(l + "\n" for l in r.stderr.splitlines()
+                                 if "remark:" not in l and "packed-fp32-ops" not in l))
+        if r.returncode != 0:
+            raise subprocess.CalledProcessError(r.returncode, cmd)
+        check_no_scratch(resource_usage(r.stderr), src)
         os.replace(obj + ".tmp", obj)
     return obj
 

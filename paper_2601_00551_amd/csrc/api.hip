@@ -85,23 +85,6 @@ int ensure_scratch(Ctx *c, size_t bytes) {
     return SBP_OK;
 }
 
-Level make_level(const sbp_model *m) {
-    Level lc;
-    const double dtk = (double)m->f * m->dt;
-    lc.ct0 = m->c * m->t0;
-    lc.cdt = m->c * dtk;
-    lc.inv_cdt = 1.0 / lc.cdt;
-    lc.inv2cdt_d = 1.0 / (2.0 * lc.cdt);
-    lc.K_d = m->gauss_K;
-    lc.eK_d = std::exp(-0.5 * m->gauss_K * m->gauss_K);
-    lc.cdt_f = (float)lc.cdt;
-    lc.inv2cdt = (float)lc.inv2cdt_d;
-    lc.K = (float)lc.K_d;
-    lc.eK = (float)lc.eK_d;
-    lc.T = m->T;
-    lc.a_softplus = m->a_softplus;
-    return lc;
-}
 
 // ----------------------------------------------------------- validation --
 
@@ -225,7 +208,7 @@ static int check_tuning(const sbp_tuning *t) {
         return fail(SBP_E_DOMAIN, "dets must be in [1, 16]");
     if (!okb(t->fwd_block) || !okb(t->adj_block)) return fail(SBP_E_DOMAIN, "block must be 64, 128, 256 or 512");
     if (t->fwd_bpt < 1 || t->fwd_bpt > 16) return fail(SBP_E_DOMAIN, "fwd_bpt must be in [1, 16]");
-    if (t->adj_bpt < 1 || t->adj_bpt > 4) return fail(SBP_E_DOMAIN, "adj_bpt must be in [1, 4]");
+    if (t->adj_bpt < 1 || t->adj_bpt > 3) return fail(SBP_E_DOMAIN, "adj_bpt must be in [1, 3]");
     if (t->fwd_grid < 0 || t->adj_grid < 0) return fail(SBP_E_DOMAIN, "grid must be >= 0");
     if ((t->fwd_tile != 0 && t->fwd_tile < 64) || (t->adj_tile != 0 && t->adj_tile < 64))
         return fail(SBP_E_DOMAIN, "tile must be 0 or >= 64");
@@ -278,7 +261,7 @@ int sbp_ctx_create(sbp_ctx **out, int device) {
     size_t lds = prop.sharedMemPerBlock;
     if (prop.maxSharedMemoryPerMultiProcessor > lds) lds = prop.maxSharedMemoryPerMultiProcessor;
     ctx->c.lds_max = lds;
-    ctx->c.tuning = sbp_tuning{4, 512, 4, 0, 4, 512, 4, 0, 0, 0};
+    ctx->c.tuning = sbp_tuning{4, 512, 4, 0, 4, 512, 3, 0, 0, 0};
     if (hipMalloc((void **)&ctx->c.misc, kMiscBytes) != hipSuccess) {
         (void)hipGetLastError();
         delete ctx;

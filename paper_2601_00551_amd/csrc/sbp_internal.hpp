@@ -18,7 +18,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 #include "../../include/sbp.h"
+
+// The per-pair arithmetic is also compiled for the host (a test checks its
+// FP64 instantiation against the CPU oracle there).
+#define SBP_HD __host__ __device__
 
 namespace sbp {
 
@@ -58,28 +64,42 @@ template <> struct LevelR<float> {
     __device__ static float eK(const Level &l) { return l.eK; }
 };
 template <> struct LevelR<double> {
-    __device__ static double cdt(const Level &l) { return l.cdt; }
-    __device__ static double inv2cdt(const Level &l) { return l.inv2cdt_d; }
-    __device__ static double eK(const Level &l) { return l.eK_d; }
+    SBP_HD static double cdt(const Level &l) { return l.cdt; }
+    SBP_HD static double inv2cdt(const Level &l) { return l.inv2cdt_d; }
+    SBP_HD static double eK(const Level &l) { return l.eK_d; }
 };
 
-Level make_level(const sbp_model *m);
+inline Level make_level(const sbp_model *m) {
+    Level lc;
+    const double dtk = (double)m->f * m->dt;
+    lc.ct0 = m->c * m->t0;
+    lc.cdt = m->c * dtk;
+    lc.inv_cdt = 1.0 / lc.cdt;
+    lc.inv2cdt_d = 1.0 / (2.0 * lc.cdt);
+    lc.K_d = m->gauss_K;
+    lc.eK_d = std::exp(-0.5 * m->gauss_K * m->gauss_K);
+    lc.cdt_f = (float)lc.cdt;
+    lc.inv2cdt = (float)lc.inv2cdt_d;
+    lc.K = (float)lc.K_d;
+    lc.eK = (float)lc.eK_d;
+    lc.T = m->T;
+    lc.a_softplus = m->a_softplus;
+    return lc;
+}
 
 // ------------------------------------------------------------ device math --
 
-template <typename R> __device__ inline R ex2(R x);
-template <> __device__ inline float ex2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
-template <> __device__ inline double ex2<double>(double x) { return exp2(x); }
-
-template <typename R> __device__ inline R rcp(R x);
-template <> __device__ inline float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <> __device__ inline double rcp<double>(double x) { return 1.0 / x; }
+// FP32: the hardware instructions (device only); FP64: the library functions.
+__device__ inline float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+SBP_HD inline double ex2(double x) { return exp2(x); }
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+SBP_HD inline double rcp(double x) { return 1.0 / x; }
 
 // a = softplus(a~) (identity above 20, as PyTorch) and d a / d a~ = sigmoid(a~).
-template <typename R> __device__ inline R softplus_dev(R x) {
+template <typename R> SBP_HD inline R softplus_dev(R x) {
     return x > R(20) ? x : log1p(exp(x));
 }
-template <typename R> __device__ inline R sigmoid_dev(R x) { return R(1) / (R(1) + exp(-x)); }
+template <typename R> SBP_HD inline R sigmoid_dev(R x) { return R(1) / (R(1) + exp(-x)); }
 
 // Per-ball constants.
 template <typename R, int PROF>
@@ -94,7 +114,7 @@ struct BallK {
 };
 
 template <typename R, int PROF>
-__device__ inline BallK<R, PROF> load_ball(R x, R y, R z, R p, R araw, const Level &lc) {
+SBP_HD inline BallK<R, PROF> load_ball(R x, R y, R z, R p, R araw, const Level &lc) {
     BallK<R, PROF> b;
     R a = lc.a_softplus ? softplus_dev(araw) : araw;
     b.x = x;
@@ -120,7 +140,7 @@ __device__ inline BallK<R, PROF> load_ball(R x, R y, R z, R p, R araw, const Lev
 
 // q(u) such that psi(u) = amp * max(q(u), 0) with amp = ampk * D / (2 rho c dt).
 template <typename R, int PROF>
-__device__ inline R shape_q(R u, const BallK<R, PROF> &b, R eK) {
+SBP_HD inline R shape_q(R u, const BallK<R, PROF> &b, R eK) {
     if (PROF == UNIFORM) return b.q0 - u * u;
     return ex2(u * u * b.q0) - eK;
 }
@@ -137,14 +157,14 @@ struct PairG {
 
 // Returns false if the pair contributes nothing (near field, facing away).
 template <typename R, int DIR>
-__device__ inline bool pair_geometry(R bx, R by, R bz, R w, R qx, R qy, R qz,
+SBP_HD inline bool pair_geometry(R bx, R by, R bz, R w, R qx, R qy, R qz,
                                      R nx, R ny, R nz, const Level &lc, PairG<R> &g) {
     const double dx = (double)bx - (double)qx, dy = (double)by - (double)qy,
                  dz = (double)bz - (double)qz;
     const double r2 = dx * dx + dy * dy + dz * dz;
     double rho;
     R inv_rho;
-    if (sizeof(R) == 4) {
+    if constexpr (sizeof(R) == 4) {
         // FP32 square root refined by one Newton step in FP64: relative error
         // about 1e-14, from a half-rate FP32 root instead of the FP64 one
         const float r0 = __builtin_amdgcn_sqrtf((float)r2);
@@ -199,7 +219,7 @@ static_assert((kMiscFlags + SBP_MAX_FRAMES) * sizeof(unsigned) <= kMiscBytes, "m
 // sample of that frame and the adjoint writes NaN to every gradient of that
 // ball.
 template <typename R>
-__device__ inline bool ball_finite(R x, R y, R z, R p, R a) {
+SBP_HD inline bool ball_finite(R x, R y, R z, R p, R a) {
     return isfinite(x) && isfinite(y) && isfinite(z) && isfinite(p) && isfinite(a);
 }
 

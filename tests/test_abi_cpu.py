@@ -220,7 +220,7 @@ def test_tuning_validation():
     lib = _abi.lib()
     t = _abi.SbpTuning(4, 512, 2, 0, 4, 256, 2, 0)
     assert lib.sbp_ctx_set_tuning(None, ctypes.byref(t)) == _abi.SBP_E_ARG and "ctx" in last()
-    for field, val in (("fwd_dets", 0), ("fwd_dets", 17), ("fwd_block", 100), ("adj_bpt", 5), ("adj_grid", -1),
+    for field, val in (("fwd_dets", 0), ("fwd_dets", 17), ("fwd_block", 100), ("adj_bpt", 4), ("adj_grid", -1),
                        ("fwd_tile", 10), ("adj_tile", -1)):
         bad = _abi.SbpTuning(4, 512, 2, 0, 4, 256, 2, 0)
         setattr(bad, field, val)

@@ -69,7 +69,7 @@ def test_forward_clipping_at_record_start_and_levels(ctx):
     dict(fwd_dets=16, fwd_block=128, fwd_bpt=16, fwd_grid=1),
     dict(fwd_dets=16, fwd_block=256, fwd_bpt=2, fwd_grid=0, adj_dets=16, adj_block=256, adj_bpt=1),
     dict(adj_dets=1, adj_block=64, adj_bpt=1, adj_grid=0),
-    dict(adj_dets=5, adj_block=512, adj_bpt=4, adj_grid=3),
+    dict(adj_dets=5, adj_block=512, adj_bpt=3, adj_grid=3),
     dict(adj_dets=16, adj_block=128, adj_bpt=2, adj_grid=1),
     dict(fwd_dets=2, fwd_tile=128, adj_dets=3, adj_tile=100),
     dict(fwd_dets=4, fwd_tile=64, fwd_grid=5, adj_dets=4, adj_tile=64, adj_block=64, adj_bpt=1),
@@ -104,7 +104,7 @@ def test_forward_bitwise_reproducible(ctx):
     ys, gs = [], []
     old = ctx.tuning
     try:
-        for t in (dict(fwd_dets=4, fwd_block=512, fwd_bpt=4, adj_dets=4, adj_block=512, adj_bpt=4),
+        for t in (dict(fwd_dets=4, fwd_block=512, fwd_bpt=4, adj_dets=4, adj_block=512, adj_bpt=3),
                   dict(fwd_dets=1, fwd_block=256, fwd_bpt=1, adj_dets=2, adj_block=128, adj_bpt=1),
                   dict(fwd_dets=8, fwd_block=128, fwd_bpt=2, fwd_grid=7)):
             ctx.tuning = t

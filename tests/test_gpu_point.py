@@ -97,7 +97,7 @@ def test_point_adjoint_masks(ctx):
 
 @pytest.mark.parametrize("tuning", [
     dict(fwd_dets=1, fwd_block=64, fwd_bpt=1, adj_dets=1, adj_block=64, adj_bpt=1),
-    dict(fwd_dets=3, fwd_block=256, fwd_bpt=4, fwd_grid=7, adj_dets=5, adj_block=512, adj_bpt=4, adj_grid=3),
+    dict(fwd_dets=3, fwd_block=256, fwd_bpt=4, fwd_grid=7, adj_dets=5, adj_block=512, adj_bpt=3, adj_grid=3),
     dict(fwd_dets=2, fwd_tile=128, adj_dets=3, adj_tile=100),
 ])
 def test_point_launch_shapes_agree(ctx, tuning):
