@@ -395,6 +395,92 @@ def suite(args):
     ctx.close()
 
 
+def response_leg(ctx, wl, A, model, args, ms_plain):
+    """The same step with each transducer's impulse response in the model
+    (2.02 MHz, 54 % means with a seeded spread): the measured record is the
+    convolved one, the filter and the adjoint correlate first.  Reports the
+    step time and rate with the response on (the cloud then evolves
+    differently, so its ball counts are given), the convolution's and the
+    correlation's own times, and what they add to a step."""
+    import numpy as np
+    import torch
+    from paper_2601_00551_amd import api, synth
+    dev = torch.device("cuda:0")
+    D, T = len(wl.array["qx"]), model.T
+    fc, bw = synth.element_responses(D, np.random.default_rng(4000))
+    m = api.with_response(ctx, model, torch.as_tensor(fc, device=dev), torch.as_tensor(bw, device=dev))
+    gt = {k: torch.as_tensor(v, device=dev) for k, v in wl.init.items()}
+    gt["p0"] = gt["p0"] * 1.5
+    y_real = api.simulate_signals(ctx, A, gt, m)
+    del gt
+    rng = np.random.default_rng(3001)
+    sigma = 0.05 * float(y_real.abs().max())
+    y_real += sigma * torch.as_tensor(rng.normal(size=tuple(y_real.shape)).astype(np.float32), device=dev)
+    cap = args.balls
+    a = api.State(wl.init, capacity=cap, device=dev)
+    b = api.State({k: np.zeros(0) for k in api.PARAMS}, ball_off=[0, 0], capacity=cap, device=dev)
+    y_k = torch.empty_like(y_real)
+    y_work = torch.empty_like(y_real)
+    prm = api.AdamParams(lr=(0.005, 0.005, 0.005, 0.02, 0.002), step=1)
+    rule = api.GrowthRule(destroy_frac=0.02, a_min=0.02, a_split=0.3, dup_frac=0.0)
+
+    def one():
+        api.downsample(ctx, y_real, 1, out=y_k)
+        api.filter_zero_grad(ctx, A, a.balls, m, y_k, ball_off=a.ball_off, strict=True, out=b.balls,
+                             off_out=b.ball_off, B_cap=a.B_cap, moments=(a.m, a.v), moments_out=(b.m, b.v))
+        api.simulate_signals(ctx, A, b.balls, m, ball_off=b.ball_off, y=y_work, B_cap=b.B_cap)
+        api.residual_loss(ctx, y_work, y_k, v_out=y_work)
+        api.adjoint_gradients(ctx, A, b.balls, m, y_work, mask=api.ALL, ball_off=b.ball_off,
+                              grad=b.grad, B_cap=b.B_cap)
+        api.adam_update(ctx, b, prm)
+        new, _ = api.grow(ctx, b, rule, capacity=cap)
+        for k in api.PARAMS:
+            a.balls[k], new.balls[k] = new.balls[k], a.balls[k]
+            a.m[k], new.m[k] = new.m[k], a.m[k]
+            a.v[k], new.v[k] = new.v[k], a.v[k]
+        a.ball_off.copy_(new.ball_off)
+        prm.step += 1
+
+    for _ in range(args.warmup):
+        one()
+    n_in = [a.count()]
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.response_steps):
+        one()
+        n_in.append(a.count())
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.response_steps
+    # the convolution and the correlation on their own, over the whole record
+    h, zero = m.response, m.response_zero
+    L = h.shape[1]
+    times = {}
+    for name, adj in (("convolve", False), ("correlate", True)):
+        api.response_apply(ctx, h, zero, y_k, adjoint=adj, out=y_work)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(10):
+            api.response_apply(ctx, h, zero, y_k, adjoint=adj, out=y_work)
+        e1.record()
+        torch.cuda.synchronize()
+        times[name] = e0.elapsed_time(e1) / 10
+    fmas = float(D) * T * L
+    # per step the response adds one convolution (simulate) and two
+    # correlations (filter reference, adjoint cotangent)
+    added = times["convolve"] + 2 * times["correlate"]
+    out = {"taps": L, "rows": D, "sampling_MHz": round(1.0 / model.dt), "steps": args.response_steps,
+           "ms_per_step": ms, "pairs_per_s": float(np.mean(n_in[:-1])) * D / (ms * 1e-3),
+           "balls_in_per_step": float(np.mean(n_in[:-1])), "kept_by_filter": int(b.ball_off[-1].item()),
+           "added_ms_per_step": added, "added_fraction_of_plain_step": added / ms_plain}
+    for name, t in times.items():
+        out[name] = {"ms": t, "fma_per_launch": fmas, "achieved_TOPs": fmas / (t * 1e-3) / 1e12,
+                     "frac": fmas / (t * 1e-3) / VALU_PEAK, "hbm_bytes": 8.0 * D * T,
+                     "hbm_GBs": 8.0 * D * T / (t * 1e-3) / 1e9}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -407,6 +493,8 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy (the reference for HBM counters)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain reconstruction timing")
+    ap.add_argument("--response-steps", type=int, default=3,
+                    help="steps timed again with a transducer response per element (0 = skip)")
     ap.add_argument("--suite", action="store_true",
                     help="measure the other workloads instead (one JSON line each)")
     ap.add_argument("--rates", action="store_true",
@@ -579,6 +667,10 @@ def main():
         "tuning": tuned,
         "wall_s": wall,
     }
+    if args.response_steps > 0:
+        del st, y_work, y_k
+        torch.cuda.empty_cache()
+        line["response"] = response_leg(ctx, wl, A, model, args, ms_step)
     line["mlp"] = mlp_rates(ctx, dev)
     if not args.no_learned:
         line["learned_vs_plain"] = learned_vs_plain(ctx)

@@ -77,6 +77,7 @@ extern "C" {
 #define SBP_COARSE (SBP_P0 | SBP_A) /* coarse stage: positions fixed (section 4.1) */
 
 #define SBP_MAX_FRAMES 64 /* F may not exceed this */
+#define SBP_MAX_TAPS 4095 /* longest transducer response, in taps */
 
 /* ------------------------------------------------------------ types ----- */
 
@@ -87,7 +88,19 @@ extern "C" {
  * pyramid is sbp_decimate).  a_softplus = 1 means the `a` arrays hold the
  * unconstrained a~ and the size is a = softplus(a~) = log(1 + e^a~) (the
  * positivity-constrained refinement of section 4.3); gradients are then with
- * respect to a~. */
+ * respect to a~.
+ * Transducer response (optional; response = NULL leaves it out, and the other
+ * three response fields are then ignored): the modelled record is the
+ * simulated record convolved in time with the element's impulse response,
+ *   y[f][d][n] = sum_{j < L} h[row(d)][j] * s[f][d][n + zero - j]
+ * (s the record described under sbp_simulate_signals, zero outside [0, T)),
+ * with tap j at lag (j - zero) dt_k, row(d) = d when response_rows = D and 0
+ * when response_rows = 1.  The taps must be those of this level's interval
+ * dt_k (sbp_response_taps).  sbp_simulate_signals then returns y,
+ * sbp_adjoint_gradients and sbp_filter_zero_grad take their cotangent and
+ * reference with respect to y (they correlate it with the taps first), and
+ * sbp_step fits y to y_ref.  The three calls and the step need F D T more
+ * elements of scratch for the intermediate record. */
 typedef struct sbp_model {
     double c;          /* speed of sound, mm/us, > 0 */
     double dt;         /* base sample interval, us, > 0 */
@@ -100,6 +113,11 @@ typedef struct sbp_model {
     int32_t directivity; /* SBP_DIR_* */
     int32_t a_softplus;  /* 0 or 1 */
     int32_t sampling;    /* SBP_SAMPLING_*; other values: SBP_E_DOMAIN */
+    const float *response; /* NULL, or device taps [response_rows][response_taps] */
+    int32_t response_taps; /* L, 1..SBP_MAX_TAPS */
+    int32_t response_zero; /* the tap at zero lag, 0 <= zero < L */
+    int32_t response_rows; /* 1 (one response for every transducer) or D */
+    int32_t reserved;      /* 0 */
 } sbp_model;
 
 /* Transducer array: D positions q and unit normals n (SoA, device, float). */
@@ -253,7 +271,8 @@ int sbp_decimate(sbp_ctx *ctx, const float *y, int64_t R, int32_t T, int32_t f,
  * two roundings), so a ball whose values are 10^k times smaller than the
  * bound keeps about 29 - 3.3 k significant bits.
  * The context's scratch holds 8 bytes per output sample (plus one per
- * transducer row) and 24 bytes per ball of B_cap during the call.
+ * transducer row) and 24 bytes per ball of B_cap during the call, and 4 more
+ * per output sample with a transducer response (the record before it).
  * Errors: SBP_E_ARG, SBP_E_DOMAIN, SBP_E_HIP, SBP_E_NOMEM. */
 int sbp_simulate_signals(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *balls,
                          const int64_t *ball_off, int32_t F, int64_t B_cap,
@@ -265,8 +284,9 @@ int sbp_simulate_signals(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *ba
  * workspace is a fixed device array of 128 MiB per GPU, held from the first
  * sbp_ctx_create on that GPU until the process ends, instead of the
  * context's scratch; the call makes no allocation of any kind.  Limit: the
- * workspace the call needs, 8 (T + 1) F D + 24 B_cap bytes (each part rounded
- * up to 256 bytes) plus 512, must fit in 128 MiB, else SBP_E_CAPACITY before
+ * workspace the call needs, 8 (T + 1) F D + 24 B_cap bytes, plus 4 T F D with
+ * a transducer response (each part rounded up to 256 bytes), plus 512, must
+ * fit in 128 MiB, else SBP_E_CAPACITY before
  * anything is enqueued.  Every call on one GPU, through any context, shares
  * that GPU's array: the call clears what it needs zeroed, but calls that
  * overlap on one GPU (other streams, other threads) race and must not be
@@ -367,6 +387,51 @@ int sbp_softplus_reparam(sbp_ctx *ctx, sbp_state *state, int32_t to_softplus, vo
  * unspecified), SBP_E_HIP. */
 int sbp_grow(sbp_ctx *ctx, const sbp_state *in, const sbp_growth_rule *rule, sbp_state *out,
              int64_t *count, void *stream);
+
+/* ------------------------------------------- transducer response ----- */
+/* The elements of the in vivo array of section 2.2 have a mean centre
+ * frequency of 2.02 MHz and a bandwidth of 54 %; the forward model of
+ * sections 4.2 and 4.3 leaves the element's response out.  These calls model
+ * it as a Gaussian-envelope cosine,
+ *   h(t) = A exp(-t^2 / (2 s_t^2)) cos(2 pi fc t),
+ * whose amplitude spectrum is a Gaussian centred on fc with full width bw fc
+ * at half its peak (-6 dB): s_f = bw fc / (2 sqrt(2 ln 2)),
+ * s_t = 1 / (2 pi s_f), A = 2 / (s_t sqrt(2 pi)) (unit gain at fc).  fc in
+ * MHz, bw a fraction, t in us. */
+
+/* Tap count and zero-lag tap that cover +-n_sigma envelope widths s_t of the
+ * widest response (the one of least fc * bw) at interval dt_k:
+ * zero = ceil(n_sigma s_t / dt_k), L = 2 zero + 1.  Host-only; no context.
+ * Errors: SBP_E_ARG (NULL outputs), SBP_E_DOMAIN (fc, bw, dt_k or n_sigma
+ * not positive and finite), SBP_E_CAPACITY (L > SBP_MAX_TAPS). */
+int sbp_response_length(double fc, double bw, double dt_k, double n_sigma, int32_t *L,
+                        int32_t *zero);
+
+/* Taps h[r][j] = dt_k h_r((j - zero) dt_k) of rows responses (device arrays
+ * fc[rows], bw[rows]), computed in FP64 and rounded to float once; the factor
+ * dt_k turns the convolution integral into the sum over taps.  h is
+ * [rows][L], device.  A row whose fc or bw is not positive and finite gets
+ * NaN taps.
+ * Errors: SBP_E_ARG (NULL, rows < 1), SBP_E_DOMAIN (dt_k not positive and
+ * finite, L outside [1, SBP_MAX_TAPS], zero outside [0, L)). */
+int sbp_response_taps(sbp_ctx *ctx, const float *fc, const float *bw, int32_t rows, double dt_k,
+                      int32_t L, int32_t zero, float *h, void *stream);
+
+/* Apply the response to R = F D records of T samples (row r is transducer
+ * r mod D):
+ *   adjoint = 0:  out[r][n] (+)= sum_j h[row][j] y[r][n + zero - j]
+ *   adjoint = 1:  out[r][n] (+)= sum_j h[row][j] y[r][n - zero + j]
+ * (the correlation, the adjoint of the convolution), zeros outside [0, T),
+ * row = 0 when rows_h = 1 and r mod D when rows_h = D.  The sum runs in the
+ * records' precision with the taps in a fixed order, so results are
+ * reproducible.  out is overwritten unless accumulate = 1; it must not
+ * overlap y.
+ * Errors: SBP_E_ARG (NULL, R < 1, D < 1, R not a multiple of D when
+ * rows_h = D, rows_h not 1 or D, out overlapping y, flags not 0 or 1),
+ * SBP_E_DOMAIN (T < 1, L outside [1, SBP_MAX_TAPS], zero outside [0, L)). */
+int sbp_response_apply(sbp_ctx *ctx, const float *h, int32_t rows_h, int32_t L, int32_t zero,
+                       const float *y, int64_t R, int32_t D, int32_t T, int32_t adjoint,
+                       int32_t accumulate, float *out, void *stream);
 
 /* Double-precision twins of sbp_simulate_signals and sbp_adjoint_gradients
  * (same contract, FP64 buffers), used to check gradients by finite

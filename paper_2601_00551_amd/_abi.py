@@ -27,6 +27,7 @@ SAMPLING_BIN, SAMPLING_POINT = 0, 1
 X, Y, Z, P0, A = 1, 2, 4, 8, 16
 XYZ, ALL, COARSE = 7, 31, 24
 MAX_FRAMES = 64
+MAX_TAPS = 4095
 
 P = ctypes.c_void_p
 
@@ -35,7 +36,10 @@ class SbpModel(ctypes.Structure):
     _fields_ = [("c", ctypes.c_double), ("dt", ctypes.c_double), ("t0", ctypes.c_double),
                 ("gauss_K", ctypes.c_double), ("T", ctypes.c_int32), ("f", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("directivity", ctypes.c_int32),
-                ("a_softplus", ctypes.c_int32), ("sampling", ctypes.c_int32)]
+                ("a_softplus", ctypes.c_int32), ("sampling", ctypes.c_int32),
+                ("response", ctypes.c_void_p), ("response_taps", ctypes.c_int32),
+                ("response_zero", ctypes.c_int32), ("response_rows", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class SbpArray(ctypes.Structure):
@@ -110,6 +114,11 @@ SIGNATURES = {
     "sbp_graph_destroy": (ctypes.c_int, [P]),
     "sbp_grow": (ctypes.c_int, [P, PS, PG, PS, ctypes.POINTER(I64), P]),
     "sbp_softplus_reparam": (ctypes.c_int, [P, PS, I32, P]),
+    "sbp_response_length": (ctypes.c_int, [ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.POINTER(I32),
+                                           ctypes.POINTER(I32)]),
+    "sbp_response_taps": (ctypes.c_int, [P, P, P, I32, ctypes.c_double, I32, I32, P, P]),
+    "sbp_response_apply": (ctypes.c_int, [P, P, I32, I32, I32, P, I64, I32, I32, I32, I32, P, P]),
     "sbp_simulate_signals_f64": (ctypes.c_int, [P, PA, PB, P, I32, I64, PM, P, I32, P]),
     "sbp_adjoint_gradients_f64": (ctypes.c_int, [P, PA, PB, P, I32, I64, PM, P, U32, PB, P]),
     # sbp_mlp.h

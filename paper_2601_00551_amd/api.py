@@ -34,14 +34,31 @@ class Model:
     gauss_K: float = 5.0
     a_softplus: int = 0
     sampling: int = SAMPLING_BIN   # SAMPLING_POINT: point-sampled variant (GAUSS only)
+    # transducer response: taps [rows][L] (float32, device) of this level's
+    # interval f dt, rows 1 or D (see with_response), and the zero-lag tap
+    response: object = None
+    response_zero: int = 0
 
     def struct(self) -> _abi.SbpModel:
+        h = self.response
+        if h is not None:
+            _need(h, torch.float32, "response")
+            if h.dim() != 2 or h.shape[1] < 1:
+                raise ValueError("response must be [rows, L]")
+            if not 0 <= int(self.response_zero) < h.shape[1]:
+                raise ValueError("response_zero must be in [0, L)")
         return _abi.SbpModel(float(self.c), float(self.dt), float(self.t0), float(self.gauss_K),
                              int(self.T), int(self.f), int(self.profile), int(self.directivity),
-                             int(self.a_softplus), int(self.sampling))
+                             int(self.a_softplus), int(self.sampling),
+                             None if h is None else h.data_ptr(),
+                             0 if h is None else int(h.shape[1]), int(self.response_zero),
+                             0 if h is None else int(h.shape[0]), 0)
 
     def level(self, f: int, T_base: int) -> "Model":
-        """The level with downsampling factor f of a record of T_base samples."""
+        """The level with downsampling factor f of a record of T_base samples
+        (without a response: its taps depend on the level's interval)."""
+        if self.response is not None:
+            raise ValueError("a model with a response: attach each level's taps with with_response")
         return dataclasses.replace(self, f=int(f), T=int(T_base) // int(f))
 
 
@@ -224,6 +241,59 @@ def adjoint_gradients(ctx, arr, balls, model: Model, v, mask=ALL, ball_off=None,
              _p(off), F, cap, ctypes.byref(model.struct()), _p(v), int(mask),
              ctypes.byref(balls_struct(grad, dtype)), _stream(stream)))
     return grad
+
+
+# ---------------------------------------------------- transducer response --
+
+def response_length(fc: float, bw: float, dt_k: float, n_sigma: float = 5.0):
+    """sbp_response_length: (L, zero) covering +-n_sigma envelope widths of
+    the response of centre fc (MHz) and fractional bandwidth bw."""
+    L, zero = _abi.I32(), _abi.I32()
+    check(lib().sbp_response_length(float(fc), float(bw), float(dt_k), float(n_sigma),
+                                    ctypes.byref(L), ctypes.byref(zero)))
+    return int(L.value), int(zero.value)
+
+
+def response_taps(ctx, fc, bw, dt_k: float, L: int, zero: int, out=None, stream=None):
+    """sbp_response_taps: taps [rows, L] of the responses fc[rows] (MHz),
+    bw[rows] (device float32)."""
+    _need(fc, torch.float32, "fc")
+    _need(bw, torch.float32, "bw")
+    rows = fc.numel()
+    _exactly(bw, rows, "bw")
+    if out is None:
+        out = torch.empty((rows, int(L)), dtype=torch.float32, device=fc.device)
+    _exactly(_need(out, torch.float32, "out"), rows * int(L), "out")
+    check(lib().sbp_response_taps(ctx.ptr, _p(fc), _p(bw), rows, float(dt_k), int(L), int(zero),
+                                  _p(out), _stream(stream)))
+    return out
+
+
+def response_apply(ctx, h, zero: int, y, adjoint=False, out=None, accumulate=False, stream=None):
+    """sbp_response_apply on y [..., D, T] with taps h [rows, L] (rows 1 or D):
+    the convolution (adjoint=False) or the correlation."""
+    _need(h, torch.float32, "h")
+    _need(y, torch.float32, "y")
+    if h.dim() != 2 or y.dim() < 2:
+        raise ValueError("h must be [rows, L] and y [..., D, T]")
+    D, T = y.shape[-2], y.shape[-1]
+    R = y.numel() // T
+    if out is None:
+        out = torch.empty_like(y)
+    _exactly(_need(out, torch.float32, "out"), y.numel(), "out")
+    check(lib().sbp_response_apply(ctx.ptr, _p(h), int(h.shape[0]), int(h.shape[1]), int(zero), _p(y),
+                                   R, D, T, int(bool(adjoint)), int(bool(accumulate)), _p(out),
+                                   _stream(stream)))
+    return out
+
+
+def with_response(ctx, model: Model, fc, bw, n_sigma: float = 5.0) -> Model:
+    """model with the taps of the responses (fc, bw: device float32, one entry
+    or one per transducer) at its interval f dt, long enough for the widest."""
+    i = int(torch.argmin(fc * bw).item())      # the widest envelope sets the length
+    L, zero = response_length(float(fc[i].item()), float(bw[i].item()), model.f * model.dt, n_sigma)
+    h = response_taps(ctx, fc, bw, model.f * model.dt, L, zero)
+    return dataclasses.replace(model, response=h, response_zero=zero)
 
 
 def simulate_signals_f64(ctx, arr, balls, model, **kw):

@@ -9,6 +9,7 @@ always runs.
 """
 import hashlib
 import os
+import re
 import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -82,6 +83,22 @@ def check_no_scratch(usage, src):
                            "\n  ".join(bad))
 
 
+def _without_remarks(text):
+    """Compiler output minus the resource-usage remarks (and the source lines
+    quoted under them) and the host pass's packed-fp32 notice."""
+    out, in_remark = [], False
+    for line in text.splitlines():
+        if "remark:" in line:
+            in_remark = True
+            continue
+        if in_remark and re.match(r"^\s*(\d+\s*)?\|", line):
+            continue
+        in_remark = False
+        if "packed-fp32-ops" not in line:
+            out.append(line)
+    return out
+
+
 def _compile(src, verbose, fresh=False):
     os.makedirs(BUILD, exist_ok=True)
     obj = os.path.join(BUILD, os.path.basename(src) + "." + _digest(src) + ".o")
@@ -90,8 +107,7 @@ def _compile(src, verbose, fresh=False):
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
-        sys.stderr.write("".join(l + "\n" for l in r.stderr.splitlines()
-                                 if "remark:" not in l and "packed-fp32-ops" not in l))
+        sys.stderr.write("".join(l + "\n" for l in _without_remarks(r.stderr)))
         if r.returncode != 0:
             raise subprocess.CalledProcessError(r.returncode, cmd)
         check_no_scratch(resource_usage(r.stderr), src)

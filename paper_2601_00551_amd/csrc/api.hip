@@ -111,7 +111,63 @@ static int check_model(const sbp_model *m) {
     if (m->profile == SBP_PROFILE_GAUSS &&
         (!(m->gauss_K > 0.0) || !(m->gauss_K <= kMaxGaussK)))
         return fail(SBP_E_DOMAIN, "gauss_K must be in (0, %g]", kMaxGaussK);
+    if (m->reserved != 0) return fail(SBP_E_ARG, "model.reserved must be 0");
+    if (m->response) {
+        if (m->response_taps < 1 || m->response_taps > SBP_MAX_TAPS)
+            return fail(SBP_E_DOMAIN, "response_taps must be in [1, %d]", SBP_MAX_TAPS);
+        if (m->response_zero < 0 || m->response_zero >= m->response_taps)
+            return fail(SBP_E_DOMAIN, "response_zero must be in [0, response_taps)");
+    }
     return SBP_OK;
+}
+
+// The response rows must match the array (checked where D is known).
+static int check_response_rows(const sbp_model *m, int D) {
+    if (m->response && m->response_rows != 1 && m->response_rows != D)
+        return fail(SBP_E_ARG, "response_rows must be 1 or D (%d), not %d", D, m->response_rows);
+    return SBP_OK;
+}
+
+static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Scratch for the record before (forward) or after (adjoint) the response.
+static size_t response_ws_bytes(const sbp_model *m, int F, int D, size_t elem) {
+    return m->response ? up256((size_t)F * (size_t)D * (size_t)m->T * elem) : 0;
+}
+
+template <typename R>
+static int apply_response(const sbp_model *m, const R *y, int F, int D, int adjoint, int accumulate,
+                          R *out, hipStream_t st) {
+    return launch_response<R>(m->response, m->response_rows, m->response_taps, m->response_zero,
+                              y, (int64_t)F * D, D, m->T, adjoint, accumulate, out, st);
+}
+
+// Forward with the model's response: the simulated record goes to `sim`
+// (F D T elements of scratch), then its convolution to y.
+template <typename R>
+static int forward_with_response(Ctx *c, const ArrayP<R> &a, const BallsP<R> &b, const int64_t *off,
+                                 int F, int64_t B_cap, const sbp_model *m, R *y, int accumulate,
+                                 unsigned *misc, void *ws, size_t ws_bytes, R *sim, hipStream_t st) {
+    if (!m->response)
+        return launch_forward<R>(c, a, b, off, F, B_cap, m, y, accumulate, misc, ws, ws_bytes, st);
+    int rc = launch_forward<R>(c, a, b, off, F, B_cap, m, sim, 0, misc, ws, ws_bytes, st);
+    if (rc) return rc;
+    return apply_response<R>(m, sim, F, a.D, 0, accumulate, y, st);
+}
+
+// Adjoint with the model's response: the cotangent of y is correlated with
+// the taps into `vsim` (F D T elements of scratch) first.
+template <typename R>
+static int adjoint_with_response(Ctx *c, const ArrayP<R> &a, const BallsP<R> &b, const int64_t *off,
+                                 int F, int64_t B_cap, const sbp_model *m, const R *v, R vscale,
+                                 uint32_t mask, const BallsP<R> &g, void *ws, size_t ws_bytes,
+                                 R *vsim, hipStream_t st, const int32_t *order = nullptr) {
+    if (m->response) {
+        int rc = apply_response<R>(m, v, F, a.D, 1, 0, vsim, st);
+        if (rc) return rc;
+        v = vsim;
+    }
+    return launch_adjoint<R>(c, a, b, off, F, B_cap, m, v, vscale, mask, g, ws, ws_bytes, st, order);
 }
 
 template <typename A>
@@ -216,22 +272,24 @@ static int check_tuning(const sbp_tuning *t) {
 }
 
 // One iteration, shared by sbp_step and the graph capture.
+// y_aux: F D T floats of scratch when the model has a transducer response
+// (the simulated record before it, then the correlated cotangent).
 static int step_body(Ctx *c, const sbp_array *arr, sbp_state *s, const sbp_model *model,
                      const float *y_ref, float *y_work, const sbp_adam_params *p,
                      const int32_t *step_dev, double *loss, double *partial, unsigned *misc,
                      void *fwd_ws, size_t fwd_ws_bytes, void *adj_ws, size_t adj_ws_bytes,
-                     hipStream_t st) {
+                     float *y_aux, hipStream_t st) {
     const ArrayP<float> a = arrp<float>(arr);
     const BallsP<float> b = ballsp<float>(&s->balls);
     const BallsP<float> g = ballsp<float>(&s->grad);
-    int rc = launch_forward<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 0, misc,
-                                   fwd_ws, fwd_ws_bytes, st);
+    int rc = forward_with_response<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 0,
+                                          misc, fwd_ws, fwd_ws_bytes, y_aux, st);
     if (rc) return rc;
     const int64_t n = (int64_t)arr->D * model->T;
     rc = launch_residual_loss(partial, y_work, y_ref, n, s->F, y_work, loss, st);
     if (rc) return rc;
-    rc = launch_adjoint<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 1.0f, p->mask, g,
-                               adj_ws, adj_ws_bytes, st);
+    rc = adjoint_with_response<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 1.0f,
+                                      p->mask, g, adj_ws, adj_ws_bytes, y_aux, st);
     if (rc) return rc;
     return launch_adam(s, p, step_dev, model->a_softplus, st);
 }
@@ -349,13 +407,19 @@ int sbp_simulate_signals(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *ba
         return rc;
     if (!y) return fail(SBP_E_ARG, "y is NULL");
     if (accumulate != 0 && accumulate != 1) return fail(SBP_E_ARG, "accumulate must be 0 or 1");
-    if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
+    if ((rc = check_model(model)) || (rc = check_response_rows(model, arr->D)) ||
+        (rc = check_ctx(ctx)))
+        return rc;
     if ((rc = set_device(ctx->c))) return rc;
-    const size_t wsb = forward_ws_bytes(F, arr->D, model->T, B_cap, sizeof(float));
-    if ((rc = ensure_scratch(&ctx->c, wsb))) return rc;
-    return launch_forward<float>(&ctx->c, arrp<float>(arr), ballsp<float>(balls), ball_off, F,
-                                 B_cap, model, y, accumulate, ctx->c.misc, ctx->c.scratch, wsb,
-                                 (hipStream_t)stream);
+    // scratch: [forward integer sums and ball constants][record before the response]
+    const size_t wsb = up256(forward_ws_bytes(F, arr->D, model->T, B_cap, sizeof(float)));
+    const size_t rb = response_ws_bytes(model, F, arr->D, sizeof(float));
+    if ((rc = ensure_scratch(&ctx->c, wsb + rb))) return rc;
+    return forward_with_response<float>(&ctx->c, arrp<float>(arr), ballsp<float>(balls), ball_off,
+                                        F, B_cap, model, y, accumulate, ctx->c.misc,
+                                        ctx->c.scratch, wsb,
+                                        (float *)((char *)ctx->c.scratch + wsb),
+                                        (hipStream_t)stream);
 }
 
 int sbp_simulate_signals_noalloc(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *balls,
@@ -368,21 +432,77 @@ int sbp_simulate_signals_noalloc(sbp_ctx *ctx, const sbp_array *arr, const sbp_b
         return rc;
     if (!y) return fail(SBP_E_ARG, "y is NULL");
     if (accumulate != 0 && accumulate != 1) return fail(SBP_E_ARG, "accumulate must be 0 or 1");
-    if ((rc = check_model(model))) return rc;
-    const size_t wsb = forward_ws_bytes(F, arr->D, model->T, B_cap, sizeof(float));
-    if (wsb > kFixedWsBytes - kMiscBytes)
+    if ((rc = check_model(model)) || (rc = check_response_rows(model, arr->D))) return rc;
+    const size_t wsb = up256(forward_ws_bytes(F, arr->D, model->T, B_cap, sizeof(float)));
+    const size_t rb = response_ws_bytes(model, F, arr->D, sizeof(float));
+    if (wsb + rb > kFixedWsBytes - kMiscBytes)
         return fail(SBP_E_CAPACITY,
                     "this call needs %zu bytes of workspace; the fixed workspace holds %zu "
-                    "(8 (T + 1) F D + 24 B_cap bytes, rounded, must fit)",
-                    wsb, kFixedWsBytes - kMiscBytes);
+                    "(8 (T + 1) F D + 24 B_cap bytes, plus 4 T F D with a response, rounded, "
+                    "must fit)",
+                    wsb + rb, kFixedWsBytes - kMiscBytes);
     if ((rc = check_ctx(ctx))) return rc;
     if (!ctx->c.fixed_ws) return fail(SBP_E_HIP, "the context has no fixed workspace address");
     if ((rc = set_device(ctx->c))) return rc;
     // [device words (bound, frame flags)][forward integer sums and ball constants]
+    // [record before the response]
     char *base = (char *)ctx->c.fixed_ws;
-    return launch_forward<float>(&ctx->c, arrp<float>(arr), ballsp<float>(balls), ball_off, F,
-                                 B_cap, model, y, accumulate, (unsigned *)base, base + kMiscBytes,
-                                 wsb, (hipStream_t)stream);
+    return forward_with_response<float>(&ctx->c, arrp<float>(arr), ballsp<float>(balls), ball_off,
+                                        F, B_cap, model, y, accumulate, (unsigned *)base,
+                                        base + kMiscBytes, wsb,
+                                        (float *)(base + kMiscBytes + wsb), (hipStream_t)stream);
+}
+
+int sbp_response_length(double fc, double bw, double dt_k, double n_sigma, int32_t *L,
+                        int32_t *zero) {
+    if (!L || !zero) return fail(SBP_E_ARG, "L or zero is NULL");
+    auto pos = [](double v) { return v > 0.0 && std::isfinite(v); };
+    if (!pos(fc) || !pos(bw) || !pos(dt_k) || !pos(n_sigma))
+        return fail(SBP_E_DOMAIN, "fc, bw, dt_k and n_sigma must be positive and finite");
+    const double s_f = bw * fc / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+    const double s_t = 1.0 / (2.0 * M_PI * s_f);
+    const double half = std::ceil(n_sigma * s_t / dt_k);
+    if (!(2.0 * half + 1.0 <= SBP_MAX_TAPS))
+        return fail(SBP_E_CAPACITY, "the response needs %.0f taps (at most %d)", 2.0 * half + 1.0,
+                    SBP_MAX_TAPS);
+    *zero = (int32_t)half;
+    *L = 2 * (int32_t)half + 1;
+    return SBP_OK;
+}
+
+int sbp_response_taps(sbp_ctx *ctx, const float *fc, const float *bw, int32_t rows, double dt_k,
+                      int32_t L, int32_t zero, float *h, void *stream) {
+    if (!fc || !bw || !h) return fail(SBP_E_ARG, "fc, bw or h is NULL");
+    if (rows < 1) return fail(SBP_E_ARG, "rows must be >= 1");
+    if (!(dt_k > 0.0) || !std::isfinite(dt_k)) return fail(SBP_E_DOMAIN, "dt_k must be > 0");
+    if (L < 1 || L > SBP_MAX_TAPS) return fail(SBP_E_DOMAIN, "L must be in [1, %d]", SBP_MAX_TAPS);
+    if (zero < 0 || zero >= L) return fail(SBP_E_DOMAIN, "zero must be in [0, L)");
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = set_device(ctx->c))) return rc;
+    return launch_response_taps(fc, bw, rows, dt_k, L, zero, h, (hipStream_t)stream);
+}
+
+int sbp_response_apply(sbp_ctx *ctx, const float *h, int32_t rows_h, int32_t L, int32_t zero,
+                       const float *y, int64_t R, int32_t D, int32_t T, int32_t adjoint,
+                       int32_t accumulate, float *out, void *stream) {
+    if (!h || !y || !out) return fail(SBP_E_ARG, "h, y or out is NULL");
+    if (R < 1 || D < 1) return fail(SBP_E_ARG, "R and D must be >= 1");
+    if (rows_h != 1 && rows_h != D) return fail(SBP_E_ARG, "rows_h must be 1 or D");
+    if (rows_h == D && R % D) return fail(SBP_E_ARG, "R must be a multiple of D");
+    if ((adjoint != 0 && adjoint != 1) || (accumulate != 0 && accumulate != 1))
+        return fail(SBP_E_ARG, "adjoint and accumulate must be 0 or 1");
+    if (T < 1) return fail(SBP_E_DOMAIN, "T must be >= 1");
+    if (L < 1 || L > SBP_MAX_TAPS) return fail(SBP_E_DOMAIN, "L must be in [1, %d]", SBP_MAX_TAPS);
+    if (zero < 0 || zero >= L) return fail(SBP_E_DOMAIN, "zero must be in [0, L)");
+    const uintptr_t y0 = (uintptr_t)y, o0 = (uintptr_t)out;
+    const uintptr_t nbytes = (uintptr_t)R * (uintptr_t)T * sizeof(float);
+    if (y0 < o0 + nbytes && o0 < y0 + nbytes) return fail(SBP_E_ARG, "out overlaps y");
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if ((rc = set_device(ctx->c))) return rc;
+    return launch_response<float>(h, rows_h, L, zero, y, R, D, T, adjoint, accumulate, out,
+                                  (hipStream_t)stream);
 }
 
 int sbp_simulate_signals_f64(sbp_ctx *ctx, const sbp_array_f64 *arr, const sbp_balls_f64 *balls,
@@ -394,11 +514,15 @@ int sbp_simulate_signals_f64(sbp_ctx *ctx, const sbp_array_f64 *arr, const sbp_b
         return rc;
     if (!y) return fail(SBP_E_ARG, "y is NULL");
     if (accumulate != 0 && accumulate != 1) return fail(SBP_E_ARG, "accumulate must be 0 or 1");
-    if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
+    if ((rc = check_model(model)) || (rc = check_response_rows(model, arr->D)) ||
+        (rc = check_ctx(ctx)))
+        return rc;
     if ((rc = set_device(ctx->c))) return rc;
-    return launch_forward<double>(&ctx->c, arrp<double>(arr), ballsp<double>(balls), ball_off, F,
-                                  B_cap, model, y, accumulate, ctx->c.misc, nullptr, 0,
-                                  (hipStream_t)stream);
+    const size_t rb = response_ws_bytes(model, F, arr->D, sizeof(double));
+    if ((rc = ensure_scratch(&ctx->c, rb))) return rc;
+    return forward_with_response<double>(&ctx->c, arrp<double>(arr), ballsp<double>(balls),
+                                         ball_off, F, B_cap, model, y, accumulate, ctx->c.misc,
+                                         nullptr, 0, (double *)ctx->c.scratch, (hipStream_t)stream);
 }
 
 int sbp_residual_loss(sbp_ctx *ctx, const float *y_sim, const float *y_ref, int64_t n_per_frame,
@@ -423,13 +547,19 @@ int sbp_adjoint_gradients(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *b
         (rc = check_balls(balls, "balls", B_cap)) || (rc = check_grad(grad, mask, B_cap)))
         return rc;
     if (!v) return fail(SBP_E_ARG, "v is NULL");
-    if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
+    if ((rc = check_model(model)) || (rc = check_response_rows(model, arr->D)) ||
+        (rc = check_ctx(ctx)))
+        return rc;
     if ((rc = set_device(ctx->c))) return rc;
-    const size_t wsb = adjoint_ws_bytes(&ctx->c, arr->D, B_cap, F, mask, sizeof(float));
-    if ((rc = ensure_scratch(&ctx->c, wsb))) return rc;
-    return launch_adjoint<float>(&ctx->c, arrp<float>(arr), ballsp<float>(balls), ball_off, F,
-                                 B_cap, model, v, 1.0f, mask, ballsp<float>(grad), ctx->c.scratch,
-                                 wsb, (hipStream_t)stream);
+    // scratch: [adjoint slices][cotangent before the response]
+    const size_t wsb = up256(adjoint_ws_bytes(&ctx->c, arr->D, B_cap, F, mask, sizeof(float)));
+    const size_t rb = response_ws_bytes(model, F, arr->D, sizeof(float));
+    if ((rc = ensure_scratch(&ctx->c, wsb + rb))) return rc;
+    return adjoint_with_response<float>(&ctx->c, arrp<float>(arr), ballsp<float>(balls), ball_off,
+                                        F, B_cap, model, v, 1.0f, mask, ballsp<float>(grad),
+                                        ctx->c.scratch, wsb,
+                                        (float *)((char *)ctx->c.scratch + wsb),
+                                        (hipStream_t)stream);
 }
 
 int sbp_adjoint_gradients_f64(sbp_ctx *ctx, const sbp_array_f64 *arr, const sbp_balls_f64 *balls,
@@ -441,13 +571,18 @@ int sbp_adjoint_gradients_f64(sbp_ctx *ctx, const sbp_array_f64 *arr, const sbp_
         (rc = check_balls(balls, "balls", B_cap)) || (rc = check_grad(grad, mask, B_cap)))
         return rc;
     if (!v) return fail(SBP_E_ARG, "v is NULL");
-    if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
+    if ((rc = check_model(model)) || (rc = check_response_rows(model, arr->D)) ||
+        (rc = check_ctx(ctx)))
+        return rc;
     if ((rc = set_device(ctx->c))) return rc;
-    const size_t wsb = adjoint_ws_bytes(&ctx->c, arr->D, B_cap, F, mask, sizeof(double));
-    if ((rc = ensure_scratch(&ctx->c, wsb))) return rc;
-    return launch_adjoint<double>(&ctx->c, arrp<double>(arr), ballsp<double>(balls), ball_off, F,
-                                  B_cap, model, v, 1.0, mask, ballsp<double>(grad), ctx->c.scratch,
-                                  wsb, (hipStream_t)stream);
+    const size_t wsb = up256(adjoint_ws_bytes(&ctx->c, arr->D, B_cap, F, mask, sizeof(double)));
+    const size_t rb = response_ws_bytes(model, F, arr->D, sizeof(double));
+    if ((rc = ensure_scratch(&ctx->c, wsb + rb))) return rc;
+    return adjoint_with_response<double>(&ctx->c, arrp<double>(arr), ballsp<double>(balls),
+                                         ball_off, F, B_cap, model, v, 1.0, mask,
+                                         ballsp<double>(grad), ctx->c.scratch, wsb,
+                                         (double *)((char *)ctx->c.scratch + wsb),
+                                         (hipStream_t)stream);
 }
 
 int sbp_filter_zero_grad(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *in,
@@ -467,16 +602,18 @@ int sbp_filter_zero_grad(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *in
             (rc = check_balls(m_out, "m_out", B_cap)) || (rc = check_balls(v_out, "v_out", B_cap)))
             return rc;
     }
-    if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
+    if ((rc = check_model(model)) || (rc = check_response_rows(model, arr->D)) ||
+        (rc = check_ctx(ctx)))
+        return rc;
     if ((rc = set_device(ctx->c))) return rc;
     // scratch: [filter gradient (if g_out is NULL)][compaction workspace][adjoint slices]
-    //          [visiting order]
-    const size_t g_bytes = g_out ? 0 : (((size_t)B_cap * sizeof(float) + 255) & ~(size_t)255);
-    const size_t c_bytes = (compact_ws_bytes(B_cap) + 255) & ~(size_t)255;
-    const size_t a_bytes =
-        (adjoint_ws_bytes(&ctx->c, arr->D, B_cap, F, SBP_P0, sizeof(float)) + 255) & ~(size_t)255;
-    const size_t o_bytes = order_ws_bytes(F, B_cap);
-    if ((rc = ensure_scratch(&ctx->c, g_bytes + c_bytes + a_bytes + o_bytes))) return rc;
+    //          [visiting order][reference correlated with the response]
+    const size_t g_bytes = g_out ? 0 : up256((size_t)B_cap * sizeof(float));
+    const size_t c_bytes = up256(compact_ws_bytes(B_cap));
+    const size_t a_bytes = up256(adjoint_ws_bytes(&ctx->c, arr->D, B_cap, F, SBP_P0, sizeof(float)));
+    const size_t o_bytes = up256(order_ws_bytes(F, B_cap));
+    const size_t r_bytes = response_ws_bytes(model, F, arr->D, sizeof(float));
+    if ((rc = ensure_scratch(&ctx->c, g_bytes + c_bytes + a_bytes + o_bytes + r_bytes))) return rc;
     float *g = g_out ? g_out : (float *)ctx->c.scratch;
     void *ws = (char *)ctx->c.scratch + g_bytes;
     hipStream_t st = (hipStream_t)stream;
@@ -488,8 +625,10 @@ int sbp_filter_zero_grad(sbp_ctx *ctx, const sbp_array *arr, const sbp_balls *in
                            &order, st)))
         return rc;
     BallsP<float> gp{nullptr, nullptr, nullptr, g, nullptr};
-    rc = launch_adjoint<float>(&ctx->c, arrp<float>(arr), ballsp<float>(in), off_in, F, B_cap, model,
-                               y_ref, -2.0f, SBP_P0, gp, (char *)ws + c_bytes, a_bytes, st, order);
+    rc = adjoint_with_response<float>(&ctx->c, arrp<float>(arr), ballsp<float>(in), off_in, F, B_cap,
+                                      model, y_ref, -2.0f, SBP_P0, gp, (char *)ws + c_bytes,
+                                      a_bytes, (float *)((char *)ws + c_bytes + a_bytes + o_bytes),
+                                      st, order);
     if (rc) return rc;
     BallsP<float> mi, vi, mo, vo;
     if (any_mom) {
@@ -521,17 +660,21 @@ int sbp_step(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state, const sbp_mod
         (rc = check_state(state, p->mask, true)))
         return rc;
     if (!y_ref || !y_work || !loss) return fail(SBP_E_ARG, "y_ref, y_work or loss is NULL");
-    if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
+    if ((rc = check_model(model)) || (rc = check_response_rows(model, arr->D)) ||
+        (rc = check_ctx(ctx)))
+        return rc;
     if ((rc = set_device(ctx->c))) return rc;
-    // scratch: [residual partial sums][forward integer sums][adjoint slices]
-    const size_t r_bytes = (residual_ws_bytes(state->F) + 255) & ~(size_t)255;
-    const size_t f_bytes = forward_ws_bytes(state->F, arr->D, model->T, state->B_cap, sizeof(float));
-    const size_t a_bytes = adjoint_ws_bytes(&ctx->c, arr->D, state->B_cap, state->F, p->mask, sizeof(float));
-    if ((rc = ensure_scratch(&ctx->c, r_bytes + f_bytes + a_bytes))) return rc;
+    // scratch: [residual partial sums][forward integer sums][adjoint slices][record before
+    //          the response]
+    const size_t r_bytes = up256(residual_ws_bytes(state->F));
+    const size_t f_bytes = up256(forward_ws_bytes(state->F, arr->D, model->T, state->B_cap, sizeof(float)));
+    const size_t a_bytes = up256(adjoint_ws_bytes(&ctx->c, arr->D, state->B_cap, state->F, p->mask, sizeof(float)));
+    const size_t x_bytes = response_ws_bytes(model, state->F, arr->D, sizeof(float));
+    if ((rc = ensure_scratch(&ctx->c, r_bytes + f_bytes + a_bytes + x_bytes))) return rc;
     char *sc = (char *)ctx->c.scratch;
     return step_body(&ctx->c, arr, state, model, y_ref, y_work, p, nullptr, loss, (double *)sc,
                      ctx->c.misc, sc + r_bytes, f_bytes, sc + r_bytes + f_bytes, a_bytes,
-                     (hipStream_t)stream);
+                     (float *)(sc + r_bytes + f_bytes + a_bytes), (hipStream_t)stream);
 }
 
 int sbp_step_graph_create(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state,
@@ -547,16 +690,20 @@ int sbp_step_graph_create(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state,
     if (!y_ref || !y_work || !loss || !step_dev) return fail(SBP_E_ARG, "y_ref, y_work, loss or step_dev is NULL");
     if (iters < 1) return fail(SBP_E_ARG, "iters must be >= 1");
     if (!stream) return fail(SBP_E_ARG, "graph capture needs a non-null stream");
-    if ((rc = check_model(model)) || (rc = check_ctx(ctx))) return rc;
+    if ((rc = check_model(model)) || (rc = check_response_rows(model, arr->D)) ||
+        (rc = check_ctx(ctx)))
+        return rc;
     if ((rc = set_device(ctx->c))) return rc;
     hipStream_t st = (hipStream_t)stream;
     sbp_graph *g = new sbp_graph();
     g->device = ctx->c.device;
     // graph workspace: [residual partial sums][device words][forward integer sums][adjoint slices]
-    const size_t ws_res = (residual_ws_bytes(state->F) + 255) & ~(size_t)255;
-    const size_t ws_fwd = forward_ws_bytes(state->F, arr->D, model->T, state->B_cap, sizeof(float));
-    const size_t ws_adj = adjoint_ws_bytes(&ctx->c, arr->D, state->B_cap, state->F, p->mask, sizeof(float));
-    if (hipMalloc(&g->ws, ws_res + kMiscBytes + ws_fwd + ws_adj) != hipSuccess) {
+    //                  [record before the response]
+    const size_t ws_res = up256(residual_ws_bytes(state->F));
+    const size_t ws_fwd = up256(forward_ws_bytes(state->F, arr->D, model->T, state->B_cap, sizeof(float)));
+    const size_t ws_adj = up256(adjoint_ws_bytes(&ctx->c, arr->D, state->B_cap, state->F, p->mask, sizeof(float)));
+    const size_t ws_aux = response_ws_bytes(model, state->F, arr->D, sizeof(float));
+    if (hipMalloc(&g->ws, ws_res + kMiscBytes + ws_fwd + ws_adj + ws_aux) != hipSuccess) {
         delete g;
         (void)hipGetLastError();
         return fail(SBP_E_NOMEM, "could not allocate the graph workspace");
@@ -572,7 +719,8 @@ int sbp_step_graph_create(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state,
         body = step_body(&ctx->c, arr, state, model, y_ref, y_work, p, step_dev,
                          loss + (int64_t)it * state->F, (double *)g->ws,
                          (unsigned *)((char *)g->ws + ws_res), (char *)g->ws + ws_res + kMiscBytes,
-                         ws_fwd, (char *)g->ws + ws_res + kMiscBytes + ws_fwd, ws_adj, st);
+                         ws_fwd, (char *)g->ws + ws_res + kMiscBytes + ws_fwd, ws_adj,
+                         (float *)((char *)g->ws + ws_res + kMiscBytes + ws_fwd + ws_adj), st);
         if (body == SBP_OK) body = launch_incr(step_dev, st);
     }
     e = hipStreamEndCapture(st, &g->graph);

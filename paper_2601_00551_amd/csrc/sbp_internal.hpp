@@ -302,6 +302,15 @@ int launch_reparam(float *a, float *m, float *v, const int64_t *ball_off, int F,
 int launch_grow(Ctx *c, const sbp_state *in, const sbp_growth_rule *rule, sbp_state *out,
                 int64_t *count, hipStream_t st);
 
+// Transducer response (response.hip): rows records of T samples, record r
+// using tap row (rows_h == 1 ? 0 : r mod D); adjoint = 0 convolves, 1
+// correlates.  out must not overlap y.
+template <typename R>
+int launch_response(const float *h, int rows_h, int L, int zero, const R *y, int64_t rows, int D,
+                    int T, int adjoint, int accumulate, R *out, hipStream_t st);
+int launch_response_taps(const float *fc, const float *bw, int rows, double dt, int L, int zero,
+                         float *h, hipStream_t st);
+
 }  // namespace sbp
 
 // The opaque context of the C-ABI.

@@ -219,6 +219,16 @@ def drop_near(balls, array, min_dist):
     return {k: v[keep] for k, v in balls.items()}
 
 
+def element_responses(n, rng, fc=2.02, bw=0.54, fc_spread=0.03, bw_spread=0.05):
+    """Centre frequency (MHz) and fractional bandwidth of n transducer elements:
+    the in vivo array's means (2.02 MHz, 54 %, section 2.2) with a seeded
+    element-to-element spread (relative, normal; the paper reports only the
+    means)."""
+    f = fc * (1.0 + fc_spread * rng.standard_normal(n))
+    b = bw * (1.0 + bw_spread * rng.standard_normal(n))
+    return f.astype(F32), b.astype(F32)
+
+
 def add_noise(y, rng, frac=0.05):
     """y + N(0, (frac * max|y|)^2), seeded."""
     y = np.asarray(y)

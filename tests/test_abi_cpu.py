@@ -246,3 +246,107 @@ def test_image_entry_points_validate_on_the_host():
     balls = _abi.SbpBalls(d, d, d, d, d)
     assert lib.sbp_voxelize(None, ctypes.byref(balls), d, 10, ctypes.byref(model), ctypes.byref(grid), d,
                             None) == _abi.SBP_E_DOMAIN
+
+
+# ------------------------------------------------------- transducer response --
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(response=FAKE.value, response_taps=0), _abi.SBP_E_DOMAIN),
+    (dict(response=FAKE.value, response_taps=4096), _abi.SBP_E_DOMAIN),
+    (dict(response=FAKE.value, response_taps=31, response_zero=-1), _abi.SBP_E_DOMAIN),
+    (dict(response=FAKE.value, response_taps=31, response_zero=31), _abi.SBP_E_DOMAIN),
+    (dict(response=FAKE.value, response_taps=31, response_zero=15, response_rows=3), _abi.SBP_E_ARG),
+    (dict(reserved=1), _abi.SBP_E_ARG),
+])
+def test_model_response_fields_are_validated(kw, code):
+    """The response fields of the model are checked on the host (rows against
+    the array's D = 4) by every call that takes a model."""
+    assert _sim(model=_model(**kw)) == code
+    assert "response" in last() or "reserved" in last(), last()
+    lib = _abi.lib()
+    g = _balls()
+    assert lib.sbp_adjoint_gradients(None, ctypes.byref(_array()), ctypes.byref(_balls()), FAKE, 1, 10,
+                                     ctypes.byref(_model(**kw)), FAKE, _abi.ALL, ctypes.byref(g),
+                                     None) == code
+
+
+def test_model_with_a_valid_response_reaches_the_context_check():
+    for rows in (1, 4):
+        m = _model(response=FAKE.value, response_taps=31, response_zero=15, response_rows=rows)
+        assert _sim(model=m) == _abi.SBP_E_ARG
+        assert "ctx" in last()
+    # with no taps pointer the other fields are ignored
+    assert _sim(model=_model(response_taps=-3, response_rows=7)) == _abi.SBP_E_ARG
+    assert "ctx" in last()
+
+
+def test_noalloc_counts_the_response_record():
+    fn = "sbp_simulate_signals_noalloc"
+    resp = dict(response=FAKE.value, response_taps=31, response_zero=15, response_rows=1)
+    # 1024 x 8000 samples and 2M balls fit without a response (113.5 MB) ...
+    assert _sim(fn=fn, arr=_array(D=1024), model=_model(T=8000), cap=2_000_000) == _abi.SBP_E_ARG
+    # ... but not with the 32.8 MB record before it
+    assert _sim(fn=fn, arr=_array(D=1024), model=_model(T=8000, **resp), cap=2_000_000) == \
+        _abi.SBP_E_CAPACITY
+
+
+def test_response_length_matches_the_oracle():
+    from oracle import response as oresp
+    L, zero = _abi.I32(), _abi.I32()
+    for fc, bw, dt, ns in [(2.02, 0.54, 0.025, 5.0), (2.02, 0.54, 0.1, 5.0), (1.9, 0.5, 0.05, 4.0),
+                           (2.3, 0.6, 0.0125, 6.0)]:
+        assert _abi.lib().sbp_response_length(fc, bw, dt, ns, ctypes.byref(L), ctypes.byref(zero)) == 0
+        assert (L.value, zero.value) == oresp.taps_length(fc, bw, dt, ns)
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0.0, 0.54, 0.025, 5.0), _abi.SBP_E_DOMAIN),
+    ((2.02, -0.5, 0.025, 5.0), _abi.SBP_E_DOMAIN),
+    ((2.02, 0.54, float("inf"), 5.0), _abi.SBP_E_DOMAIN),
+    ((2.02, 0.54, 0.025, 0.0), _abi.SBP_E_DOMAIN),
+    ((2.02, 0.54, 1e-5, 5.0), _abi.SBP_E_CAPACITY),
+])
+def test_response_length_validation(args, code):
+    L, zero = _abi.I32(), _abi.I32()
+    assert _abi.lib().sbp_response_length(*args, ctypes.byref(L), ctypes.byref(zero)) == code
+    assert last()
+
+
+@pytest.mark.parametrize("args,code", [
+    (dict(fc=None), _abi.SBP_E_ARG),
+    (dict(rows=0), _abi.SBP_E_ARG),
+    (dict(dt=0.0), _abi.SBP_E_DOMAIN),
+    (dict(L=0), _abi.SBP_E_DOMAIN),
+    (dict(L=4096), _abi.SBP_E_DOMAIN),
+    (dict(zero=31), _abi.SBP_E_DOMAIN),
+    (dict(), _abi.SBP_E_ARG),         # valid but the NULL context
+])
+def test_response_taps_validation(args, code):
+    a = dict(fc=FAKE, bw=FAKE, rows=4, dt=0.025, L=31, zero=15, h=FAKE)
+    a.update(args)
+    assert _abi.lib().sbp_response_taps(None, a["fc"], a["bw"], a["rows"], a["dt"], a["L"], a["zero"],
+                                        a["h"], None) == code
+    assert last()
+
+
+@pytest.mark.parametrize("args,code", [
+    (dict(h=None), _abi.SBP_E_ARG),
+    (dict(R=0), _abi.SBP_E_ARG),
+    (dict(rows_h=3), _abi.SBP_E_ARG),
+    (dict(rows_h=4, R=6), _abi.SBP_E_ARG),
+    (dict(adjoint=2), _abi.SBP_E_ARG),
+    (dict(accumulate=-1), _abi.SBP_E_ARG),
+    (dict(out=ctypes.c_void_p(0x1000 + 4 * 100)), _abi.SBP_E_ARG),    # overlaps y
+    (dict(T=0), _abi.SBP_E_DOMAIN),
+    (dict(L=0), _abi.SBP_E_DOMAIN),
+    (dict(zero=-1), _abi.SBP_E_DOMAIN),
+    (dict(out=ctypes.c_void_p(0x1000 + 4 * 8 * 64)), _abi.SBP_E_ARG),  # adjacent: the NULL context
+])
+def test_response_apply_validation(args, code):
+    a = dict(h=FAKE, rows_h=1, L=31, zero=15, y=FAKE, R=8, D=4, T=64, adjoint=0, accumulate=0,
+             out=ctypes.c_void_p(0x100000))
+    a.update(args)
+    rc = _abi.lib().sbp_response_apply(None, a["h"], a["rows_h"], a["L"], a["zero"], a["y"], a["R"],
+                                       a["D"], a["T"], a["adjoint"], a["accumulate"], a["out"], None)
+    assert rc == code
+    assert last()
