@@ -307,11 +307,15 @@ def suite(args):
     wl = synth.tiny_config()
     A, y = measured(wl, noise=0.0)
     model = api.Model(c=c, dt=wl.dt, T=wl.T, f=1)
+    tuned = autotune.apply_cached(ctx, args.tuning, model, len(wl.array["qx"]), len(wl.init["x"]))
     st = api.State(wl.init, device=dev)
     te, tg = iteration_rates(A, st, model, y, iters=10, reps=20)
     print(json.dumps({"workload": wl.name, "balls": len(wl.init["x"]), "transducers": len(wl.array["qx"]),
                       "us_per_iteration_eager": te * 1e3, "us_per_iteration_graph": tg * 1e3,
-                      "graph_speedup": te / tg}), flush=True)
+                      "graph_speedup": te / tg, "tuning": tuned}), flush=True)
+    if args.tiny:
+        ctx.close()
+        return
 
     # conformal: per level, filter then forward + adjoint on the kept balls
     wl = synth.conformal_config()
@@ -495,12 +499,14 @@ def main():
                     help="skip the learned-vs-plain reconstruction timing")
     ap.add_argument("--response-steps", type=int, default=3,
                     help="steps timed again with a transducer response per element (0 = skip)")
+    ap.add_argument("--tiny", action="store_true",
+                    help="only the tiny workload's per-iteration latency (eager vs graph)")
     ap.add_argument("--suite", action="store_true",
                     help="measure the other workloads instead (one JSON line each)")
     ap.add_argument("--rates", action="store_true",
                     help="only run the issue-rate microbenchmark (VALU, transcendental, LDS)")
     args = ap.parse_args()
-    if args.suite:
+    if args.suite or args.tiny:
         suite(args)
         return
     if args.rates:

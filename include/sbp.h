@@ -356,10 +356,10 @@ int sbp_step(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state, const sbp_mod
              const float *y_ref, float *y_work, const sbp_adam_params *p, double *loss,
              void *stream);
 
-/* Capture `iters` consecutive sbp_step iterations into one HIP graph.  The
- * step count starts at *step_dev (device int32) and is incremented on the
- * device after each iteration, so successive launches continue the Adam
- * schedule.  loss receives iters * F doubles (iteration-major).  The ball
+/* Capture `iters` consecutive sbp_step iterations into one HIP graph.
+ * Iteration i of a launch uses the step count *step_dev + i (device int32),
+ * and the launch ends by adding iters to *step_dev, so successive launches
+ * continue the Adam schedule.  loss receives iters * F doubles (iteration-major).  The ball
  * counts in state->ball_off may change between launches (up to B_cap).  The
  * graph keeps the pointers it was created with.
  * Errors: as sbp_step, plus SBP_E_HIP on capture failure. */

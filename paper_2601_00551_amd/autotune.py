@@ -17,7 +17,7 @@ import os
 
 FWD_SPACE = {"fwd_dets": (1, 2, 4, 8), "fwd_block": (256, 512), "fwd_bpt": (1, 2, 4),
              "fwd_tile": (0, 2048, 1024)}
-ADJ_SPACE = {"adj_dets": (2, 4, 8), "adj_block": (128, 256, 512), "adj_bpt": (1, 2, 3),
+ADJ_SPACE = {"adj_dets": (1, 2, 4, 8), "adj_block": (128, 256, 512), "adj_bpt": (1, 2, 3),
              "adj_tile": (0, 2048)}
 # The launch-shape cache shipped with the package (tuned on an MI355X).
 DEFAULT_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
@@ -98,9 +98,31 @@ def _time(fn, reps: int) -> float:
     return e0.elapsed_time(e1) / reps
 
 
-def tune(ctx, arr, balls, model, v, reps: int = 3, path: str | None = None, log=print) -> dict:
+def _step_timer(ctx, arr, balls, model, y_ref, reps: int, iters: int = 10):
+    """Time per iteration of a captured reconstruction step (for clouds small
+    enough that a single call's time is the host's, not the kernels')."""
+    import torch
+    from . import api
+    B = balls["x"].numel()
+    yw = torch.empty_like(y_ref)
+    cur = torch.cuda.current_stream()
+
+    def timed():
+        st = api.State({k: balls[k] for k in api.PARAMS}, capacity=B, device=y_ref.device)
+        g = api.StepGraph(ctx, arr, st, model, y_ref, yw, api.AdamParams(step=1), iters=iters, step0=1)
+        try:
+            return _time(lambda: g.launch(stream=cur), reps) / iters
+        finally:
+            g.close()
+    return timed
+
+
+def tune(ctx, arr, balls, model, v, reps: int = 3, path: str | None = None, log=print,
+         by_step: bool = False) -> dict:
     """Sweep FWD_SPACE and ADJ_SPACE on (arr, balls, model) with cotangent v;
-    store the winners under the workload's key in `path` and install them."""
+    store the winners under the workload's key in `path` and install them.
+    by_step: rank each shape by the captured step's time per iteration (v is
+    then the reference record) instead of the call's own time."""
     from . import api
     D = arr["qx"].numel()
     B = balls["x"].numel()
@@ -109,6 +131,7 @@ def tune(ctx, arr, balls, model, v, reps: int = 3, path: str | None = None, log=
     base = ctx.tuning
     results = {}
     best_f, best_a = None, None
+    step = _step_timer(ctx, arr, balls, model, v, reps) if by_step else None
     for vals in itertools.product(*FWD_SPACE.values()):
         t = dict(zip(FWD_SPACE, vals))
         if t["fwd_tile"] and t["fwd_tile"] >= model.T:
@@ -116,21 +139,21 @@ def tune(ctx, arr, balls, model, v, reps: int = 3, path: str | None = None, log=
         rows = min(model.T, t["fwd_tile"] or model.T)
         if t["fwd_dets"] * rows * 8 > 150 * 1024 and t["fwd_dets"] > 1:   # int64 rows
             continue
-        ctx.tuning = t
-        ms = _time(lambda: api.simulate_signals(ctx, arr, balls, model, y=y), reps)
+        ctx.tuning = dict(base, **t)
+        ms = step() if step else _time(lambda: api.simulate_signals(ctx, arr, balls, model, y=y), reps)
         results[json.dumps(t)] = ms
         log(f"forward {t}: {ms:.3f} ms")
         if best_f is None or ms < best_f[1]:
             best_f = (t, ms)
-    ctx.tuning = best_f[0]
+    ctx.tuning = dict(base, **best_f[0])
     for vals in itertools.product(*ADJ_SPACE.values()):
         t = dict(zip(ADJ_SPACE, vals))
         if t["adj_tile"] and t["adj_tile"] >= model.T + 1:
             continue
         if t["adj_dets"] * min(model.T + 1, t["adj_tile"] or model.T + 1) * 4 > 150 * 1024:
             continue
-        ctx.tuning = t
-        ms = _time(lambda: api.adjoint_gradients(ctx, arr, balls, model, v, grad=grad), reps)
+        ctx.tuning = dict(base, **best_f[0], **t)
+        ms = step() if step else _time(lambda: api.adjoint_gradients(ctx, arr, balls, model, v, grad=grad), reps)
         results[json.dumps(t)] = ms
         log(f"adjoint {t}: {ms:.3f} ms")
         if best_a is None or ms < best_a[1]:
@@ -155,7 +178,7 @@ def main(argv=None):
     import torch
     from . import api, synth
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=("large", "conformal"), default="large")
+    ap.add_argument("--workload", choices=("large", "conformal", "tiny"), default="large")
     ap.add_argument("--balls", type=int, default=2_000_000)
     ap.add_argument("--out", default=DEFAULT_PATH)
     ap.add_argument("--reps", type=int, default=3)
@@ -170,6 +193,9 @@ def main(argv=None):
     ctx = api.Context(0)
     if args.workload == "large":
         wl = synth.large_config(n_balls=args.balls)
+        balls = wl.init
+    elif args.workload == "tiny":
+        wl = synth.tiny_config()
         balls = wl.init
     else:
         wl = synth.conformal_config()
@@ -187,7 +213,11 @@ def main(argv=None):
                           directivity=api.DIR_COS,
                           sampling=api.SAMPLING_POINT if args.sampling == "point" else api.SAMPLING_BIN)
         v = torch.as_tensor(rng.normal(size=(1, len(wl.array["qx"]), model.T)).astype(np.float32), device=dev)
-        res = tune(ctx, A, Bt, model, v, reps=args.reps, path=args.out, log=lambda s: print(s, flush=True))
+        if args.workload == "tiny":     # rank by the captured step: one call is host-bound
+            v = api.simulate_signals(ctx, A, {k: torch.as_tensor(x, device=dev) for k, x in wl.gt.items()},
+                                     model)
+        res = tune(ctx, A, Bt, model, v, reps=args.reps, path=args.out, log=lambda s: print(s, flush=True),
+                   by_step=args.workload == "tiny")
         print(json.dumps({"workload": wl.name, "f": f, "chosen": res["chosen"],
                           "forward_ms": res["forward_ms"], "adjoint_ms": res["adjoint_ms"]}), flush=True)
     ctx.close()

@@ -275,29 +275,23 @@ __global__ __launch_bounds__(512, (AdjMinBlocks<R, PROF, DIR, FULL>::v)) void k_
     }
 }
 
-// Sums the transducer slices of the partial gradients, slice 0 first.
+// Sums the transducer slices of the partial gradients, slice 0 first;
+// blockIdx.y is the parameter (the p0-only variant has one).
 template <typename R, bool FULL>
 __global__ void k_adj_reduce(const R *__restrict__ part, int nsl, int64_t pstride,
                              const int64_t *__restrict__ ball_off, int F, uint32_t mask,
                              int a_softplus, const R *__restrict__ a_arr, BallsP<R> grad) {
+    const int k = FULL ? (int)blockIdx.y : 3;
+    if (!(mask & (1u << k))) return;
+    const int nf = FULL ? 5 : 1;
+    R *out = k == 0 ? grad.x : k == 1 ? grad.y : k == 2 ? grad.z : k == 3 ? grad.p0 : grad.a;
+    const R *pk = part + (int64_t)(FULL ? k : 0) * pstride;
     const int64_t lo = ball_off[0], hi = ball_off[F];
-    R *out[5] = {grad.x, grad.y, grad.z, grad.p0, grad.a};
     for (int64_t i = lo + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hi;
          i += (int64_t)gridDim.x * blockDim.x) {
-        if (FULL) {
-#pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                if (!(mask & (1u << k))) continue;
-                R s = R(0);
-                for (int sl = 0; sl < nsl; ++sl) s += part[((int64_t)sl * 5 + k) * pstride + i];
-                if (k == 4 && a_softplus) s *= sigmoid_dev(a_arr[i]);
-                out[k][i] = s;
-            }
-        } else {
-            R s = R(0);
-            for (int sl = 0; sl < nsl; ++sl) s += part[(int64_t)sl * pstride + i];
-            grad.p0[i] = s;
-        }
+        R s = slice_sum(pk + i, nsl, (int64_t)nf * pstride);
+        if (k == 4 && a_softplus) s *= sigmoid_dev(a_arr[i]);
+        out[i] = s;
     }
 }
 
@@ -347,7 +341,7 @@ template <typename R, int PROF, int DIR, bool FULL>
 static int run_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
                        const int64_t *ball_off, int F, int64_t B_cap, const Level &lc, const R *v,
                        R vscale, uint32_t mask, const BallsP<R> &grad, void *ws, size_t ws_bytes,
-                       hipStream_t st, const int32_t *order) {
+                       hipStream_t st, const int32_t *order, AdjDeferred *defer) {
     auto kern = k_adjoint<R, PROF, DIR, FULL>;
     const size_t reserve = 2 * (SBP_MAX_FRAMES + 1) * sizeof(int64_t) + 256;
     const size_t avail = c->lds_max > reserve ? c->lds_max - reserve : 0;
@@ -385,10 +379,22 @@ static int run_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
                        (int)TT, pl.bpt, pl.nsl, pl.dsl, lc, v, vscale, mask, grad, part, B_cap,
                        order);
     SBP_HIP(hipGetLastError());
+    if (defer) {
+        *defer = AdjDeferred{};
+        if constexpr (FULL && sizeof(R) == sizeof(float)) {
+            if (part) {
+                defer->part = (const float *)part;
+                defer->nsl = pl.nsl;
+                defer->pstride = B_cap;
+                return SBP_OK;
+            }
+        }
+    }
     if (part) {
         int64_t nb = (B_cap + 255) / 256;
         if (nb > 2048) nb = 2048;
-        hipLaunchKernelGGL((k_adj_reduce<R, FULL>), dim3((int)nb), dim3(256), 0, st, (const R *)part,
+        hipLaunchKernelGGL((k_adj_reduce<R, FULL>), dim3((int)nb, FULL ? 5 : 1), dim3(256), 0, st,
+                           (const R *)part,
                            pl.nsl, B_cap, ball_off, F, mask, lc.a_softplus, (const R *)balls.a, grad);
         SBP_HIP(hipGetLastError());
     }
@@ -399,49 +405,51 @@ template <typename R, bool FULL>
 static int dispatch_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
                             const int64_t *ball_off, int F, int64_t B_cap, const sbp_model *m,
                             const R *v, R vscale, uint32_t mask, const BallsP<R> &grad, void *ws,
-                            size_t ws_bytes, hipStream_t st, const int32_t *order) {
+                            size_t ws_bytes, hipStream_t st, const int32_t *order,
+                            AdjDeferred *defer) {
     const Level lc = make_level(m);
     if (profile_code(m) == GPOINT) {
         if (m->directivity == SBP_DIR_COS)
             return run_adjoint<R, GPOINT, COS, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v,
-                                                     vscale, mask, grad, ws, ws_bytes, st, order);
+                                                     vscale, mask, grad, ws, ws_bytes, st, order, defer);
         return run_adjoint<R, GPOINT, OMNI, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v, vscale,
-                                                  mask, grad, ws, ws_bytes, st, order);
+                                                  mask, grad, ws, ws_bytes, st, order, defer);
     }
     if (m->profile == SBP_PROFILE_GAUSS) {
         if (m->directivity == SBP_DIR_COS)
             return run_adjoint<R, GAUSS, COS, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v,
-                                                    vscale, mask, grad, ws, ws_bytes, st, order);
+                                                    vscale, mask, grad, ws, ws_bytes, st, order, defer);
         return run_adjoint<R, GAUSS, OMNI, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v, vscale,
-                                                 mask, grad, ws, ws_bytes, st, order);
+                                                 mask, grad, ws, ws_bytes, st, order, defer);
     }
     if (m->directivity == SBP_DIR_COS)
         return run_adjoint<R, UNIFORM, COS, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v, vscale,
-                                                  mask, grad, ws, ws_bytes, st, order);
+                                                  mask, grad, ws, ws_bytes, st, order, defer);
     return run_adjoint<R, UNIFORM, OMNI, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v, vscale,
-                                               mask, grad, ws, ws_bytes, st, order);
+                                               mask, grad, ws, ws_bytes, st, order, defer);
 }
 
 template <typename R>
 int launch_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
                    int F, int64_t B_cap, const sbp_model *m, const R *v, R vscale,
                    uint32_t mask, const BallsP<R> &grad, void *ws, size_t ws_bytes, hipStream_t st,
-                   const int32_t *order) {
+                   const int32_t *order, AdjDeferred *defer) {
+    if (defer) *defer = AdjDeferred{};
     if (B_cap == 0) return SBP_OK;
     if ((mask & ~SBP_P0) == 0)
         return dispatch_adjoint<R, false>(c, arr, balls, ball_off, F, B_cap, m, v, vscale, mask,
-                                          grad, ws, ws_bytes, st, order);
+                                          grad, ws, ws_bytes, st, order, defer);
     return dispatch_adjoint<R, true>(c, arr, balls, ball_off, F, B_cap, m, v, vscale, mask, grad,
-                                     ws, ws_bytes, st, order);
+                                     ws, ws_bytes, st, order, defer);
 }
 
 template int launch_adjoint<float>(Ctx *, const ArrayP<float> &, const BallsP<float> &,
                                    const int64_t *, int, int64_t, const sbp_model *, const float *,
                                    float, uint32_t, const BallsP<float> &, void *, size_t,
-                                   hipStream_t, const int32_t *);
+                                   hipStream_t, const int32_t *, AdjDeferred *);
 template int launch_adjoint<double>(Ctx *, const ArrayP<double> &, const BallsP<double> &,
                                     const int64_t *, int, int64_t, const sbp_model *,
                                     const double *, double, uint32_t, const BallsP<double> &,
-                                    void *, size_t, hipStream_t, const int32_t *);
+                                    void *, size_t, hipStream_t, const int32_t *, AdjDeferred *);
 
 }  // namespace sbp

@@ -272,26 +272,62 @@ static int check_tuning(const sbp_tuning *t) {
 }
 
 // One iteration, shared by sbp_step and the graph capture.
-// y_aux: F D T floats of scratch when the model has a transducer response
-// (the simulated record before it, then the correlated cotangent).
+// One iteration: forward, residual and loss, adjoint, Adam.  Without a
+// transducer response it runs as four kernels after the forward's prep: the
+// forward's conversion writes v = 2 (y - y_ref) and the loss partial sums, and
+// the Adam kernel adds the adjoint's transducer slices and reduces the loss
+// (the same bits as the separate kernels).  y_aux: F D T floats of scratch
+// when the model has a response (the simulated record before it, then the
+// correlated cotangent).  `captured`: the forward's integer sums and device
+// words are zero on entry and are left zero (the conversion clears the sums,
+// Adam the words), so a captured sequence fills them once per launch; the
+// step count is *step_dev + step_add.
 static int step_body(Ctx *c, const sbp_array *arr, sbp_state *s, const sbp_model *model,
                      const float *y_ref, float *y_work, const sbp_adam_params *p,
                      const int32_t *step_dev, double *loss, double *partial, unsigned *misc,
                      void *fwd_ws, size_t fwd_ws_bytes, void *adj_ws, size_t adj_ws_bytes,
-                     float *y_aux, hipStream_t st) {
+                     float *y_aux, hipStream_t st, bool captured = false, int step_add = 0) {
     const ArrayP<float> a = arrp<float>(arr);
     const BallsP<float> b = ballsp<float>(&s->balls);
     const BallsP<float> g = ballsp<float>(&s->grad);
-    int rc = forward_with_response<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 0,
-                                          misc, fwd_ws, fwd_ws_bytes, y_aux, st);
-    if (rc) return rc;
     const int64_t n = (int64_t)arr->D * model->T;
-    rc = launch_residual_loss(partial, y_work, y_ref, n, s->F, y_work, loss, st);
+    const bool fused = !model->response && s->B_cap > 0;
+    int rc;
+    if (fused) {
+        FwdStep fs;
+        fs.ws_clean = captured;
+        fs.clear_after = captured;
+        fs.y_ref = y_ref;
+        fs.partial = partial;
+        rc = launch_forward<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 0, misc,
+                                   fwd_ws, fwd_ws_bytes, st, &fs);
+    } else {
+        rc = forward_with_response<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 0,
+                                          misc, fwd_ws, fwd_ws_bytes, y_aux, st);
+        if (!rc) rc = launch_residual_loss(partial, y_work, y_ref, n, s->F, y_work, loss, st);
+    }
     if (rc) return rc;
-    rc = adjoint_with_response<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 1.0f,
-                                      p->mask, g, adj_ws, adj_ws_bytes, y_aux, st);
+    AdamFuse af;
+    if (model->response) {
+        rc = adjoint_with_response<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work,
+                                          1.0f, p->mask, g, adj_ws, adj_ws_bytes, y_aux, st);
+    } else {
+        rc = launch_adjoint<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 1.0f,
+                                   p->mask, g, adj_ws, adj_ws_bytes, st, nullptr, &af.adj);
+    }
     if (rc) return rc;
-    return launch_adam(s, p, step_dev, model->a_softplus, st);
+    af.a_softplus = model->a_softplus;
+    if (fused) {
+        af.loss_partial = partial;
+        af.loss = loss;
+    }
+    // the forward left its device words set; in a captured sequence Adam
+    // clears them for the next forward (with fills skipped on entry).  Any
+    // forward that did not clear its sums (no fused conversion) breaks that,
+    // so a captured step always fuses or fills.
+    if (captured && fused) af.misc_clear = misc;
+    af.step_add = step_add;
+    return launch_adam(s, p, step_dev, model->a_softplus, st, &af);
 }
 
 }  // namespace sbp
@@ -714,15 +750,21 @@ int sbp_step_graph_create(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state,
         delete g;
         return hip_fail(e, "hipStreamBeginCapture");
     }
-    int body = SBP_OK;
-    for (int it = 0; it < iters && body == SBP_OK; ++it) {
+    // Each launch starts by zeroing the forward's device words and integer
+    // sums (fill kernels, not memset nodes); the iterations then leave them
+    // zero for each other, and one increment advances the step count by iters.
+    unsigned *g_misc = (unsigned *)((char *)g->ws + ws_res);
+    char *g_fwd = (char *)g->ws + ws_res + kMiscBytes;
+    int body = launch_fill<int32_t>((int32_t *)g_misc, kMiscFlags + SBP_MAX_FRAMES, 0, st);
+    if (body == SBP_OK)
+        body = launch_fill<uint64_t>((uint64_t *)g_fwd,
+                                     (int64_t)state->F * arr->D * ((int64_t)model->T + 1), 0, st);
+    for (int it = 0; it < iters && body == SBP_OK; ++it)
         body = step_body(&ctx->c, arr, state, model, y_ref, y_work, p, step_dev,
-                         loss + (int64_t)it * state->F, (double *)g->ws,
-                         (unsigned *)((char *)g->ws + ws_res), (char *)g->ws + ws_res + kMiscBytes,
-                         ws_fwd, (char *)g->ws + ws_res + kMiscBytes + ws_fwd, ws_adj,
-                         (float *)((char *)g->ws + ws_res + kMiscBytes + ws_fwd + ws_adj), st);
-        if (body == SBP_OK) body = launch_incr(step_dev, st);
-    }
+                         loss + (int64_t)it * state->F, (double *)g->ws, g_misc, g_fwd, ws_fwd,
+                         g_fwd + ws_fwd, ws_adj, (float *)(g_fwd + ws_fwd + ws_adj), st,
+                         /*captured=*/true, /*step_add=*/it);
+    if (body == SBP_OK) body = launch_incr_by(step_dev, iters, st);
     e = hipStreamEndCapture(st, &g->graph);
     if (body != SBP_OK || e != hipSuccess) {
         char msg[512];

@@ -80,18 +80,6 @@ int launch_decimate(const float *y, int64_t R_, int T, int f, float *out, hipStr
 
 // ------------------------------------------------------- residual + loss --
 
-__device__ inline double block_sum(double x, double *s_part) {
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) s_part[wid] = x;
-    __syncthreads();
-    double t = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) t += s_part[w];
-    return t;
-}
-
-constexpr int kLossBlocks = 512;  // partial sums per frame (fixed: deterministic order)
 
 __global__ void k_residual(const float *__restrict__ ys, const float *__restrict__ yr, int64_t n,
                            float *v, double *__restrict__ partial) {
@@ -135,48 +123,81 @@ int launch_residual_loss(double *partial, const float *ys, const float *yr, int6
 
 struct AdamArgs {
     float *param[5];
-    const float *grad[5];
+    float *grad[5];
     float *m[5];
     float *v[5];
     float lr[5];
     float beta1, beta2, eps;
     int32_t step;
     uint32_t mask;
+    // fused work of a reconstruction step (AdamFuse)
+    const float *part;
+    int nsl;
+    int64_t pstride;
+    int a_softplus;
+    const double *loss_partial;
+    double *loss;
+    unsigned *misc_clear;
+    int step_add;
+    int n_adam;   // workgroups of the update; the F after them reduce the loss
 };
 
 // PyTorch's single-tensor Adam in FP32: m.lerp_(g, 1-b1); v = v*b2 + (1-b2) g g;
 // denom = sqrt(v) / sqrt(bc2) + eps; param += (-lr/bc1) * m / denom, where the
-// bias corrections are formed in FP64 and rounded once.
+// bias corrections are formed in FP64 and rounded once.  blockIdx.y is the
+// parameter.  Inside a step the same kernel first adds the adjoint's
+// transducer slices into the gradient (same order and chain factor as
+// k_adj_reduce, so the same bits), and its last F workgroups of parameter 0
+// reduce the loss partial sums (as k_loss_final).
 __global__ void k_adam(AdamArgs a, const int64_t *__restrict__ ball_off, int F,
                        const int32_t *__restrict__ step_dev) {
+    __shared__ double s_part[kEw / 64];
+    const int k = (int)blockIdx.y;
+    if ((int)blockIdx.x >= a.n_adam) {
+        if (k != 0) return;
+        const int f = (int)blockIdx.x - a.n_adam;
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < kLossBlocks; i += blockDim.x)
+            acc += a.loss_partial[(int64_t)f * kLossBlocks + i];
+        const double t = block_sum(acc, s_part);
+        if (threadIdx.x == 0) a.loss[f] = t;
+        return;
+    }
+    if (a.misc_clear && blockIdx.x == 0 && k == 0)
+        for (int i = threadIdx.x; i < kMiscFlags + SBP_MAX_FRAMES; i += blockDim.x) a.misc_clear[i] = 0u;
+    if (!(a.mask & (1u << k))) return;
     const int64_t count = ball_off[F];
-    const int step = step_dev ? *step_dev : a.step;
+    const int step = step_dev ? *step_dev + a.step_add : a.step;
     const double bc1 = 1.0 - pow((double)a.beta1, (double)step);
     const double bc2 = 1.0 - pow((double)a.beta2, (double)step);
     const float bc2_sqrt = (float)sqrt(bc2);
     const float w1 = 1.0f - a.beta1;
     const float w2 = 1.0f - a.beta2;
+    const float step_size = (float)(-(double)a.lr[k] / bc1);
+    float *param = a.param[k], *grad = a.grad[k], *mk = a.m[k], *vk = a.v[k];
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-         i += (int64_t)gridDim.x * blockDim.x) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            if (!(a.mask & (1u << k))) continue;
-            const float g = a.grad[k][i];
-            float m = a.m[k][i];
-            float v = a.v[k][i];
-            m = m + w1 * (g - m);
-            v = v * a.beta2 + w2 * g * g;
-            const float denom = sqrtf(v) / bc2_sqrt + a.eps;
-            const float step_size = (float)(-(double)a.lr[k] / bc1);
-            a.param[k][i] = a.param[k][i] + step_size * (m / denom);
-            a.m[k][i] = m;
-            a.v[k][i] = v;
+         i += (int64_t)a.n_adam * blockDim.x) {
+        float g;
+        if (a.part) {
+            g = slice_sum(a.part + (int64_t)k * a.pstride + i, a.nsl, 5 * a.pstride);
+            if (k == 4 && a.a_softplus) g *= sigmoid_dev(param[i]);
+            grad[i] = g;
+        } else {
+            g = grad[i];
         }
+        float m = mk[i];
+        float v = vk[i];
+        m = m + w1 * (g - m);
+        v = v * a.beta2 + w2 * g * g;
+        const float denom = sqrtf(v) / bc2_sqrt + a.eps;
+        param[i] = param[i] + step_size * (m / denom);
+        mk[i] = m;
+        vk[i] = v;
     }
 }
 
 int launch_adam(const sbp_state *s, const sbp_adam_params *p, const int32_t *step_dev,
-                int a_softplus, hipStream_t st) {
+                int a_softplus, hipStream_t st, const AdamFuse *fuse) {
     (void)a_softplus;
     AdamArgs a;
     float *P[5] = {s->balls.x, s->balls.y, s->balls.z, s->balls.p0, s->balls.a};
@@ -195,8 +216,18 @@ int launch_adam(const sbp_state *s, const sbp_adam_params *p, const int32_t *ste
     a.eps = p->eps;
     a.step = p->step;
     a.mask = p->mask;
-    if (s->B_cap == 0) return SBP_OK;
-    hipLaunchKernelGGL(k_adam, dim3(ew_grid(s->B_cap)), dim3(kEw), 0, st, a, s->ball_off, s->F,
+    a.part = fuse ? fuse->adj.part : nullptr;
+    a.nsl = fuse ? fuse->adj.nsl : 0;
+    a.pstride = fuse ? fuse->adj.pstride : 0;
+    a.a_softplus = fuse ? fuse->a_softplus : 0;
+    a.loss_partial = fuse ? fuse->loss_partial : nullptr;
+    a.loss = fuse ? fuse->loss : nullptr;
+    a.misc_clear = fuse ? fuse->misc_clear : nullptr;
+    a.step_add = fuse ? fuse->step_add : 0;
+    a.n_adam = ew_grid(s->B_cap);
+    const int nloss = a.loss_partial ? s->F : 0;
+    if (s->B_cap == 0 && nloss == 0 && !a.misc_clear) return SBP_OK;
+    hipLaunchKernelGGL(k_adam, dim3(a.n_adam + nloss, 5), dim3(kEw), 0, st, a, s->ball_off, s->F,
                        step_dev);
     SBP_HIP(hipGetLastError());
     return SBP_OK;
@@ -233,12 +264,14 @@ int launch_reparam(float *a, float *m, float *v, const int64_t *ball_off, int F,
     return SBP_OK;
 }
 
-__global__ void k_incr(int32_t *p) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p += 1;
+__global__ void k_incr(int32_t *p, int32_t by) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p += by;
 }
 
-int launch_incr(int32_t *p, hipStream_t st) {
-    hipLaunchKernelGGL(k_incr, dim3(1), dim3(64), 0, st, p);
+int launch_incr(int32_t *p, hipStream_t st) { return launch_incr_by(p, 1, st); }
+
+int launch_incr_by(int32_t *p, int32_t by, hipStream_t st) {
+    hipLaunchKernelGGL(k_incr, dim3(1), dim3(64), 0, st, p, by);
     SBP_HIP(hipGetLastError());
     return SBP_OK;
 }

@@ -377,17 +377,35 @@ __device__ inline float fixed_scale(const unsigned *slot, int profile, const Lev
 
 // y = (accumulate ? y : 0) + q * sum, for every sample of the launch (grid.y =
 // frame); a flagged frame gets NaN.
-__global__ void k_fwd_convert(const unsigned long long *__restrict__ gacc, int64_t nper,
+// Inside a step (y_ref given) the value written is v = 2 (y - y_ref), and the
+// workgroup's sum of (y - y_ref)^2 goes to partial[frame][blockIdx.x]
+// (gridDim.x = kLossBlocks); with `clear` each integer sum is zeroed once read.
+__global__ void k_fwd_convert(unsigned long long *__restrict__ gacc, int64_t nper,
                               const unsigned *__restrict__ misc, int profile, Level lc,
-                              int accumulate, float *__restrict__ y) {
+                              int accumulate, float *__restrict__ y, int clear,
+                              const float *__restrict__ y_ref, double *__restrict__ partial) {
+    __shared__ double s_part[4];
     const bool bad = misc[kMiscFlags + blockIdx.y] != 0;
     const float inv_scale = 1.0f / fixed_scale(misc + kMiscBound, profile, lc);
-    const unsigned long long *g = gacc + (int64_t)blockIdx.y * nper;
+    unsigned long long *g = gacc + (int64_t)blockIdx.y * nper;
     float *yf = y + (int64_t)blockIdx.y * nper;
+    const float *rf = y_ref ? y_ref + (int64_t)blockIdx.y * nper : nullptr;
+    double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nper;
          i += (int64_t)gridDim.x * blockDim.x) {
         const float v = bad ? __builtin_nanf("") : FwdAcc<float>::value(g[i], inv_scale);
-        yf[i] = accumulate ? yf[i] + v : v;
+        if (clear) g[i] = 0ull;
+        if (rf) {
+            const float e = v - rf[i];
+            yf[i] = 2.0f * e;
+            acc += (double)e * (double)e;
+        } else {
+            yf[i] = accumulate ? yf[i] + v : v;
+        }
+    }
+    if (rf) {
+        const double t = block_sum(acc, s_part);
+        if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
     }
 }
 
@@ -684,20 +702,42 @@ __global__ __launch_bounds__(512, 4) void k_forward_gz(ArrayP<float> arr, FwdPre
 
 // y[f][d][n] = (accumulate ? y : 0) + q (W[f][d][n+1] - W[f][d][n]); a flagged
 // frame gets NaN.  grid.y = frame, workgroups stride over the transducers.
-__global__ void k_fwd_convert_edges(const unsigned long long *__restrict__ gacc, int D, int T,
+// Inside a step (y_ref given) the value written is v = 2 (y - y_ref) and the
+// workgroup's sum of (y - y_ref)^2 goes to partial[frame][blockIdx.x]
+// (gridDim.x = kLossBlocks); with `clear` a row's integer sums are zeroed once
+// the whole workgroup has read them (each edge feeds two samples).
+__global__ void k_fwd_convert_edges(unsigned long long *__restrict__ gacc, int D, int T,
                                     const unsigned *__restrict__ misc, Level lc, int accumulate,
-                                    float *__restrict__ y) {
+                                    float *__restrict__ y, int clear,
+                                    const float *__restrict__ y_ref, double *__restrict__ partial) {
+    __shared__ double s_part[4];
     const bool bad = misc[kMiscFlags + blockIdx.y] != 0;
     const float inv_scale = 1.0f / fixed_scale(misc + kMiscBound, GAUSS, lc);
+    double acc = 0.0;
     for (int d = blockIdx.x; d < D; d += gridDim.x) {
         const int64_t r = (int64_t)blockIdx.y * D + d;
-        const unsigned long long *w = gacc + r * (T + 1);
+        unsigned long long *w = gacc + r * (T + 1);
         float *yr = y + r * T;
+        const float *rr = y_ref ? y_ref + r * T : nullptr;
         for (int n = threadIdx.x; n < T; n += blockDim.x) {
             const long long diff = (long long)(w[n + 1] - w[n]);
             const float v = bad ? __builtin_nanf("") : (float)((double)diff * (double)inv_scale);
-            yr[n] = accumulate ? yr[n] + v : v;
+            if (rr) {
+                const float e = v - rr[n];
+                yr[n] = 2.0f * e;
+                acc += (double)e * (double)e;
+            } else {
+                yr[n] = accumulate ? yr[n] + v : v;
+            }
         }
+        if (clear) {
+            __syncthreads();
+            for (int n = threadIdx.x; n <= T; n += blockDim.x) w[n] = 0ull;
+        }
+    }
+    if (y_ref) {
+        const double t = block_sum(acc, s_part);
+        if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
     }
 }
 
@@ -812,8 +852,13 @@ size_t forward_ws_bytes(int F, int D, int T, int64_t B_cap, size_t elem) {
 template <typename R>
 int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
                    int F, int64_t B_cap, const sbp_model *m, R *y, int accumulate,
-                   unsigned *misc, void *ws, size_t ws_bytes, hipStream_t st) {
+                   unsigned *misc, void *ws, size_t ws_bytes, hipStream_t st,
+                   const FwdStep *step) {
     const Level lc = make_level(m);
+    const FwdStep none{};
+    const FwdStep &sp = step ? *step : none;
+    if (sp.y_ref && (sizeof(R) != sizeof(float) || !sp.partial))
+        return fail(SBP_E_ARG, "the fused residual needs the FP32 forward and a partial buffer");
     const int64_t nper = (int64_t)arr.D * m->T;
     const int64_t ns = (int64_t)F * nper;
     if (B_cap == 0 || sizeof(R) != sizeof(float)) {
@@ -825,8 +870,9 @@ int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const i
     }
     if (!misc) return fail(SBP_E_ARG, "forward needs the context's device words");
     // bound word and frame flags start at zero
-    int rc = launch_fill<int32_t>((int32_t *)misc, kMiscFlags + SBP_MAX_FRAMES, 0, st);
-    if (rc) return rc;
+    int rc = SBP_OK;
+    if (!sp.ws_clean && (rc = launch_fill<int32_t>((int32_t *)misc, kMiscFlags + SBP_MAX_FRAMES, 0, st)))
+        return rc;
     int64_t nbb = (B_cap + 255) / 256;
     if (nbb > 1024) nbb = 1024;
     unsigned long long *gacc = nullptr;
@@ -842,8 +888,7 @@ int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const i
         FwdPrepP pb;
         float **fields[6] = {&pb.x, &pb.y, &pb.z, &pb.w, &pb.q0, &pb.pa2};
         for (int k = 0; k < 6; ++k) *fields[k] = (float *)(pp + k * pb_bytes);
-        rc = launch_fill<uint64_t>((uint64_t *)gacc, ne, 0, st);
-        if (rc) return rc;
+        if (!sp.ws_clean && (rc = launch_fill<uint64_t>((uint64_t *)gacc, ne, 0, st))) return rc;
         hipLaunchKernelGGL(k_fwd_prep, dim3((int)nbb), dim3(kPrepBlock), 0, st,
                            BallsP<float>{(float *)balls.x, (float *)balls.y, (float *)balls.z,
                                          (float *)balls.p0, (float *)balls.a},
@@ -858,10 +903,10 @@ int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const i
         else
             rc = run_forward_gz<OMNI>(c, af, pb, ball_off, F, B_cap, lc, bound, gacc, st);
         if (rc) return rc;
-        int nbx = arr.D < 1024 ? arr.D : 1024;
-        hipLaunchKernelGGL(k_fwd_convert_edges, dim3(nbx, F), dim3(256), 0, st,
-                           (const unsigned long long *)gacc, arr.D, m->T, (const unsigned *)misc, lc,
-                           accumulate, (float *)y);
+        int nbx = sp.y_ref ? kLossBlocks : (arr.D < 1024 ? arr.D : 1024);
+        hipLaunchKernelGGL(k_fwd_convert_edges, dim3(nbx, F), dim3(256), 0, st, gacc, arr.D, m->T,
+                           (const unsigned *)misc, lc, accumulate, (float *)y,
+                           (int)sp.clear_after, sp.y_ref, sp.partial);
         SBP_HIP(hipGetLastError());
         return SBP_OK;
       }
@@ -870,8 +915,7 @@ int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const i
         if (!ws || ws_bytes < (size_t)ns * sizeof(unsigned long long))
             return fail(SBP_E_NOMEM, "forward workspace too small");
         gacc = (unsigned long long *)ws;
-        rc = launch_fill<uint64_t>((uint64_t *)gacc, ns, 0, st);
-        if (rc) return rc;
+        if (!sp.ws_clean && (rc = launch_fill<uint64_t>((uint64_t *)gacc, ns, 0, st))) return rc;
         hipLaunchKernelGGL(k_amp_bound, dim3((int)nbb), dim3(256), 0, st,
                            BallsP<float>{(float *)balls.x, (float *)balls.y, (float *)balls.z,
                                          (float *)balls.p0, (float *)balls.a},
@@ -912,17 +956,19 @@ int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const i
         SBP_HIP(hipGetLastError());
         return SBP_OK;
     }
-    hipLaunchKernelGGL(k_fwd_convert, dim3((int)nb, F), dim3(256), 0, st, (const unsigned long long *)gacc,
-                       nper, (const unsigned *)misc, profile_code(m), lc, accumulate, (float *)y);
+    if (sp.y_ref) nb = kLossBlocks;
+    hipLaunchKernelGGL(k_fwd_convert, dim3((int)nb, F), dim3(256), 0, st, gacc, nper,
+                       (const unsigned *)misc, profile_code(m), lc, accumulate, (float *)y,
+                       (int)sp.clear_after, sp.y_ref, sp.partial);
     SBP_HIP(hipGetLastError());
     return SBP_OK;
 }
 
 template int launch_forward<float>(Ctx *, const ArrayP<float> &, const BallsP<float> &,
                                    const int64_t *, int, int64_t, const sbp_model *, float *, int,
-                                   unsigned *, void *, size_t, hipStream_t);
+                                   unsigned *, void *, size_t, hipStream_t, const FwdStep *);
 template int launch_forward<double>(Ctx *, const ArrayP<double> &, const BallsP<double> &,
                                     const int64_t *, int, int64_t, const sbp_model *, double *,
-                                    int, unsigned *, void *, size_t, hipStream_t);
+                                    int, unsigned *, void *, size_t, hipStream_t, const FwdStep *);
 
 }  // namespace sbp

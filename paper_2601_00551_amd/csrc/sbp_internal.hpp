@@ -256,6 +256,53 @@ struct BallsP {
     R *x, *y, *z, *p0, *a;
 };
 
+// Sum of x over the workgroup in a fixed order (lanes, then waves); the
+// result is valid in thread 0.  s_part holds one double per wave.
+__device__ inline double block_sum(double x, double *s_part) {
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) s_part[wid] = x;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) t += s_part[w];
+    return t;
+}
+
+// p[0] + p[step] + ... + p[(nsl - 1) step], added in that order (the result
+// does not depend on how the loads are issued: eight at a time here, since the
+// slices of small clouds are many and the sum is latency-bound).
+template <typename R>
+__device__ inline R slice_sum(const R *__restrict__ p, int nsl, int64_t step) {
+    R s = R(0);
+    int sl = 0;
+    for (; sl + 8 <= nsl; sl += 8) {
+        R v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = p[(int64_t)(sl + j) * step];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s += v[j];
+    }
+    for (; sl < nsl; ++sl) s += p[(int64_t)sl * step];
+    return s;
+}
+
+// Partial sums of the loss per frame (a fixed count: a deterministic order).
+constexpr int kLossBlocks = 512;
+
+// The forward inside a reconstruction step (FP32):
+//   ws_clean     misc and the integer sums are zero on entry (no fills);
+//   clear_after  the conversion zeroes each integer sum once it has read it;
+//   y_ref        when set, the conversion writes v = 2 (y - y_ref) instead of y,
+//                and the sums of (y - y_ref)^2 (FP64, kLossBlocks per frame)
+//                to partial[F][kLossBlocks].
+struct FwdStep {
+    bool ws_clean = false;
+    bool clear_after = false;
+    const float *y_ref = nullptr;
+    double *partial = nullptr;
+};
+
 // misc: kMiscBytes of device words (the fixed-point bound of the FP32 path and
 // the per-frame non-finite flags); ws: the FP32 path's per-sample integer sums
 // (forward_ws_bytes; none for FP64).
@@ -263,7 +310,18 @@ size_t forward_ws_bytes(int F, int D, int T, int64_t B_cap, size_t elem);
 template <typename R>
 int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
                    int F, int64_t B_cap, const sbp_model *m, R *y, int accumulate,
-                   unsigned *misc, void *ws, size_t ws_bytes, hipStream_t st);
+                   unsigned *misc, void *ws, size_t ws_bytes, hipStream_t st,
+                   const FwdStep *step = nullptr);
+
+// An all-gradient FP32 adjoint that splits the transducers into slices can
+// leave the sum of the slices to the Adam kernel that follows it: with
+// `defer` given, the launch skips its reduction and reports the partial sums
+// (part == NULL when it did not split and wrote the gradients itself).
+struct AdjDeferred {
+    const float *part = nullptr;
+    int nsl = 0;
+    int64_t pstride = 0;
+};
 
 // vscale multiplies v (the filter passes y_ref with vscale = -2).  ws holds the
 // per-slice partial gradients when the launch splits the transducers into
@@ -273,7 +331,7 @@ template <typename R>
 int launch_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
                    int F, int64_t B_cap, const sbp_model *m, const R *v, R vscale,
                    uint32_t mask, const BallsP<R> &grad, void *ws, size_t ws_bytes, hipStream_t st,
-                   const int32_t *order = nullptr);
+                   const int32_t *order = nullptr, AdjDeferred *defer = nullptr);
 
 template <typename R>
 int launch_fill(R *p, int64_t n, R value, hipStream_t st);
@@ -283,8 +341,26 @@ int launch_decimate(const float *y, int64_t R_, int T, int f, float *out, hipStr
 size_t residual_ws_bytes(int F);
 int launch_residual_loss(double *partial_ws, const float *ys, const float *yr, int64_t n, int F,
                          float *v, double *loss, hipStream_t st);
+// What the Adam kernel of a reconstruction step also does:
+//   part/nsl/pstride  sum the adjoint's transducer slices into the gradients
+//                     (in slice order, as the adjoint's own reduction) first;
+//   a_softplus        the size gradient then takes the softplus chain factor;
+//   loss_partial      reduce partial[F][kLossBlocks] into loss[F] (F extra
+//                     workgroups);
+//   misc_clear        zero the forward's device words afterwards (so that the
+//                     next forward needs no fill);
+//   step_add          the step count is *step_dev + step_add.
+struct AdamFuse {
+    AdjDeferred adj;
+    int a_softplus = 0;
+    const double *loss_partial = nullptr;
+    double *loss = nullptr;
+    unsigned *misc_clear = nullptr;
+    int step_add = 0;
+};
 int launch_adam(const sbp_state *s, const sbp_adam_params *p, const int32_t *step_dev,
-                int a_softplus, hipStream_t st);
+                int a_softplus, hipStream_t st, const AdamFuse *fuse = nullptr);
+int launch_incr_by(int32_t *p, int32_t by, hipStream_t st);
 size_t compact_ws_bytes(int64_t B_cap);
 int launch_compact(void *ws, const float *g, int strict, const BallsP<float> &in,
                    const int64_t *off_in, int F, int64_t B_cap, const BallsP<float> &out,
