@@ -166,14 +166,21 @@ __global__ void k_adam(AdamArgs a, const int64_t *__restrict__ ball_off, int F,
     if (a.misc_clear && blockIdx.x == 0 && k == 0)
         for (int i = threadIdx.x; i < kMiscFlags + SBP_MAX_FRAMES; i += blockDim.x) a.misc_clear[i] = 0u;
     if (!(a.mask & (1u << k))) return;
+    // the bias corrections once per workgroup (FP64 pow is costly per lane)
+    __shared__ float s_bc[2];
+    if (threadIdx.x == 0) {
+        const int step = step_dev ? *step_dev + a.step_add : a.step;
+        const double bc1 = 1.0 - pow((double)a.beta1, (double)step);
+        const double bc2 = 1.0 - pow((double)a.beta2, (double)step);
+        s_bc[0] = (float)sqrt(bc2);
+        s_bc[1] = (float)(-(double)a.lr[k] / bc1);
+    }
+    __syncthreads();
     const int64_t count = ball_off[F];
-    const int step = step_dev ? *step_dev + a.step_add : a.step;
-    const double bc1 = 1.0 - pow((double)a.beta1, (double)step);
-    const double bc2 = 1.0 - pow((double)a.beta2, (double)step);
-    const float bc2_sqrt = (float)sqrt(bc2);
+    const float bc2_sqrt = s_bc[0];
+    const float step_size = s_bc[1];
     const float w1 = 1.0f - a.beta1;
     const float w2 = 1.0f - a.beta2;
-    const float step_size = (float)(-(double)a.lr[k] / bc1);
     float *param = a.param[k], *grad = a.grad[k], *mk = a.m[k], *vk = a.v[k];
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)a.n_adam * blockDim.x) {
@@ -224,7 +231,7 @@ int launch_adam(const sbp_state *s, const sbp_adam_params *p, const int32_t *ste
     a.loss = fuse ? fuse->loss : nullptr;
     a.misc_clear = fuse ? fuse->misc_clear : nullptr;
     a.step_add = fuse ? fuse->step_add : 0;
-    a.n_adam = ew_grid(s->B_cap);
+    a.n_adam = ew_grid(s->B_cap) < 2048 ? ew_grid(s->B_cap) : 2048;   // per parameter row
     const int nloss = a.loss_partial ? s->F : 0;
     if (s->B_cap == 0 && nloss == 0 && !a.misc_clear) return SBP_OK;
     hipLaunchKernelGGL(k_adam, dim3(a.n_adam + nloss, 5), dim3(kEw), 0, st, a, s->ball_off, s->F,

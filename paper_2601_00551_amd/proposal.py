@@ -139,13 +139,27 @@ class ProposalMLP:
         self.adam(lr=lr, stream=stream)
         return loss
 
-    def save(self, path):
-        np.savez(path, params=self.params.cpu().numpy())
+    def save(self, path, bf16=False):
+        """Write the parameters (.npz).  bf16=True stores them rounded to
+        BF16 (to nearest, ties to even) as their 16-bit patterns: the matrix
+        cores read BF16 copies, so inference from the file is unchanged and
+        the file is half the size."""
+        p = self.params.cpu().numpy()
+        if bf16:
+            bits = p.view(np.uint32).astype(np.uint64)
+            rounded = ((bits + 0x7FFF + ((bits >> 16) & 1)) >> 16).astype(np.uint16)
+            np.savez_compressed(path, params_bf16=rounded)
+        else:
+            np.savez(path, params=p)
 
     @classmethod
     def load(cls, ctx, path, device="cuda:0"):
         with np.load(path) as z:
-            return cls(ctx, device=device, params=z["params"])
+            if "params_bf16" in z:
+                p = (z["params_bf16"].astype(np.uint32) << 16).view(np.float32)
+            else:
+                p = z["params"]
+            return cls(ctx, device=device, params=p)
 
 
 # ------------------------------------------------------ candidate sites --
@@ -287,30 +301,58 @@ class LearnedProposer:
     """
 
     def __init__(self, mlp: ProposalMLP, builder: FeatureBuilder, a_init=0.1, judge=True,
-                 max_scale=4.0, stages=None, max_per_stage=None):
+                 max_scale=4.0, stages=None, max_per_stage=None, patience=None, reprobe_every=None):
         self.mlp, self.builder, self.a_init, self.judge = mlp, builder, a_init, judge
         self.max_scale = max_scale
         self.stages = None if stages is None else set(stages)   # stage indices it acts in
         self.max_per_stage = max_per_stage                       # growth points per stage
+        # the gate: after `patience` proposals in a row that the loss judge
+        # rejected, the network stays off (None: never).  With reprobe_every
+        # = None the gate is per run (new_run opens it again); with a number
+        # it carries over the runs of one configuration and reopens for one
+        # probe every `reprobe_every` runs.
+        self.patience = patience
+        self.reprobe_every = reprobe_every
+        self.rejected_in_a_row = 0
+        self.gated = False
+        self.runs = 0
+        self.closed_at_run = None
         self.events = []
         self._zero = None
         self._ys = None
         self._off = None
 
+    def new_run(self):
+        """Call before each reconstruction the proposer serves."""
+        self.runs += 1
+        if self.reprobe_every is None:
+            self.gated, self.rejected_in_a_row = False, 0
+        elif self.gated and self.runs - self.closed_at_run >= self.reprobe_every:
+            self.gated = False
+            self.rejected_in_a_row = max(0, (self.patience or 1) - 1)   # one probe
+
     def __call__(self, r: recon.Recon, si, model, y_k, yw):
+        if self.gated:
+            return
         if self.stages is not None and si not in self.stages:
             return
         if self.max_per_stage is not None and \
-                sum(e["stage"] == si for e in self.events) >= self.max_per_stage:
+                sum(e["stage"] == si and e["run"] == self.runs for e in self.events) >= self.max_per_stage:
             return
         t0 = time.perf_counter()
-        ev = dict(stage=si, candidates=0, accepted=0, kept=False, scale=0.0)
+        ev = dict(run=self.runs, stage=si, candidates=0, accepted=0, kept=False, scale=0.0)
         self.events.append(ev)
         try:
             self._propose(r, model, y_k, yw, ev)
         finally:
-            torch.cuda.synchronize(yw.device)
+            if yw.is_cuda:
+                torch.cuda.synchronize(yw.device)
             ev["seconds"] = time.perf_counter() - t0
+        self.rejected_in_a_row = 0 if ev["kept"] else self.rejected_in_a_row + 1
+        if self.patience is not None and self.rejected_in_a_row >= self.patience:
+            self.gated = True
+            self.closed_at_run = self.runs
+            ev["gate_closed"] = True
 
     def _propose(self, r, model, y_k, yw, ev):
         st = r.state
@@ -410,13 +452,15 @@ def plain_run(ctx, wl, y, stages, builder=None, capacity=0, graph_iters=0, stop_
 
 
 def generate(ctx, indices, grid: Grid, stages, workload=proposal_workload, log=print, labels="phantom",
-             **wl_kw):
+             neg_frac=1.0, **wl_kw):
     """Training set from plain reconstructions of the given workload indices.
 
     labels = "phantom": a candidate is labelled by the seeded phantom's mass in
     its cell (the reconstructions are of synthetic phantoms, so the answer the
     network should give is known); "final": by the mass the plain
-    reconstruction ends up with in the cell."""
+    reconstruction ends up with in the cell.  neg_frac < 1 keeps every positive
+    site and a seeded random fraction of the negative ones (the balanced
+    "auto" class weight of train() is unchanged by it)."""
     builder = FeatureBuilder(ctx, grid, a_probe=0.1, half=-grid.ox)
     Xs, ys, ps = [], [], []
     for i in indices:
@@ -435,6 +479,9 @@ def generate(ctx, indices, grid: Grid, stages, workload=proposal_workload, log=p
             raise ValueError(f"unknown labels {labels!r}")
         if rec.events:
             X, yg, yp = label_events(rec.events, grid, fm)
+            if neg_frac < 1.0:
+                keep = (yg > 0.5) | (np.random.default_rng(70_000 + i).random(len(yg)) < neg_frac)
+                X, yg, yp = X[keep], yg[keep], yp[keep]
             Xs.append(X), ys.append(yg), ps.append(yp)
         log(json.dumps(dict(event="plain-run", index=i, wall_s=round(out["wall_s"], 3),
                             final_loss=out["final_loss"], growth_points=len(rec.events),
@@ -443,12 +490,16 @@ def generate(ctx, indices, grid: Grid, stages, workload=proposal_workload, log=p
     return np.concatenate(Xs), np.concatenate(ys), np.concatenate(ps)
 
 
-def train(mlp: ProposalMLP, X, yg, yp, epochs=4, batch=8192, lr=1e-3, seed=0, log=print):
-    """Minibatch Adam on the GPU; returns the per-epoch mean losses.  Classes are
-    not re-weighted: a site is accepted where the network's P(grow) > 1/2."""
+def train(mlp: ProposalMLP, X, yg, yp, epochs=4, batch=8192, lr=1e-3, seed=0, log=print, pos_weight=1.0):
+    """Minibatch Adam on the GPU; returns the per-epoch mean losses.  With
+    pos_weight = 1 the classes are not re-weighted (a site is accepted where
+    the network's P(grow) > 1/2); "auto" weighs the positives by the
+    negatives-to-positives ratio of the training set."""
     rng = np.random.default_rng(seed)
     n = len(X)
-    pos_weight = 1.0
+    if pos_weight == "auto":
+        p = float(np.mean(yg))
+        pos_weight = (1.0 - p) / p if 0.0 < p < 1.0 else 1.0
     order = rng.permutation(n)
     dev = mlp.dev
     Xd = torch.as_tensor(np.ascontiguousarray(X[order], np.float32), device=dev)
@@ -468,6 +519,17 @@ def train(mlp: ProposalMLP, X, yg, yp, epochs=4, batch=8192, lr=1e-3, seed=0, lo
     return hist
 
 
+def auc(score, label):
+    """Area under the ROC curve (ties count one half) of scores against 0/1 labels."""
+    from scipy.stats import rankdata
+    label = np.asarray(label) > 0.5
+    npos, nneg = int(label.sum()), int((~label).sum())
+    if npos == 0 or nneg == 0:
+        return None
+    r = rankdata(np.asarray(score, np.float64))
+    return float((r[label].sum() - npos * (npos + 1) / 2.0) / (npos * nneg))
+
+
 def first_below(log, target):
     """Time of the first final-stage iteration whose loss is <= target (None if none)."""
     last = max(e["stage"] for e in log)
@@ -475,6 +537,68 @@ def first_below(log, target):
         if e["kind"] == "iter" and e["stage"] == last and e["loss"] <= target:
             return e["t"]
     return None
+
+
+def compare(ctx, mlp, stages, grid, evals, n_init, when=(0,), max_per_stage=None, patience=1,
+            reprobe_every=None, graph_iters=0, labels="final", first_index=10_000, log=print):
+    """Wall time to the plain method's final residual with and without the
+    network on `evals` held-out phantoms (seeds first_index + j), run one
+    after the other with one proposer (so a gate that carries over runs,
+    reprobe_every, sees them in order), and the network's held-out AUC on the
+    candidate sites of the plain runs."""
+    rows, scores, labs = [], [], []
+    builder = FeatureBuilder(ctx, grid, a_probe=0.1, half=-grid.ox)
+    lp = LearnedProposer(mlp, builder, stages=list(when) if when else None,
+                         max_per_stage=max_per_stage, patience=patience, reprobe_every=reprobe_every)
+    for j in range(evals):
+        i = first_index + j
+        wl = proposal_workload(i, n_init=n_init)
+        y = synthetic_measurement(ctx, wl, seed=60_000 + j)
+        cap = 4 * len(wl.init["x"])
+        rec = Recorder(builder)
+        _, plain = plain_run(ctx, wl, y, stages, capacity=cap, proposer=rec)
+        # runs differ by FP32 summation order (~1e-5 relative): the target is
+        # the plain final loss plus a 1e-3 relative margin, for every run
+        target = plain["final_loss"] * (1.0 + 1e-3)
+        _, plain2 = plain_run(ctx, wl, y, stages, capacity=cap, stop_below=target,
+                              graph_iters=graph_iters)
+        lp.a_init = wl.a_init
+        lp.new_run()
+        n_ev = len(lp.events)
+        _, learned = plain_run(ctx, wl, y, stages, capacity=cap, stop_below=target, proposer=lp,
+                               graph_iters=graph_iters)
+        if rec.events:
+            st = plain["state"]
+            if labels == "phantom":
+                gt = {k: torch.as_tensor(np.asarray(v, np.float32), device=mlp.dev) for k, v in wl.gt.items()}
+                off = torch.tensor([0, len(wl.gt["x"])], dtype=torch.int64, device=mlp.dev)
+                fm = grid_mass(ctx, gt, off, grid).cpu().numpy()
+            else:
+                fm = grid_mass(ctx, st.balls, st.ball_off, grid, B_cap=st.B_cap).cpu().numpy()
+            X, yg, _ = label_events(rec.events, grid, fm)
+            out = mlp.forward(torch.as_tensor(X, device=mlp.dev)).cpu().numpy()
+            scores.append(out[:, 0])
+            labs.append(yg)
+        row = dict(event="compare", index=i,
+                   plain_s=plain2["t_target"] or plain2["wall_s"], plain_reached=plain2["t_target"] is not None,
+                   plain_final_loss=plain["final_loss"],
+                   learned_s=learned["t_target"] or learned["wall_s"],
+                   learned_reached=learned["t_target"] is not None, learned_final_loss=learned["final_loss"],
+                   proposals_tried=len(lp.events) - n_ev,
+                   proposals_kept=sum(e["kept"] for e in lp.events[n_ev:]),
+                   gate_closed=lp.gated, proposal_s=sum(e.get("seconds", 0.0) for e in lp.events[n_ev:]))
+        rows.append(row)
+        log(json.dumps(row), flush=True)
+    S = np.concatenate(scores) if scores else np.zeros(0)
+    Lb = np.concatenate(labs) if labs else np.zeros(0)
+    plain_s = float(np.sum([r["plain_s"] for r in rows]))
+    learned_s = float(np.sum([r["learned_s"] for r in rows]))
+    return dict(rows=rows, phantoms=evals, plain_s=plain_s, learned_s=learned_s,
+                speedup=plain_s / learned_s if learned_s > 0 else None,
+                per_phantom_speedup=[r["plain_s"] / r["learned_s"] for r in rows],
+                reached=sum(r["learned_reached"] for r in rows),
+                heldout_auc=auc(S, Lb), heldout_sites=int(len(Lb)),
+                heldout_positives=float(np.mean(Lb)) if len(Lb) else None)
 
 
 def main(argv=None):
@@ -485,66 +609,69 @@ def main(argv=None):
     ap.add_argument("--iters", type=int, default=60)
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--n-init", type=int, default=200_000)
-    ap.add_argument("--labels", choices=("phantom", "final"), default="phantom")
+    ap.add_argument("--train-n-init", type=int, default=None,
+                    help="initial cloud of the training runs (default: --n-init)")
+    ap.add_argument("--labels", choices=("phantom", "final"), default="final")
+    ap.add_argument("--pos-weight", default="auto", help="a number, or auto (negatives / positives)")
+    ap.add_argument("--patience", type=int, default=1,
+                    help="rejected proposals in a row after which the network stays off (0: never)")
+    ap.add_argument("--reprobe-every", type=int, default=0,
+                    help="carry the gate over the runs, reopening it for one probe every N runs "
+                         "(0: the gate is per run)")
+    ap.add_argument("--neg-frac", type=float, default=1.0,
+                    help="fraction of the negative training sites kept (all positives are)")
     ap.add_argument("--when", default="0", help="comma-separated stage indices the network acts in "
                                                 "(default: the coarse stage, where its proposals are kept)")
     ap.add_argument("--max-per-stage", type=int, default=None)
-    ap.add_argument("--graph-iters", type=int, default=10,
-                    help="iterations per captured HIP graph in the batched runs")
+    ap.add_argument("--graph-iters", type=int, default=0,
+                    help="iterations per captured HIP graph in the timed runs")
+    ap.add_argument("--load-weights", default=None, help="skip training: use these weights")
+    ap.add_argument("--save-weights", default=None, help="write the trained weights (BF16) here")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     ctx = api.context(0)
     grid = Grid.cube(10.0, 0.2)
     stages = default_schedule((4, 2, 1), iters=args.iters)
-    t0 = time.perf_counter()
-    X, yg, yp = generate(ctx, range(args.train), grid, stages, labels=args.labels, n_init=args.n_init)
-    t_gen = time.perf_counter() - t0
-    mlp = ProposalMLP(ctx, seed=0)
-    t0 = time.perf_counter()
-    hist = train(mlp, X, yg, yp, epochs=args.epochs)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    rows = []
-    for j in range(args.eval):
-        i = 10_000 + j
-        wl = proposal_workload(i, n_init=args.n_init)
-        y = synthetic_measurement(ctx, wl, seed=60_000 + j)
-        cap = 4 * len(wl.init["x"])
-        _, plain = plain_run(ctx, wl, y, stages, capacity=cap)
-        # runs differ by FP32 summation order (~1e-5 relative): the target is the
-        # plain final loss plus a 1e-3 relative margin, for every compared run
-        target = plain["final_loss"] * (1.0 + 1e-3)
-        _, pgraph = plain_run(ctx, wl, y, stages, capacity=cap, stop_below=target,
-                              graph_iters=args.graph_iters)
-        when = [int(v) for v in args.when.split(",") if v != ""] or None
-        lp = LearnedProposer(mlp, FeatureBuilder(ctx, grid, a_probe=0.1, half=10.0), a_init=wl.a_init,
-                             stages=when, max_per_stage=args.max_per_stage)
-        r, learned = plain_run(ctx, wl, y, stages, capacity=cap, stop_below=target, proposer=lp,
-                               graph_iters=args.graph_iters)
-        row = dict(event="compare", index=i, plain_wall_s=plain["wall_s"], plain_final_loss=plain["final_loss"],
-                   plain_t_target=first_below(plain["log"], target),
-                   plain_graph_s=pgraph["t_target"] or pgraph["wall_s"],
-                   plain_graph_reached=pgraph["t_target"] is not None,
-                   learned_wall_s=learned["t_target"] or learned["wall_s"],
-                   learned_reached=learned["t_target"] is not None,
-                   learned_final_loss=learned["final_loss"],
-                   proposals_kept=sum(e["kept"] for e in lp.events),
-                   proposals_tried=len(lp.events),
-                   proposal_s=sum(e.get("seconds", 0.0) for e in lp.events),
-                   events=[{k: (round(v, 6) if isinstance(v, float) else v) for k, v in e.items()}
-                           for e in lp.events])
-        rows.append(row)
-        print(json.dumps(row), flush=True)
-    summary = dict(event="summary", train_runs=args.train, samples=len(X), positives=float(np.mean(yg)),
+    pw = args.pos_weight if args.pos_weight == "auto" else float(args.pos_weight)
+    t_gen = t_train = 0.0
+    hist, n_samples, positives = [], 0, None
+    if args.load_weights:
+        mlp = ProposalMLP.load(ctx, args.load_weights)
+    else:
+        t0 = time.perf_counter()
+        X, yg, yp = generate(ctx, range(args.train), grid, stages, labels=args.labels,
+                             n_init=args.train_n_init or args.n_init, neg_frac=args.neg_frac)
+        t_gen = time.perf_counter() - t0
+        n_samples, positives = len(X), float(np.mean(yg))
+        mlp = ProposalMLP(ctx, seed=0)
+        t0 = time.perf_counter()
+        hist = train(mlp, X, yg, yp, epochs=args.epochs, pos_weight=pw)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        del X, yg, yp
+        if args.save_weights:
+            mlp.save(args.save_weights, bf16=True)
+    when = [int(v) for v in args.when.split(",") if v != ""] or None
+    res = compare(ctx, mlp, stages, grid, args.eval, args.n_init, when=when,
+                  max_per_stage=args.max_per_stage, patience=args.patience or None,
+                  reprobe_every=args.reprobe_every or None, graph_iters=args.graph_iters,
+                  labels=args.labels)
+    summary = dict(event="summary", train_runs=0 if args.load_weights else args.train,
+                   labels=args.labels, pos_weight=pw, neg_frac=args.neg_frac, patience=args.patience,
+                   reprobe_every=args.reprobe_every, samples=n_samples, positives=positives,
                    generate_s=t_gen, train_s=t_train, epoch_losses=hist,
-                   plain_wall_s=float(np.mean([r["plain_wall_s"] for r in rows])) if rows else None,
-                   plain_graph_s=float(np.mean([r["plain_graph_s"] for r in rows])) if rows else None,
-                   learned_wall_s=float(np.mean([r["learned_wall_s"] for r in rows])) if rows else None,
-                   reached=sum(r["learned_reached"] for r in rows))
+                   **{k: v for k, v in res.items() if k != "rows"})
     print(json.dumps(summary), flush=True)
+    if args.save_weights and not args.load_weights:
+        meta = {k: summary[k] for k in ("train_runs", "labels", "pos_weight", "neg_frac", "samples",
+                                        "positives", "epoch_losses", "heldout_auc", "heldout_sites")}
+        meta.update(n_init=args.train_n_init or args.n_init, epochs=args.epochs, iters=args.iters,
+                    command="python -m paper_2601_00551_amd.proposal " + " ".join(argv or sys.argv[1:]))
+        with open(args.save_weights[:-4] + ".json", "w") as fh:
+            json.dump(meta, fh, indent=1)
     if args.out:
         with open(args.out, "w") as fh:
-            json.dump(dict(rows=rows, summary=summary), fh, indent=1)
+            json.dump(dict(rows=res["rows"], summary=summary), fh, indent=1)
     return 0
 
 
