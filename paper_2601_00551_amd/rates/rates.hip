@@ -125,6 +125,40 @@ __global__ __launch_bounds__(256) void k_lds_pattern(unsigned long long *out, in
     atomicAdd(out, s);
 }
 
+// 64-bit adds at random entries done as a returning 32-bit add to the low
+// word and, where it wrapped, a 32-bit add of the carry to the high word (the
+// sum is the same 64-bit integer).  Values are uniform below 2^VBITS, so a
+// carry follows about 2^(VBITS-33) of the adds once the low words are busy;
+// eight adds are issued before their carries are checked.
+template <int VBITS>
+__global__ __launch_bounds__(256) void k_lds_split(unsigned long long *out, int iters) {
+    __shared__ unsigned int row[2 * 4096];
+    for (int i = threadIdx.x; i < 2 * 4096; i += blockDim.x) row[i] = 0u;
+    __syncthreads();
+    uint32_t h = (blockIdx.x * 256u + threadIdx.x) * 2654435761u + 12345u;
+    uint32_t g = (blockIdx.x * 256u + threadIdx.x) * 2246822519u + 777u;
+    for (int i = 0; i < iters; ++i) {
+        uint32_t idx[8], v[8], old[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            h = h * 1664525u + 1013904223u;
+            g = g * 22695477u + 1u;
+            idx[r] = (h >> 16) & 4095u;
+            v[r] = g >> (32 - VBITS);
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r) old[r] = atomicAdd(&row[2 * idx[r]], v[r]);
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+            if (old[r] + v[r] < old[r]) atomicAdd(&row[2 * idx[r] + 1], 1u);
+    }
+    __syncthreads();
+    unsigned long long s = 0;
+    for (int i = threadIdx.x; i < 4096; i += blockDim.x)
+        s += ((unsigned long long)row[2 * i + 1] << 32) | row[2 * i];
+    atomicAdd(out, s);
+}
+
 // Aligned random reads of W dwords per lane (the row holds 4096 dwords).
 template <int W>
 __global__ __launch_bounds__(256) void k_lds_wide(unsigned long long *out, int iters) {
@@ -193,6 +227,9 @@ int main() {
     if (run("lds_add_u32_random", [&] { hipLaunchKernelGGL((k_lds<unsigned int, false>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_u64_consecutive", [&] { hipLaunchKernelGGL((k_lds_pattern<unsigned long long, PAT_CONSEC>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_u64_four_lanes_per_entry", [&] { hipLaunchKernelGGL((k_lds_pattern<unsigned long long, PAT_CLUSTER4>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
+    if (run("lds_add_u64_as_u32_carry_v22", [&] { hipLaunchKernelGGL(k_lds_split<22>, dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
+    if (run("lds_add_u64_as_u32_carry_v26", [&] { hipLaunchKernelGGL(k_lds_split<26>, dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
+    if (run("lds_add_u64_as_u32_carry_v29", [&] { hipLaunchKernelGGL(k_lds_split<29>, dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_u32_consecutive", [&] { hipLaunchKernelGGL((k_lds_pattern<unsigned int, PAT_CONSEC>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_f64_random", [&] { hipLaunchKernelGGL((k_lds<double, false>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_f64_consecutive", [&] { hipLaunchKernelGGL((k_lds_pattern<double, PAT_CONSEC>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
