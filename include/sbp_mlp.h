@@ -124,6 +124,28 @@ int sbp_features(sbp_ctx *ctx, const sbp_grid *grid, const float *mass, const sb
 int sbp_append_proposals(sbp_ctx *ctx, sbp_state *state, const sbp_balls *sites, const float *out,
                          int64_t M, float a_init, float p0_scale, int64_t *count, void *stream);
 
+/* The proposals of every frame of a multi-frame state, merged into a new
+ * state.  The candidate sites of all frames are back to back: frame f owns
+ * sites [site_off[f], site_off[f+1]) (site_off: device, F+1 int64, ascending,
+ * site_off[F] = M_total), with network outputs out[m][0..1].  Site m of frame
+ * f is accepted when out[m][0] > 0 and p0_scale[f] > 0 (p0_scale: device, F
+ * floats; 0 leaves frame f as it is).  out_state receives, frame by frame, the
+ * balls of `in` in order with their gradients and moments (zeros where `in`
+ * has no such array; arrays of out_state that are NULL are skipped), then the
+ * frame's accepted sites in site order with x, y, z = the site, p0 =
+ * max(out[m][1], 0) * p0_scale[f], a = a_init and zero gradients and moments;
+ * out_state->ball_off gets the new offsets and *count (host) the new total
+ * (the call synchronises `stream`).  `in` and out_state must not share
+ * arrays.  An `in` with no balls (B_cap = 0, offsets all zero) gives the
+ * proposals alone.
+ * Errors: SBP_E_ARG (NULL, M_total < 0, F outside [1, SBP_MAX_FRAMES] or
+ * different in the two states), SBP_E_DOMAIN (a_init <= 0), SBP_E_CAPACITY
+ * (more than out_state->B_cap balls; out_state unchanged). */
+int sbp_merge_proposals(sbp_ctx *ctx, const sbp_state *in, const sbp_balls *sites,
+                        const int64_t *site_off, const float *out, int64_t M_total,
+                        const float *p0_scale, float a_init, sbp_state *out_state, int64_t *count,
+                        void *stream);
+
 #ifdef __cplusplus
 }
 #endif

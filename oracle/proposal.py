@@ -102,3 +102,38 @@ def append(balls, sites, out, a_init, p0_scale=1.0):
     new = {"x": sites[acc, 0], "y": sites[acc, 1], "z": sites[acc, 2],
            "p0": np.maximum(out[acc, 1], 0.0) * p0_scale, "a": np.full(int(acc.sum()), float(a_init))}
     return {k: np.concatenate([np.asarray(balls[k], np.float64), new[k]]) for k in new}
+
+
+def merge(balls, ball_off, sites, site_off, out, p0_scale, a_init, extra=None):
+    """Per frame: the frame's balls in order, then its accepted sites in site
+    order (logit > 0 and the frame's p0_scale > 0) with p0 = max(predicted p0,
+    0) * p0_scale[f] and size a_init.  `extra` maps names (gradients, moments)
+    to per-ball arrays carried with their balls; the new balls get zeros.
+    Returns (balls, ball_off, extra) of the merged state."""
+    out = np.asarray(out, np.float64)
+    sites = np.asarray(sites, np.float64)
+    F = len(ball_off) - 1
+    keys = ("x", "y", "z", "p0", "a")
+    extra = extra or {}
+    nb = {k: [] for k in keys}
+    ne = {k: [] for k in extra}
+    off = [0]
+    for f in range(F):
+        lo, hi = int(ball_off[f]), int(ball_off[f + 1])
+        for k in keys:
+            nb[k].append(np.asarray(balls[k][lo:hi], np.float64))
+        for k in extra:
+            ne[k].append(np.asarray(extra[k][lo:hi], np.float64))
+        s0, s1 = int(site_off[f]), int(site_off[f + 1])
+        acc = (out[s0:s1, 0] > 0) & (p0_scale[f] > 0)
+        n = int(acc.sum())
+        nb["x"].append(sites[s0:s1, 0][acc])
+        nb["y"].append(sites[s0:s1, 1][acc])
+        nb["z"].append(sites[s0:s1, 2][acc])
+        nb["p0"].append(np.maximum(out[s0:s1, 1][acc], 0.0) * p0_scale[f])
+        nb["a"].append(np.full(n, float(a_init)))
+        for k in extra:
+            ne[k].append(np.zeros(n))
+        off.append(off[-1] + (hi - lo) + n)
+    return ({k: np.concatenate(v) for k, v in nb.items()}, np.array(off, np.int64),
+            {k: np.concatenate(v) for k, v in ne.items()})

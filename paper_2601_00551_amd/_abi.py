@@ -131,6 +131,7 @@ SIGNATURES = {
     "sbp_candidates": (ctypes.c_int, [P, PGr, P, F32, F32, PB, I64, ctypes.POINTER(I64), P]),
     "sbp_features": (ctypes.c_int, [P, PGr, P, PB, I64, PB, F32, P, P]),
     "sbp_append_proposals": (ctypes.c_int, [P, PS, PB, P, I64, F32, F32, ctypes.POINTER(I64), P]),
+    "sbp_merge_proposals": (ctypes.c_int, [P, PS, PB, P, P, I64, P, F32, PS, ctypes.POINTER(I64), P]),
     # sbp_image.h
     "sbp_voxelize": (ctypes.c_int, [P, PB, P, I64, PM, PGr, P, P]),
     "sbp_image_metrics": (ctypes.c_int, [P, P, P, I32, I32, I32, F32, P, P, P]),

@@ -216,6 +216,110 @@ __global__ void k_bump_count(int64_t *off, const int64_t *__restrict__ pre, int 
     if (threadIdx.x == 0 && blockIdx.x == 0) off[1] += pre[nblk];
 }
 
+// ------------------------------------------------ merge into a new state --
+struct MergePred {
+    const float *out;
+    const int64_t *site_off;
+    const float *scale;
+    int F;
+    __device__ bool operator()(int64_t m) const {
+        return out[2 * m] > 0.0f && scale[frame_of(site_off, F, m)] > 0.0f;
+    }
+};
+
+// Rank of the flagged sites below index t: the block's prefix plus the flags
+// of its earlier elements (t may equal n: the total).
+__device__ inline int64_t rank_below(const MergePred &p, int64_t n, const int64_t *pre, int64_t t) {
+    const int64_t blk = t / kPb;
+    int64_t r = pre[blk];
+    for (int64_t u = blk * kPb; u < t && u < n; ++u) r += p(u) ? 1 : 0;
+    return r;
+}
+
+// One workgroup: per frame the rank of its first site (racc[f]) and the new
+// offsets off_out[f] = sum over g < f of (balls of g + accepted sites of g).
+__global__ void k_merge_offsets(MergePred p, int64_t n, const int64_t *__restrict__ pre,
+                                const int64_t *__restrict__ off_in, int64_t *__restrict__ racc,
+                                int64_t *__restrict__ off_out) {
+    const int F = p.F;
+    for (int f = threadIdx.x; f <= F; f += blockDim.x) racc[f] = rank_below(p, n, pre, p.site_off[f]);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t o = 0;
+        off_out[0] = 0;
+        for (int f = 0; f < F; ++f) {
+            o += (off_in[f + 1] - off_in[f]) + (racc[f + 1] - racc[f]);
+            off_out[f + 1] = o;
+        }
+    }
+}
+
+__device__ inline void copy_or_zero(float *dst, const float *src, int64_t o, int64_t i) {
+    if (dst) dst[o] = src ? src[i] : 0.0f;
+}
+
+// The existing balls, frame by frame, to their new places (with gradients and
+// moments where both sides have them).
+__global__ void k_merge_balls(sbp_state in, const int64_t *__restrict__ off_out, sbp_state out) {
+    __shared__ int64_t s_in[SBP_MAX_FRAMES + 1], s_out[SBP_MAX_FRAMES + 1];
+    const int F = in.F;
+    for (int f = threadIdx.x; f <= F; f += blockDim.x) {
+        s_in[f] = in.ball_off[f];
+        s_out[f] = off_out[f];
+    }
+    __syncthreads();
+    for (int64_t i = s_in[0] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < s_in[F];
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int f = frame_of(s_in, F, i);
+        const int64_t o = s_out[f] + (i - s_in[f]);
+        out.balls.x[o] = in.balls.x[i];
+        out.balls.y[o] = in.balls.y[i];
+        out.balls.z[o] = in.balls.z[i];
+        out.balls.p0[o] = in.balls.p0[i];
+        out.balls.a[o] = in.balls.a[i];
+        copy_or_zero(out.grad.x, in.grad.x, o, i);
+        copy_or_zero(out.grad.y, in.grad.y, o, i);
+        copy_or_zero(out.grad.z, in.grad.z, o, i);
+        copy_or_zero(out.grad.p0, in.grad.p0, o, i);
+        copy_or_zero(out.grad.a, in.grad.a, o, i);
+        copy_or_zero(out.m.x, in.m.x, o, i);
+        copy_or_zero(out.m.y, in.m.y, o, i);
+        copy_or_zero(out.m.z, in.m.z, o, i);
+        copy_or_zero(out.m.p0, in.m.p0, o, i);
+        copy_or_zero(out.m.a, in.m.a, o, i);
+        copy_or_zero(out.v.x, in.v.x, o, i);
+        copy_or_zero(out.v.y, in.v.y, o, i);
+        copy_or_zero(out.v.z, in.v.z, o, i);
+        copy_or_zero(out.v.p0, in.v.p0, o, i);
+        copy_or_zero(out.v.a, in.v.a, o, i);
+    }
+}
+
+// The accepted sites after their frame's balls, in site order.
+__global__ void k_merge_sites(int64_t n, MergePred p, const int64_t *__restrict__ pre,
+                              const int64_t *__restrict__ racc, const int64_t *__restrict__ off_in,
+                              const int64_t *__restrict__ off_out, BallsP<float> site, float a_init,
+                              sbp_state out) {
+    __shared__ int s_wave[kPb / 64];
+    const int64_t m = (int64_t)blockIdx.x * kPb + threadIdx.x;
+    const bool fl = m < n && p(m);
+    const int64_t r = flag_rank(fl, pre, s_wave);
+    if (!fl) return;
+    const int f = frame_of(p.site_off, p.F, m);
+    const int64_t o = off_out[f] + (off_in[f + 1] - off_in[f]) + (r - racc[f]);
+    out.balls.x[o] = site.x[m];
+    out.balls.y[o] = site.y[m];
+    out.balls.z[o] = site.z[m];
+    out.balls.p0[o] = fmaxf(p.out[2 * m + 1], 0.0f) * p.scale[f];
+    out.balls.a[o] = a_init;
+    float *zero[15] = {out.grad.x, out.grad.y, out.grad.z, out.grad.p0, out.grad.a,
+                       out.m.x,    out.m.y,    out.m.z,    out.m.p0,    out.m.a,
+                       out.v.x,    out.v.y,    out.v.z,    out.v.p0,    out.v.a};
+#pragma unroll
+    for (int k = 0; k < 15; ++k)
+        if (zero[k]) zero[k][o] = 0.0f;
+}
+
 }  // namespace sbp
 
 using namespace sbp;
@@ -307,6 +411,67 @@ int sbp_features(sbp_ctx *ctx, const sbp_grid *grid, const float *mass, const sb
     hipLaunchKernelGGL(k_features, dim3((unsigned)nb), dim3(kPb), 0, st, gd(grid), mass,
                        BallsP<float>{sites->x, sites->y, sites->z, nullptr, nullptr}, M, g->p0, g->x, g->y,
                        g->z, half, scales, X);
+    SBP_HIP(hipGetLastError());
+    return SBP_OK;
+}
+
+int sbp_merge_proposals(sbp_ctx *ctx, const sbp_state *in, const sbp_balls *sites,
+                        const int64_t *site_off, const float *out, int64_t M_total,
+                        const float *p0_scale, float a_init, sbp_state *out_state, int64_t *count,
+                        void *stream) {
+    if (!in || !out_state || !count || !sites || !site_off || !p0_scale || (M_total > 0 && !out))
+        return fail(SBP_E_ARG, "a required pointer is NULL");
+    if (M_total < 0) return fail(SBP_E_ARG, "M_total must be >= 0");
+    if (in->F < 1 || in->F > SBP_MAX_FRAMES || out_state->F != in->F)
+        return fail(SBP_E_ARG, "F must be in [1, %d] and equal in both states", SBP_MAX_FRAMES);
+    if (!in->ball_off || !out_state->ball_off) return fail(SBP_E_ARG, "ball_off is NULL");
+    if (in->B_cap < 0 || out_state->B_cap < 0) return fail(SBP_E_ARG, "B_cap must be >= 0");
+    if (in->B_cap > 0 && !soa_ok(&in->balls, true)) return fail(SBP_E_ARG, "in.balls has a NULL array");
+    if (out_state->B_cap > 0 && !soa_ok(&out_state->balls, true))
+        return fail(SBP_E_ARG, "out_state.balls has a NULL array");
+    if (M_total > 0 && !soa_ok(sites, false)) return fail(SBP_E_ARG, "sites has a NULL array");
+    if (!(a_init > 0.0f)) return fail(SBP_E_DOMAIN, "a_init must be > 0");
+    if (!ctx) return fail(SBP_E_ARG, "ctx is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const int F = in->F;
+    const int64_t nblk64 = (M_total + kPb - 1) / kPb;
+    if (nblk64 > INT32_MAX / 2) return fail(SBP_E_ARG, "too many sites");
+    const int nblk = (int)nblk64;
+    // scratch: [block counts][block prefix][rank of each frame's first site][new offsets]
+    const size_t off_pre = ((size_t)(nblk + 1) * sizeof(int) + 255) & ~(size_t)255;
+    const size_t off_racc = off_pre + (((size_t)(nblk + 2) * sizeof(int64_t) + 255) & ~(size_t)255);
+    const size_t off_new = off_racc + 1024;
+    int rc = ensure_scratch(&ctx->c, off_new + 1024);
+    if (rc) return rc;
+    char *sc = (char *)ctx->c.scratch;
+    int *cnt = (int *)sc;
+    int64_t *pre = (int64_t *)(sc + off_pre);
+    int64_t *racc = (int64_t *)(sc + off_racc);
+    int64_t *noff = (int64_t *)(sc + off_new);
+    MergePred p{out, site_off, p0_scale, F};
+    if (nblk > 0) hipLaunchKernelGGL(k_flag_count<MergePred>, dim3(nblk), dim3(kPb), 0, st, M_total, p, cnt);
+    hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, st, cnt, nblk, pre);
+    hipLaunchKernelGGL(k_merge_offsets, dim3(1), dim3(64), 0, st, p, M_total, pre, in->ball_off, racc, noff);
+    SBP_HIP(hipGetLastError());
+    int64_t total = 0;
+    SBP_HIP(hipMemcpyAsync(&total, noff + F, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    SBP_HIP(hipStreamSynchronize(st));
+    *count = total;
+    if (total > out_state->B_cap)
+        return fail(SBP_E_CAPACITY, "%lld balls after merging, capacity %lld", (long long)total,
+                    (long long)out_state->B_cap);
+    SBP_HIP(hipMemcpyAsync(out_state->ball_off, noff, (size_t)(F + 1) * sizeof(int64_t),
+                           hipMemcpyDeviceToDevice, st));
+    if (in->B_cap > 0) {
+        int64_t nb = (in->B_cap + kPb - 1) / kPb;
+        if (nb > 4096) nb = 4096;
+        hipLaunchKernelGGL(k_merge_balls, dim3((unsigned)nb), dim3(kPb), 0, st, *in, noff, *out_state);
+    }
+    if (nblk > 0)
+        hipLaunchKernelGGL(k_merge_sites, dim3(nblk), dim3(kPb), 0, st, M_total, p, pre, racc,
+                           in->ball_off, noff,
+                           BallsP<float>{sites->x, sites->y, sites->z, nullptr, nullptr}, a_init,
+                           *out_state);
     SBP_HIP(hipGetLastError());
     return SBP_OK;
 }

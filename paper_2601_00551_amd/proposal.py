@@ -241,6 +241,28 @@ def append_proposals(ctx, state: api.State, sites, out, M, a_init, p0_scale=1.0,
     return cnt.value
 
 
+def merge_proposals(ctx, state: api.State, sites, site_off, out, p0_scale, a_init, out_state=None,
+                    capacity=None, stream=None):
+    """sbp_merge_proposals: a new state holding every frame's balls followed by
+    its accepted sites (site_off: device int64 [F+1], p0_scale: device float [F])."""
+    F = state.F
+    _exactly(_need(site_off, torch.int64, "site_off"), F + 1, "site_off")
+    _exactly(_need(p0_scale, name="p0_scale"), F, "p0_scale")
+    M = int(site_off[-1].item())
+    _check_balls(sites, M, "sites")
+    if M > 0:
+        _at_least(_need(out, name="out"), 2 * M, "out")
+    if out_state is None:
+        cap = int(capacity if capacity is not None else state.B_cap + M)
+        out_state = api.State({k: np.zeros(0) for k in PARAMS}, ball_off=[0] * (F + 1), capacity=cap,
+                              device=state.ball_off.device)
+    cnt = ctypes.c_int64()
+    check(lib().sbp_merge_proposals(ctx.ptr, ctypes.byref(state.struct()), ctypes.byref(balls_struct(sites)),
+                                    _p(site_off), _p(out) if M > 0 else None, M, _p(p0_scale), float(a_init),
+                                    ctypes.byref(out_state.struct()), ctypes.byref(cnt), _stream(stream)))
+    return out_state, cnt.value
+
+
 class FeatureBuilder:
     """Candidate sites and their features for one state, reusing its buffers."""
 
@@ -270,6 +292,48 @@ def _residual(r: recon.Recon, model, y_k, yw):
     st = r.state
     api.simulate_signals(r.ctx, r.A, st.balls, model, ball_off=st.ball_off, y=yw, B_cap=st.B_cap)
     return float(api.residual_loss(r.ctx, yw, y_k, v_out=yw).sum().item())
+
+
+class FrameFeatureBuilder(FeatureBuilder):
+    """Candidate sites and features of every frame of a state, back to back
+    (frame f's rows from site_off[f]), for the multi-frame proposer."""
+
+    def __init__(self, ctx, grid: Grid, occ=0.1, a_probe=0.1, half=10.0, device="cuda:0"):
+        super().__init__(ctx, grid, occ, a_probe, half, device)
+        self.cap = 0
+        self.all_sites = self.all_g = self.X = None
+
+    def _grow_to(self, n):
+        if n <= self.cap:
+            return
+        dev = self.mass.device
+        self.all_sites = {k: torch.empty(n, dtype=torch.float32, device=dev) for k in PARAMS}
+        self.all_g = {k: torch.empty(n, dtype=torch.float32, device=dev) for k in PARAMS}
+        self.X = torch.empty((n, MLP_IN), dtype=torch.float32, device=dev)
+        self.cap = n
+
+    def build_frames(self, A, state: api.State, model: api.Model, v):
+        """(M_total, X [M_total][31], sites, site_off device [F+1]) given
+        v [F][D][T] = dL/dy_sim of the current state."""
+        F = state.F
+        nc = self.grid.ncell
+        self._grow_to(F * nc)
+        probe_model = dataclasses.replace(model, a_softplus=0)
+        offs = [0]
+        for f in range(F):
+            o = offs[-1]
+            grid_mass(self.ctx, state.balls, state.ball_off[f:], self.grid, B_cap=state.B_cap, mass=self.mass)
+            view = {k: self.all_sites[k][o:o + nc] for k in PARAMS}
+            _, M = candidates(self.ctx, self.grid, self.mass, self.occ, self.a_probe, sites=view)
+            if M > 0:
+                self.off[1] = M
+                gv = {k: self.all_g[k][o:o + M] for k in PARAMS}
+                api.adjoint_gradients(self.ctx, A, {k: view[k][:M] for k in PARAMS}, probe_model,
+                                      v[f:f + 1], mask=P0 | XYZ, ball_off=self.off, grad=gv, B_cap=M)
+                features(self.ctx, self.grid, self.mass, view, M, gv, self.half, X=self.X[o:o + M])
+            offs.append(o + M)
+        site_off = torch.tensor(offs, dtype=torch.int64, device=self.mass.device)
+        return offs[-1], self.X[:offs[-1]], self.all_sites, site_off
 
 
 class Recorder:
@@ -354,10 +418,69 @@ class LearnedProposer:
             self.closed_at_run = self.runs
             ev["gate_closed"] = True
 
+    def _frame_losses(self, r, model, state, y_k, yw):
+        api.simulate_signals(r.ctx, r.A, state.balls, model, ball_off=state.ball_off, y=yw, B_cap=state.B_cap)
+        return api.residual_loss(r.ctx, yw, y_k, v_out=yw).cpu().numpy()
+
+    def _propose_frames(self, r, model, y_k, yw, ev):
+        """Every frame at once: candidate sites and features per frame, one
+        network pass over all of them, then per frame the exact line search
+        along its proposals and the loss judge; the accepted proposals of all
+        frames are merged into a new state (sbp_merge_proposals)."""
+        st = r.state
+        F = st.F
+        dev = yw.device
+        L0 = self._frame_losses(r, model, st, y_k, yw)          # yw = dL/dy_sim now
+        ev.update(loss_before=float(L0.sum()), loss_after=float(L0.sum()))
+        if not isinstance(self.builder, FrameFeatureBuilder):
+            b = self.builder
+            self.builder = FrameFeatureBuilder(r.ctx, b.grid, b.occ, b.a_probe, b.half, device=dev)
+        M, X, sites, site_off = self.builder.build_frames(r.A, st, model, yw)
+        ev["candidates"] = M
+        if M == 0:
+            return
+        out = self.mlp.forward(X)
+        ones = torch.ones(F, dtype=torch.float32, device=dev)
+        empty = api.State({k: np.zeros(0) for k in PARAMS}, ball_off=[0] * (F + 1), capacity=0, device=dev)
+        P, nP = merge_proposals(r.ctx, empty, sites, site_off, out, ones, self.a_init, capacity=M)
+        ev["accepted"] = nP
+        if nP == 0:
+            return
+        if self._ys is None or self._ys.shape != yw.shape:
+            self._zero = torch.zeros_like(yw)
+            self._ys = torch.empty_like(yw)
+        api.simulate_signals(r.ctx, r.A, P.balls, model, ball_off=P.ball_off, y=self._ys, B_cap=P.B_cap)
+        Ls = api.residual_loss(r.ctx, self._ys, self._zero).cpu().numpy()
+        T1, _ = merge_proposals(r.ctx, st, sites, site_off, out, ones, self.a_init, capacity=st.count() + nP)
+        L1 = self._frame_losses(r, model, T1, y_k, yw)
+        es = 0.5 * (L1 - L0 - Ls)
+        alpha = np.where((Ls > 0.0) & (es < 0.0), np.minimum(-es / np.where(Ls > 0, Ls, 1.0), self.max_scale),
+                         0.0).astype(np.float32)
+        for _ in range(2):           # the judge: frames whose loss did not fall get no proposals
+            if not np.any(alpha > 0):
+                return
+            try:
+                new, _ = merge_proposals(r.ctx, st, sites, site_off, out, torch.as_tensor(alpha, device=dev),
+                                         self.a_init, capacity=r.cap)
+            except _abi.SbpError as e:
+                if e.code != _abi.SBP_E_CAPACITY:
+                    raise
+                return
+            L2 = self._frame_losses(r, model, new, y_k, yw)
+            bad = (alpha > 0) & ~(L2 < L0) if self.judge else np.zeros(F, bool)
+            if not np.any(bad):
+                break
+            alpha[bad] = 0.0
+        else:
+            return
+        r.state = new
+        ev.update(scale=float(alpha.max()), loss_after=float(L2.sum()), frames_kept=int((alpha > 0).sum()))
+        ev["kept"] = True
+
     def _propose(self, r, model, y_k, yw, ev):
         st = r.state
         if st.F != 1:
-            raise ValueError("the learned proposal works on single-frame states")
+            return self._propose_frames(r, model, y_k, yw, ev)
         L0 = _residual(r, model, y_k, yw)
         ev.update(loss_before=L0, loss_after=L0)
         M, X, sites = self.builder.build(r.A, st, model, yw)
@@ -601,6 +724,65 @@ def compare(ctx, mlp, stages, grid, evals, n_init, when=(0,), max_per_stage=None
                 heldout_positives=float(np.mean(Lb)) if len(Lb) else None)
 
 
+def frames_workload(index=0, n_frames=16, lo=100_000, hi=2_000_000):
+    """The batched workload: frames of the conformal workload's array whose
+    phantom is shifted within 1 mm and rescaled per frame, with per-frame
+    initial clouds log-uniform in [lo, hi] balls."""
+    base = synth.conformal_config(seed_index=index)
+    gts, inits = synth.batched_frames(base, n_frames, seed_index=index, lo=lo, hi=hi)
+    return base, gts, inits
+
+
+def frames_measurement(ctx, base, gts, noise=0.05, seed=0, device="cuda:0"):
+    dev = torch.device(device)
+    A = {k: torch.as_tensor(v, device=dev) for k, v in base.array.items()}
+    model = api.Model(c=synth.C, dt=base.dt, T=base.T, f=1)
+    ys = [api.simulate_signals(ctx, A, {k: torch.as_tensor(v, device=dev) for k, v in g.items()}, model)[0]
+          for g in gts]
+    y = torch.stack(ys)
+    if noise > 0:
+        rng = np.random.default_rng(seed)
+        sigma = noise * float(y.abs().max())
+        y = y + sigma * torch.as_tensor(rng.normal(size=tuple(y.shape)).astype(np.float32), device=dev)
+    return y.contiguous()
+
+
+def frames_run(ctx, base, y, inits, stages, proposer=None, stop_below=None, graph_iters=0):
+    balls = synth.concat_balls(inits)
+    off = np.cumsum([0] + [len(b["x"]) for b in inits]).tolist()
+    cfg = recon.ReconConfig(stages=stages, T=base.T, dt=base.dt, dup_frac=0.05, capacity=2 * off[-1],
+                            graph_iters=graph_iters)
+    r = recon.Recon(base.array, y, balls, cfg, ball_off=off, ctx=ctx)
+    r.proposer = proposer
+    return r, r.run(stop_below=stop_below)
+
+
+def compare_frames(ctx, mlp, stages, grid, n_frames=16, lo=100_000, hi=2_000_000, index=0, when=(0,),
+                   patience=1, graph_iters=0, log=print):
+    """Learned + batched against plain batched: wall time of one batched
+    reconstruction (all frames in every call) to the plain run's final loss
+    summed over the frames."""
+    base, gts, inits = frames_workload(index, n_frames, lo, hi)
+    y = frames_measurement(ctx, base, gts, seed=80_000 + index)
+    _, plain = frames_run(ctx, base, y, inits, stages, graph_iters=graph_iters)
+    target = plain["final_loss"] * (1.0 + 1e-3)
+    _, plain2 = frames_run(ctx, base, y, inits, stages, stop_below=target, graph_iters=graph_iters)
+    lp = LearnedProposer(mlp, FeatureBuilder(ctx, grid, a_probe=0.1, half=-grid.ox), a_init=base.a_init,
+                         stages=list(when) if when else None, patience=patience)
+    lp.new_run()
+    _, learned = frames_run(ctx, base, y, inits, stages, proposer=lp, stop_below=target, graph_iters=graph_iters)
+    row = dict(event="compare-frames", frames=n_frames, balls=int(sum(len(b["x"]) for b in inits)),
+               plain_s=plain2["t_target"] or plain2["wall_s"], plain_reached=plain2["t_target"] is not None,
+               plain_final_loss=plain["final_loss"], learned_s=learned["t_target"] or learned["wall_s"],
+               learned_reached=learned["t_target"] is not None, learned_final_loss=learned["final_loss"],
+               proposals_tried=len(lp.events), proposals_kept=sum(e["kept"] for e in lp.events),
+               frames_kept=[e.get("frames_kept", 0) for e in lp.events], gate_closed=lp.gated,
+               proposal_s=sum(e.get("seconds", 0.0) for e in lp.events))
+    row["speedup"] = row["plain_s"] / row["learned_s"]
+    log(json.dumps(row), flush=True)
+    return row
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description="Train the growth-proposal network on plain runs and "
                                              "compare wall time to the plain final residual.")
@@ -625,6 +807,11 @@ def main(argv=None):
     ap.add_argument("--max-per-stage", type=int, default=None)
     ap.add_argument("--graph-iters", type=int, default=0,
                     help="iterations per captured HIP graph in the timed runs")
+    ap.add_argument("--frames", type=int, default=0,
+                    help="compare learned + batched against plain batched on this many frames of the "
+                         "batched workload instead (with --load-weights)")
+    ap.add_argument("--frame-balls", default="100000,2000000",
+                    help="lo,hi of the per-frame initial cloud (log-uniform) for --frames")
     ap.add_argument("--load-weights", default=None, help="skip training: use these weights")
     ap.add_argument("--save-weights", default=None, help="write the trained weights (BF16) here")
     ap.add_argument("--out", default=None)
@@ -652,6 +839,15 @@ def main(argv=None):
         if args.save_weights:
             mlp.save(args.save_weights, bf16=True)
     when = [int(v) for v in args.when.split(",") if v != ""] or None
+    if args.frames > 0:
+        lo, hi = (int(v) for v in args.frame_balls.split(","))
+        rows = [compare_frames(ctx, mlp, stages, grid, args.frames, lo, hi, index=j, when=when,
+                               patience=args.patience or None, graph_iters=args.graph_iters)
+                for j in range(max(args.eval, 1))]
+        if args.out:
+            with open(args.out, "w") as fh:
+                json.dump(dict(rows=rows), fh, indent=1)
+        return 0
     res = compare(ctx, mlp, stages, grid, args.eval, args.n_init, when=when,
                   max_per_stage=args.max_per_stage, patience=args.patience or None,
                   reprobe_every=args.reprobe_every or None, graph_iters=args.graph_iters,
