@@ -350,3 +350,36 @@ def test_response_apply_validation(args, code):
                                        a["D"], a["T"], a["adjoint"], a["accumulate"], a["out"], None)
     assert rc == code
     assert last()
+
+
+# -------------------------------------------------- multi-frame proposals --
+
+def _state_struct(F=2, cap=10, null_off=False):
+    b = _balls()
+    return _abi.SbpState(b, _abi.SbpBalls(), _abi.SbpBalls(), _abi.SbpBalls(), None if null_off else FAKE.value,
+                         F, 0, cap)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(site_off=None), _abi.SBP_E_ARG),
+    (dict(scale=None), _abi.SBP_E_ARG),
+    (dict(M=-1), _abi.SBP_E_ARG),
+    (dict(out=None), _abi.SBP_E_ARG),                     # M > 0 needs the outputs
+    (dict(in_F=0), _abi.SBP_E_ARG),
+    (dict(in_F=65, out_F=65), _abi.SBP_E_ARG),
+    (dict(out_F=3), _abi.SBP_E_ARG),                      # frame counts differ
+    (dict(null_off=True), _abi.SBP_E_ARG),
+    (dict(a_init=0.0), _abi.SBP_E_DOMAIN),
+    (dict(), _abi.SBP_E_ARG),                             # valid but the NULL context
+])
+def test_merge_proposals_validation(kw, code):
+    a = dict(site_off=FAKE, scale=FAKE, M=5, out=FAKE, in_F=2, out_F=2, null_off=False, a_init=0.1)
+    a.update(kw)
+    s_in = _state_struct(a["in_F"], null_off=a["null_off"])
+    s_out = _state_struct(a["out_F"])
+    cnt = ctypes.c_int64()
+    rc = _abi.lib().sbp_merge_proposals(None, ctypes.byref(s_in), ctypes.byref(_balls()), a["site_off"],
+                                        a["out"], a["M"], a["scale"], a["a_init"], ctypes.byref(s_out),
+                                        ctypes.byref(cnt), None)
+    assert rc == code
+    assert last()
