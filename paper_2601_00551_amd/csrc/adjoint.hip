@@ -39,10 +39,11 @@ template <typename R> __device__ __forceinline__ R ld_uniform(const R *p) {
 // The values are the same either way.
 //
 // kStageU, the quads in flight per thread: four covers a 4096-sample row in
-// one round with 256 threads; the point-sampled OMNI gradient kernel takes
-// three, the most that keeps its pass loop free of register spills.
+// one round with 256 threads; the point-sampled OMNI and the UNIFORM / COS
+// all-gradient kernels take three, which keeps them free of register spills
+// at four waves per SIMD.
 template <int PROF, int DIR, bool FULL> struct StageDepth {
-    static constexpr int v = (PROF == GPOINT && DIR == OMNI && FULL) ? 3 : 4;
+    static constexpr int v = (FULL && ((PROF == GPOINT && DIR == OMNI) || (PROF == UNIFORM && DIR == COS))) ? 3 : 4;
 };
 
 template <typename R, bool DIFF>
@@ -151,11 +152,11 @@ __host__ __device__ inline int adj_row_stride(int TT) { return (TT + 3) & ~3; }
 // FP32 kernels hold up to kMaxBpt = 3 balls per lane in 128 VGPRs (four
 // waves); the FP64 twin, a correctness path, gets 256 (two waves).
 template <typename R, int PROF, int DIR, bool FULL> struct AdjMinBlocks {
-    // all-gradient GAUSS / OMNI and UNIFORM / COS need a few registers more
-    // than four waves per SIMD leave them: three waves rather than spilling
+    // all-gradient GAUSS / OMNI needs more registers than four waves per SIMD
+    // leave it: three waves rather than spilling (UNIFORM / COS fits four with
+    // a staging depth of three)
     static constexpr int v = sizeof(R) == sizeof(double) ? 2
-                             : (FULL && ((PROF == GAUSS && DIR == OMNI) || (PROF == UNIFORM && DIR == COS))) ? 3
-                                                                                                              : 4;
+                             : (FULL && PROF == GAUSS && DIR == OMNI) ? 3 : 4;
 };
 
 template <typename R, int PROF, int DIR, bool FULL>

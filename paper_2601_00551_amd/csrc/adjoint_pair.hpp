@@ -194,7 +194,9 @@ SBP_HD inline void adj_pair(const BallK<R, PROF> &b, R qx, R qy, R qz, R nx, R n
         S2 = R(-2) * b.a * A0 - A2 / b.a;
     } else {
         W = P;
-        S0 = R(-0.5) * (b.q0 * W - A2);                  // -(1/2) sum w (a^2 - u^2)
+        // -(1/2) sum w (a^2 - u^2); a^2 formed here (the same product as
+        // b.q0) so that b.q0 is not held per ball across the transducers
+        S0 = R(-0.5) * ((b.a * b.a) * W - A2);
         S1 = A1;
         S2 = -b.a * W;
     }
