@@ -493,11 +493,11 @@ __global__ __launch_bounds__(512, 4) void k_forward(ArrayP<R> arr, BallsP<R> bal
 // which is >= 0 for p0 >= 0.  The values are rounded to the nearest multiple
 // of the same quantum as the bin values (|W| <= |p0| a^2 / (2 rho c dt_k),
 // below the bound since rho > K a) and summed exactly; the last pass takes the
-// differences exactly on the integers.  Per edge this is the exponent (two
-// FMAs), one exp2, one FMA, the conversion and one LDS add: two operations
-// fewer than a bin value (a difference and its sign word), and one LDS add
-// fewer per pair.  When no ball of a wave has p0 < 0 the 64-bit value needs no
-// sign word.  Each sample carries two roundings per ball instead of one.
+// differences exactly on the integers.  Per edge this is two multiplies of the
+// Gaussian's recurrence (two exp2 per four edges restart it), one FMA, the
+// conversion and one LDS add, and one LDS add fewer per pair than bin values.
+// When no ball of a wave has p0 < 0 the 64-bit value needs no sign word.  Each
+// sample carries two roundings per ball instead of one.
 //
 // The per-ball constants come from one pass over the cloud (k_fwd_prep),
 // which also takes the fixed-point bound and the non-finite flags, so the
@@ -555,34 +555,48 @@ __global__ __launch_bounds__(kPrepBlock) void k_fwd_prep(BallsP<float> balls,
     }
 }
 
-// Adds an edge value (already scaled) to an LDS row entry.  NN: the value is
-// known to be > -1/2, so its nearest integer is >= 0 and the high word is 0.
+// Adds an edge value to an LDS row entry: vh is the scaled value plus 1/2, so
+// its nearest integer is floor(vh).  NN: the value is >= 0 but for rounding
+// just inside the support edge; v_cvt_u32_f32 truncates and clamps a negative
+// input to 0, so the integer is floor(vh) >= 0 and the high word is 0.
 template <bool NN>
-__device__ inline void edge_add(unsigned long long *p, float v) {
-    int iv;
-    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(iv) : "v"(v));
-    if (NN)
-        atomicAdd(p, (unsigned long long)(unsigned)iv);
-    else
+__device__ inline void edge_add(unsigned long long *p, float vh) {
+    if (NN) {
+        unsigned iv;
+        asm("v_cvt_u32_f32 %0, %1" : "=v"(iv) : "v"(vh));
+        atomicAdd(p, (unsigned long long)iv);
+    } else {
+        int iv;
+        asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(iv) : "v"(vh));
         atomicAdd(p, (unsigned long long)(long long)iv);
+    }
 }
 
-// N consecutive inside edges from u = ub: edge k has exponent
-// q0 (ub - k c)^2 = X0 + k (X1 + k X2) and adds namp (e_k - e_K).
+// N consecutive inside edges from offset u0 (edge k at u0 - k c), adding
+// namp (e_k - e_K): the Gaussian e_k = 2^(q0 (u0 - k c)^2) by the two-multiply
+// recurrence e_{k+1} = e_k g_k, g_{k+1} = g_k h restarted here, with
+// e_0 = 2^(q0 u0^2), g_0 = 2^(q0 c (c - 2 u0)) = 2^(Y1 u0 + X2), h = 2^(2 X2).
 template <bool NN, int N>
-__device__ inline void gz_edges(unsigned long long *p, float ub, float q0, float X2, float Y1,
-                                float namp, float nampK) {
-    const float X0 = q0 * ub * ub;
-    const float X1 = Y1 * ub;
+__device__ inline void gz_edges(unsigned long long *p, float u0, float q0, float X2, float Y1,
+                                float h, float namp, float nampKh) {
+    float e = __builtin_amdgcn_exp2f(q0 * u0 * u0);
+    float g = __builtin_amdgcn_exp2f(fmaf(Y1, u0, X2));
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-        const float X = k == 0 ? X0 : fmaf((float)k, fmaf((float)k, X2, X1), X0);
-        edge_add<NN>(p + k, fmaf(namp, __builtin_amdgcn_exp2f(X), nampK));
+        edge_add<NN>(p + k, fmaf(namp, e, nampKh));
+        if (k + 1 < N) {
+            e *= g;
+            g *= h;
+        }
     }
 }
 
 // Adds the pair's inside edges that fall in the tile [tlo, thi) to
-// row[m - tlo]; `scale` is the inverse of the fixed-point quantum.
+// row[m - tlo]; `scale` is the inverse of the fixed-point quantum.  The first
+// edge's offset is formed exactly (FP64 difference, FP32 result), the later
+// restarts' offsets by one FP32 fma from it; the recurrence restarts every
+// four edges (its rounding grows with the run: about 1e-6 of a sample at 40
+// edges per pair, several times that with eight).
 template <int DIR, bool NN>
 __device__ inline void gz_pair(float bx, float by, float bz, float w, float q0, float pa2,
                                float qx, float qy, float qz, float nx, float ny, float nz,
@@ -594,29 +608,32 @@ __device__ inline void gz_pair(float bx, float by, float bz, float w, float q0, 
     const double lo = fmax(floor((g.s - (double)w) * lc.inv_cdt) + 1.0, (double)tlo);
     const double hi = fmin(floor((g.s + (double)w) * lc.inv_cdt), (double)(thi - 1));
     if (!(lo <= hi)) return;
-    int m = (int)lo;
+    const int m = (int)lo;
     int cnt = (int)hi - m + 1;
     const float namp = pa2 * g.dir * lc.inv2cdt * g.inv_rho * scale;
-    const float nampK = -namp * lc.eK;
+    const float nampKh = fmaf(-namp, lc.eK, 0.5f);
     const float c = lc.cdt_f;
     const float X2 = q0 * c * c;
     const float Y1 = -2.0f * q0 * c;
+    const float h = __builtin_amdgcn_exp2f(2.0f * X2);
+    const float u0 = (float)(g.s - (double)m * lc.cdt);
     unsigned long long *p = row - tlo + m;
-    // blocks of eight edges, the block's first offset formed exactly (FP64
-    // difference, FP32 result), then the remainder as blocks of 4, 2 and 1
-    for (; cnt >= 8; cnt -= 8, p += 8, m += 8)
-        gz_edges<NN, 8>(p, (float)(g.s - (double)m * lc.cdt), q0, X2, Y1, namp, nampK);
+    float k0 = 0.0f;
+    for (; cnt >= 8; cnt -= 8, p += 8, k0 += 8.0f) {
+        gz_edges<NN, 4>(p, fmaf(-k0, c, u0), q0, X2, Y1, h, namp, nampKh);
+        gz_edges<NN, 4>(p + 4, fmaf(-(k0 + 4.0f), c, u0), q0, X2, Y1, h, namp, nampKh);
+    }
     if (cnt & 4) {
-        gz_edges<NN, 4>(p, (float)(g.s - (double)m * lc.cdt), q0, X2, Y1, namp, nampK);
+        gz_edges<NN, 4>(p, fmaf(-k0, c, u0), q0, X2, Y1, h, namp, nampKh);
         p += 4;
-        m += 4;
+        k0 += 4.0f;
     }
     if (cnt & 2) {
-        gz_edges<NN, 2>(p, (float)(g.s - (double)m * lc.cdt), q0, X2, Y1, namp, nampK);
+        gz_edges<NN, 2>(p, fmaf(-k0, c, u0), q0, X2, Y1, h, namp, nampKh);
         p += 2;
-        m += 2;
+        k0 += 2.0f;
     }
-    if (cnt & 1) gz_edges<NN, 1>(p, (float)(g.s - (double)m * lc.cdt), q0, X2, Y1, namp, nampK);
+    if (cnt & 1) gz_edges<NN, 1>(p, fmaf(-k0, c, u0), q0, X2, Y1, h, namp, nampKh);
 }
 
 // The edge-form forward: work items and flushes as in k_forward, over edge

@@ -85,6 +85,37 @@ def test_forward_wide_dynamic_range(ctx):
     assert np.linalg.norm((y - ref)[dim_only]) <= 1.5 * rms_bound
 
 
+def near_field_scene(K=2.0, a=0.15, n_near=400):
+    """Balls just beyond the support radius of a transducer (rho from 1.02 to
+    1.5 K a along its normal), where a pair's edge values reach the top of the
+    fixed-point range, plus a uniform cloud."""
+    rng = np.random.default_rng(2121)
+    arr = synth.hemisphere_array(8, 12.0, rng)
+    q = np.stack([arr["qx"], arr["qy"], arr["qz"]], 1).astype(np.float64)
+    nrm = np.stack([arr["nx"], arr["ny"], arr["nz"]], 1).astype(np.float64)
+    d = rng.integers(0, 8, n_near)
+    r = rng.uniform(1.02, 1.5, n_near) * K * a
+    pos = q[d] + nrm[d] * r[:, None] + rng.normal(0.0, 0.005, (n_near, 3))
+    near = {"x": pos[:, 0], "y": pos[:, 1], "z": pos[:, 2], "p0": rng.uniform(0.5, 1.0, n_near),
+            "a": np.full(n_near, a)}
+    near = {k: np.asarray(v, np.float32) for k, v in near.items()}
+    return arr, synth.concat_balls([near, synth.uniform_balls(rng, 2000, 3.0, a)])
+
+
+@pytest.mark.parametrize("K", [1.0, 2.0, 5.0])
+def test_forward_near_field_small_truncation(ctx, K):
+    """A small truncation K (e_K = exp(-K^2 / 2) not small) and balls in the
+    near field: an edge value just inside the support may round to slightly
+    below zero, and with all peaks positive (64-bit values without a sign
+    word) it must add nothing rather than wrap around."""
+    arr, balls = near_field_scene(K)
+    T = 800
+    y = to_np(api.simulate_signals(ctx, to_dev(arr, dev()), to_dev(balls, dev()), gmodel(T, K=K)))[0]
+    ref = oracle.simulate(balls, arr, otime(T, K=K))
+    assert rel_l2(y, ref) <= 1e-5
+    assert np.max(np.abs(y - ref)) <= 1e-4 * np.max(np.abs(ref))
+
+
 def dev():
     return torch.device("cuda:0")
 

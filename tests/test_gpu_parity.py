@@ -620,6 +620,68 @@ def test_step_graph_replays_match_eager(ctx):
     graph.close()
 
 
+@pytest.mark.parametrize("nd,counts,tuning,mask,extra", [
+    (17, [700, 0, 1300, 41], None, api.ALL, {}),                  # slices summed by the Adam step
+    (3, [2000, 900], None, api.ALL, {}),                          # one slice: gradients stored
+    (13, [1500, 333], dict(adj_block=128, adj_bpt=2, adj_dets=2), api.ALL, {"a_softplus": 1}),
+    (13, [1500], dict(adj_block=64, adj_bpt=1, adj_dets=1, adj_grid=5), api.ALL, {}),
+    (11, [800, 1200], None, api._abi.X | api._abi.Z | api._abi.A, {}),
+    (11, [900], None, api._abi.P0, {}),                            # the p0-only adjoint
+    (9, [600, 500, 400], None, api.ALL, {"nan_ball": (1, 7)}),    # frame 1 non-finite
+    (9, [600, 500], None, api.ALL, {"profile": 0}),               # UNIFORM balls
+])
+def test_step_graph_matches_eager_bitwise(ctx, nd, counts, tuning, mask, extra):
+    """Captured iterations (device words and integer sums filled once per
+    launch and left zero by the conversion and Adam, the step count read on
+    the device) against eager steps: over uneven frames, several iterations,
+    launch shapes, masks, the softplus size, a non-finite ball and UNIFORM
+    balls, the balls, gradients, moments and losses are equal bit for bit (NaN
+    where the eager run has NaN)."""
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(nd * 1000 + len(counts))
+    arr = synth.hemisphere_array(nd, 12.0, rng, tilt_deg=20)
+    balls = synth.concat_balls([synth.uniform_balls(rng, n, 3.5, 0.15) for n in counts])
+    off = np.cumsum([0] + counts)
+    T = 400
+    model = gmodel(T, profile=extra.get("profile", 1), a_softplus=extra.get("a_softplus", 0))
+    toff = torch.as_tensor(off, device=dev)
+    old = ctx.tuning
+    try:
+        if tuning:
+            ctx.tuning = tuning
+        gt = dict(balls, p0=(balls["p0"] * 0.8).astype(np.float32))
+        y_ref = run_fwd(ctx, arr, gt, model, ball_off=toff)
+        if "nan_ball" in extra:
+            f, k = extra["nan_ball"]
+            balls["y"][off[f] + k] = np.nan
+        prm = api.AdamParams(lr=(0.002, 0.002, 0.002, 0.02, 0.002), step=1, mask=mask)
+        A = to_dev(arr, dev)
+        st_e = api.State(balls, ball_off=off, device=dev)
+        st_g = api.State(balls, ball_off=off, device=dev)
+        yw_e, yw_g = torch.empty_like(y_ref), torch.empty_like(y_ref)
+        graph = api.StepGraph(ctx, A, st_g, model, y_ref, yw_g, prm, iters=4, step0=1)
+        for rep in range(2):
+            losses = []
+            for it in range(4):
+                prm.step = 4 * rep + it + 1
+                losses.append(api.step(ctx, A, st_e, model, y_ref, yw_e, prm).cpu().numpy())
+            graph.launch()
+            graph.stream.synchronize()
+            np.testing.assert_array_equal(graph.loss.cpu().numpy().reshape(4, -1), np.stack(losses))
+            for k in PARAMS:
+                for w in ("balls", "grad", "m", "v"):
+                    np.testing.assert_array_equal(getattr(st_g, w)[k].cpu().numpy(),
+                                                  getattr(st_e, w)[k].cpu().numpy(), err_msg=f"{rep} {w} {k}")
+        if "nan_ball" in extra:
+            assert np.isnan(losses[-1][1]) and np.isfinite(np.delete(losses[-1], 1)).all()
+        else:
+            assert np.isfinite(np.stack(losses)).all() and losses[-1].sum() < losses[0].sum()
+        assert graph.step_dev.item() == 9
+        graph.close()
+    finally:
+        ctx.tuning = old
+
+
 def test_sixty_four_frames(ctx):
     """The largest batch the ABI takes (SBP_MAX_FRAMES = 64 frames), with empty
     and uneven frames: every frame's signals and gradients against the oracle
