@@ -125,6 +125,35 @@ __global__ __launch_bounds__(256) void k_lds_pattern(unsigned long long *out, in
     atomicAdd(out, s);
 }
 
+// Random 64-bit atomic adds with the address residue fixed by the lane:
+// RES entries in a row of the same residue modulo RES are lane l's (l mod RES)
+// (RES = 8: eight lanes per residue class; 16: four), and with only the first
+// ACTIVE lanes of each wave taking part (ACTIVE < 64: a partly masked
+// instruction, as at the end of a pair's edges).
+template <int RES, int ACTIVE>
+__global__ __launch_bounds__(256) void k_lds_residue(unsigned long long *out, int iters) {
+    __shared__ unsigned long long row[4096];
+    for (int i = threadIdx.x; i < 4096; i += blockDim.x) row[i] = 0ull;
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t h = (blockIdx.x * 256u + threadIdx.x) * 2654435761u + 12345u;
+    if (lane < (uint32_t)ACTIVE) {
+        for (int i = 0; i < iters; ++i) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                h = h * 1664525u + 1013904223u;
+                const uint32_t idx = RES > 1 ? (((h >> 16) & 4095u & ~(uint32_t)(RES - 1)) | (lane & (RES - 1)))
+                                             : ((h >> 16) & 4095u);
+                atomicAdd(&row[idx], (unsigned long long)(h & 7u));
+            }
+        }
+    }
+    __syncthreads();
+    unsigned long long s = 0;
+    for (int i = threadIdx.x; i < 4096; i += blockDim.x) s += row[i];
+    atomicAdd(out, s);
+}
+
 // 64-bit adds at random entries done as a returning 32-bit add to the low
 // word and, where it wrapped, a 32-bit add of the carry to the high word (the
 // sum is the same 64-bit integer).  Values are uniform below 2^VBITS, so a
@@ -227,6 +256,11 @@ int main() {
     if (run("lds_add_u32_random", [&] { hipLaunchKernelGGL((k_lds<unsigned int, false>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_u64_consecutive", [&] { hipLaunchKernelGGL((k_lds_pattern<unsigned long long, PAT_CONSEC>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_u64_four_lanes_per_entry", [&] { hipLaunchKernelGGL((k_lds_pattern<unsigned long long, PAT_CLUSTER4>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
+    if (run("lds_add_u64_random_residue8", [&] { hipLaunchKernelGGL((k_lds_residue<8, 64>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
+    if (run("lds_add_u64_random_residue16", [&] { hipLaunchKernelGGL((k_lds_residue<16, 64>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
+    if (run("lds_add_u64_random_48_lanes", [&] { hipLaunchKernelGGL((k_lds_residue<1, 48>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl * 48 / 64)) return 1;
+    if (run("lds_add_u64_random_32_lanes", [&] { hipLaunchKernelGGL((k_lds_residue<1, 32>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl * 32 / 64)) return 1;
+    if (run("lds_add_u64_random_16_lanes", [&] { hipLaunchKernelGGL((k_lds_residue<1, 16>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl * 16 / 64)) return 1;
     if (run("lds_add_u64_as_u32_carry_v22", [&] { hipLaunchKernelGGL(k_lds_split<22>, dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_u64_as_u32_carry_v26", [&] { hipLaunchKernelGGL(k_lds_split<26>, dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_u64_as_u32_carry_v29", [&] { hipLaunchKernelGGL(k_lds_split<29>, dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
