@@ -142,6 +142,77 @@ __device__ inline void stage_rows(const R *__restrict__ vf, int d0, int nd, int 
 // Row stride of the staged tiles: the tile length rounded up to four floats.
 __host__ __device__ inline int adj_row_stride(int TT) { return (TT + 3) & ~3; }
 
+// Stages the nd whole rows d0.. of frame f from the forward's edge sums
+// (AdjSrc): v_n = 2 (y_n - y_ref_n) with y_n = (W_{n+1} - W_n) q as the
+// conversion forms it (NaN in a flagged frame) into vrows (stride T), then
+// w_m = vscale (v_m - v_{m-1}) for m = 0..T into rows (stride TS).  `first`
+// (the frame's first ball chunk): also v to y_work and, one wave per row, each
+// row's sum of (y - y_ref)^2 in FP64 (lane n mod 64 adds its samples in order,
+// then a fixed tree), so the loss does not depend on the launch shape.
+__device__ inline void stage_rows_from_sums(const AdjSrc &src, int f, int D, int d0, int nd, int T,
+                                            const Level &lc, float vscale, float *rows, int TS,
+                                            float *vrows, bool first) {
+    const int tid = threadIdx.x;
+    const int nth = blockDim.x;
+    const bool bad = src.misc[kMiscFlags + f] != 0;
+    const float inv_scale = 1.0f / fixed_scale(src.misc + kMiscBound, GAUSS, lc);
+    // all rows' samples as one range, four per thread in flight (loads first)
+    const int total = nd * T;
+    for (int i0 = tid; i0 < total; i0 += 4 * nth) {
+        unsigned long long wa[4], wb[4];
+        float rv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * nth;
+            if (i < total) {
+                const int dl = i / T;
+                const int n = i - dl * T;
+                const int64_t r = (int64_t)f * D + d0 + dl;
+                wa[u] = src.gacc[r * (T + 1) + n];
+                wb[u] = src.gacc[r * (T + 1) + n + 1];
+                rv[u] = src.y_ref[r * T + n];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * nth;
+            if (i < total) {
+                const int dl = i / T;
+                const int n = i - dl * T;
+                const long long diff = (long long)(wb[u] - wa[u]);
+                const float y = bad ? __builtin_nanf("") : (float)((double)diff * (double)inv_scale);
+                const float v = 2.0f * (y - rv[u]);
+                vrows[(int64_t)dl * T + n] = v;
+                if (first) src.y_work[((int64_t)f * D + d0 + dl) * T + n] = v;
+            }
+        }
+    }
+    __syncthreads();
+    for (int dl = 0; dl < nd; ++dl) {
+        const float *vr = vrows + (int64_t)dl * T;
+        float *wr = rows + (int64_t)dl * TS;
+        for (int m = tid; m <= T; m += nth) {
+            const float cur = m < T ? vr[m] : 0.0f;
+            const float prv = m > 0 ? vr[m - 1] : 0.0f;
+            wr[m] = vscale * (cur - prv);
+        }
+    }
+    if (first) {
+        // one wave per row (the order within a row does not depend on the block size)
+        const int lane = tid & 63;
+        for (int dl = tid >> 6; dl < nd; dl += (nth + 63) >> 6) {
+            const float *vr = vrows + (int64_t)dl * T;
+            double acc = 0.0;
+            for (int n = lane; n < T; n += 64) {
+                const double e = (double)(0.5f * vr[n]);
+                acc += e * e;
+            }
+            for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+            if (lane == 0) src.row_loss[(int64_t)f * D + d0 + dl] = acc;
+        }
+    }
+}
+
 // Work items are (frame, ball chunk, transducer slice).  With one slice the
 // kernel writes the gradients; with nsl > 1 each item writes its slice's
 // partial sums to part[(slice * NF + field) * pstride + ball] (NF = 5, or 1
@@ -151,22 +222,33 @@ __host__ __device__ inline int adj_row_stride(int TT) { return (TT + 3) & ~3; }
 // spill to scratch (the build checks the compiler's resource-usage remarks).
 // FP32 kernels hold up to kMaxBpt = 3 balls per lane in 128 VGPRs (four
 // waves); the FP64 twin, a correctness path, gets 256 (two waves).
-template <typename R, int PROF, int DIR, bool FULL> struct AdjMinBlocks {
+template <typename R, int PROF, int DIR, bool FULL, bool SRC = false> struct AdjMinBlocks {
     // all-gradient GAUSS / OMNI needs more registers than four waves per SIMD
     // leave it: three waves rather than spilling (UNIFORM / COS fits four with
-    // a staging depth of three)
+    // a staging depth of three); the variants that form the cotangent from
+    // edge sums (small clouds) hold three
     static constexpr int v = sizeof(R) == sizeof(double) ? 2
-                             : (FULL && PROF == GAUSS && DIR == OMNI) ? 3 : 4;
+                             : ((FULL && PROF == GAUSS && DIR == OMNI) || SRC) ? 3 : 4;
 };
 
-template <typename R, int PROF, int DIR, bool FULL>
-__global__ __launch_bounds__(512, (AdjMinBlocks<R, PROF, DIR, FULL>::v)) void k_adjoint(ArrayP<R> arr, BallsP<R> balls,
+// S: NoSrc, or AdjSrc (FP32 GAUSS bins only) for the cotangent formed from
+// the forward's edge sums (a separate instantiation, so that the other
+// kernels carry neither its arguments nor its registers).
+struct NoSrc {
+    static constexpr bool on = false;
+};
+struct AdjSrcK : AdjSrc {
+    static constexpr bool on = true;
+};
+
+template <typename R, int PROF, int DIR, bool FULL, typename S = NoSrc>
+__global__ __launch_bounds__(512, (AdjMinBlocks<R, PROF, DIR, FULL, S::on>::v)) void k_adjoint(ArrayP<R> arr, BallsP<R> balls,
                                                  const int64_t *__restrict__ ball_off, int F,
                                                  int ds, int TT, int bpt, int nsl, int dsl,
                                                  Level lc, const R *__restrict__ v, R vscale,
                                                  uint32_t mask, BallsP<R> grad,
                                                  R *__restrict__ part, int64_t pstride,
-                                                 const int32_t *__restrict__ order) {
+                                                 const int32_t *__restrict__ order, S src) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     R *rows = reinterpret_cast<R *>(lds_raw);
     __shared__ int64_t s_off[SBP_MAX_FRAMES + 1];
@@ -191,6 +273,7 @@ __global__ __launch_bounds__(512, (AdjMinBlocks<R, PROF, DIR, FULL>::v)) void k_
         const int sl = (int)(it - ci * nsl);
         int f = 0;
         while (ci >= s_cpre[f + 1]) ++f;
+        [[maybe_unused]] const bool first = ci == s_cpre[f];   // the frame's first ball chunk
         const int64_t base = s_off[f] + (ci - s_cpre[f]) * CH;
         const int64_t end = min(base + CH, s_off[f + 1]);
         BallK<R, PROF> b[kMaxBpt];
@@ -218,8 +301,12 @@ __global__ __launch_bounds__(512, (AdjMinBlocks<R, PROF, DIR, FULL>::v)) void k_
                 const int thi = min(tlo + TT, T + 1);
                 __syncthreads();
                 // point samples are staged as they are, bin edges differenced
-                stage_rows<R, PROF != GPOINT, StageDepth<PROF, DIR, FULL>::v>(vf, d0, nd, T, tlo, thi,
-                                                                              vscale, rows, TS);
+                if constexpr (S::on)
+                    stage_rows_from_sums(src, f, D, d0, nd, T, lc, vscale, rows, TS,
+                                         rows + (int64_t)ds * TS, first);
+                else
+                    stage_rows<R, PROF != GPOINT, StageDepth<PROF, DIR, FULL>::v>(vf, d0, nd, T, tlo,
+                                                                                  thi, vscale, rows, TS);
                 __syncthreads();
                 for (int dl = 0; dl < nd; ++dl) {
                     const int d = __builtin_amdgcn_readfirstlane(d0 + dl);
@@ -227,7 +314,9 @@ __global__ __launch_bounds__(512, (AdjMinBlocks<R, PROF, DIR, FULL>::v)) void k_
                             qz = ld_uniform(arr.qz + d), nx = ld_uniform(arr.nx + d),
                             ny = ld_uniform(arr.ny + d), nz = ld_uniform(arr.nz + d);
                     const R *wrow = rows + (int64_t)dl * TS;
-                    const R *vrow = vf + (int64_t)d * T;
+                    // the cotangent row: global, or staged after the rows when formed here
+                    const R *vrow = S::on ? rows + (int64_t)ds * TS + (int64_t)dl * T
+                                          : vf + (int64_t)d * T;
 #pragma unroll
                     for (int jb = 0; jb < kMaxBpt; ++jb) {
                         if (!act[jb]) continue;
@@ -338,14 +427,28 @@ size_t adjoint_ws_bytes(const Ctx *c, int D, int64_t B_cap, int F, uint32_t mask
     return ((size_t)p.nsl * slice + 255) & ~(size_t)255;
 }
 
+// LDS for the staged rows: what a workgroup may take, less the static arrays.
+static size_t adj_lds_avail(const Ctx *c) {
+    const size_t reserve = 2 * (SBP_MAX_FRAMES + 1) * sizeof(int64_t) + 256;
+    return c->lds_max > reserve ? c->lds_max - reserve : 0;
+}
+
+bool adjoint_src_fits(const Ctx *c, int D, int T) {
+    int ds = c->tuning.adj_dets;
+    if (ds > D) ds = D;
+    if (c->tuning.adj_tile > 0 && c->tuning.adj_tile < T + 1) return false;
+    const size_t need = (size_t)ds * ((size_t)adj_row_stride(T + 1) + (size_t)T) * sizeof(float);
+    return need <= adj_lds_avail(c);
+}
+
 template <typename R, int PROF, int DIR, bool FULL>
 static int run_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
                        const int64_t *ball_off, int F, int64_t B_cap, const Level &lc, const R *v,
                        R vscale, uint32_t mask, const BallsP<R> &grad, void *ws, size_t ws_bytes,
-                       hipStream_t st, const int32_t *order, AdjDeferred *defer) {
+                       hipStream_t st, const int32_t *order, AdjDeferred *defer,
+                       const AdjSrc *src) {
     auto kern = k_adjoint<R, PROF, DIR, FULL>;
-    const size_t reserve = 2 * (SBP_MAX_FRAMES + 1) * sizeof(int64_t) + 256;
-    const size_t avail = c->lds_max > reserve ? c->lds_max - reserve : 0;
+    const size_t avail = adj_lds_avail(c);
     int ds = c->tuning.adj_dets;
     if (ds > arr.D) ds = arr.D;
     // edges 0..T staged per pass: the whole record if the ds rows fit (rows
@@ -354,6 +457,12 @@ static int run_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
     if (TT > (int64_t)lc.T + 1) TT = (int64_t)lc.T + 1;
     if (TT < (int64_t)lc.T + 1 && TT < 64) return fail(SBP_E_DOMAIN, "LDS too small for %d rows", ds);
     if (c->tuning.adj_tile > 0 && TT > c->tuning.adj_tile) TT = c->tuning.adj_tile;
+    constexpr bool CAN_SRC = sizeof(R) == sizeof(float) && PROF == GAUSS;
+    if (src) {
+        if (!CAN_SRC || !adjoint_src_fits(c, arr.D, lc.T))
+            return fail(SBP_E_ARG, "the cotangent from edge sums needs FP32 GAUSS bins and whole rows");
+        TT = (int64_t)lc.T + 1;
+    }
     const int nf = FULL ? 5 : 1;
     AdjPlan pl = adjoint_plan(c, arr.D, B_cap, F, (size_t)nf * (size_t)B_cap * sizeof(R));
     if (pl.nsl > 1 && ws_bytes < (size_t)pl.nsl * nf * (size_t)B_cap * sizeof(R)) {
@@ -362,13 +471,17 @@ static int run_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
     }
     R *part = pl.nsl > 1 ? (R *)ws : nullptr;
     const int block = pl.block;
-    const size_t lds = (size_t)ds * (size_t)adj_row_stride((int)TT) * sizeof(R);
-    SBP_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds));
+    // (with the cotangent formed here, its rows follow the staged edge rows)
+    const size_t lds = (size_t)ds * ((size_t)adj_row_stride((int)TT) + (src ? (size_t)lc.T : 0)) *
+                       sizeof(R);
+    const void *kfun = (const void *)kern;
+    if constexpr (CAN_SRC)
+        if (src) kfun = (const void *)k_adjoint<R, PROF, DIR, FULL, AdjSrcK>;
+    SBP_HIP(hipFuncSetAttribute(kfun, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int grid = c->tuning.adj_grid;
     if (grid <= 0) {
         int per_cu = 0;
-        SBP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, block, lds));
+        SBP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfun, block, lds));
         if (per_cu < 1) per_cu = 1;
         grid = per_cu * c->num_cus;
     }
@@ -376,9 +489,21 @@ static int run_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls,
     const int64_t max_items = ((B_cap + CH - 1) / CH + F) * pl.nsl;
     if (grid > max_items) grid = (int)max_items;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, arr, balls, ball_off, F, ds,
-                       (int)TT, pl.bpt, pl.nsl, pl.dsl, lc, v, vscale, mask, grad, part, B_cap,
-                       order);
+    bool launched = false;
+    if constexpr (CAN_SRC) {
+        if (src) {
+            AdjSrcK sk;
+            static_cast<AdjSrc &>(sk) = *src;
+            hipLaunchKernelGGL((k_adjoint<R, PROF, DIR, FULL, AdjSrcK>), dim3(grid), dim3(block), lds,
+                               st, arr, balls, ball_off, F, ds, (int)TT, pl.bpt, pl.nsl, pl.dsl, lc,
+                               v, vscale, mask, grad, part, B_cap, order, sk);
+            launched = true;
+        }
+    }
+    if (!launched)
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, st, arr, balls, ball_off, F, ds,
+                           (int)TT, pl.bpt, pl.nsl, pl.dsl, lc, v, vscale, mask, grad, part, B_cap,
+                           order, NoSrc{});
     SBP_HIP(hipGetLastError());
     if (defer) {
         *defer = AdjDeferred{};
@@ -407,50 +532,51 @@ static int dispatch_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls
                             const int64_t *ball_off, int F, int64_t B_cap, const sbp_model *m,
                             const R *v, R vscale, uint32_t mask, const BallsP<R> &grad, void *ws,
                             size_t ws_bytes, hipStream_t st, const int32_t *order,
-                            AdjDeferred *defer) {
+                            AdjDeferred *defer, const AdjSrc *src) {
     const Level lc = make_level(m);
     if (profile_code(m) == GPOINT) {
         if (m->directivity == SBP_DIR_COS)
             return run_adjoint<R, GPOINT, COS, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v,
-                                                     vscale, mask, grad, ws, ws_bytes, st, order, defer);
+                                                     vscale, mask, grad, ws, ws_bytes, st, order, defer, src);
         return run_adjoint<R, GPOINT, OMNI, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v, vscale,
-                                                  mask, grad, ws, ws_bytes, st, order, defer);
+                                                  mask, grad, ws, ws_bytes, st, order, defer, src);
     }
     if (m->profile == SBP_PROFILE_GAUSS) {
         if (m->directivity == SBP_DIR_COS)
             return run_adjoint<R, GAUSS, COS, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v,
-                                                    vscale, mask, grad, ws, ws_bytes, st, order, defer);
+                                                    vscale, mask, grad, ws, ws_bytes, st, order, defer, src);
         return run_adjoint<R, GAUSS, OMNI, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v, vscale,
-                                                 mask, grad, ws, ws_bytes, st, order, defer);
+                                                 mask, grad, ws, ws_bytes, st, order, defer, src);
     }
     if (m->directivity == SBP_DIR_COS)
         return run_adjoint<R, UNIFORM, COS, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v, vscale,
-                                                  mask, grad, ws, ws_bytes, st, order, defer);
+                                                  mask, grad, ws, ws_bytes, st, order, defer, src);
     return run_adjoint<R, UNIFORM, OMNI, FULL>(c, arr, balls, ball_off, F, B_cap, lc, v, vscale,
-                                               mask, grad, ws, ws_bytes, st, order, defer);
+                                               mask, grad, ws, ws_bytes, st, order, defer, src);
 }
 
 template <typename R>
 int launch_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
                    int F, int64_t B_cap, const sbp_model *m, const R *v, R vscale,
                    uint32_t mask, const BallsP<R> &grad, void *ws, size_t ws_bytes, hipStream_t st,
-                   const int32_t *order, AdjDeferred *defer) {
+                   const int32_t *order, AdjDeferred *defer, const AdjSrc *src) {
     if (defer) *defer = AdjDeferred{};
     if (B_cap == 0) return SBP_OK;
     if ((mask & ~SBP_P0) == 0)
         return dispatch_adjoint<R, false>(c, arr, balls, ball_off, F, B_cap, m, v, vscale, mask,
-                                          grad, ws, ws_bytes, st, order, defer);
+                                          grad, ws, ws_bytes, st, order, defer, src);
     return dispatch_adjoint<R, true>(c, arr, balls, ball_off, F, B_cap, m, v, vscale, mask, grad,
-                                     ws, ws_bytes, st, order, defer);
+                                     ws, ws_bytes, st, order, defer, src);
 }
 
 template int launch_adjoint<float>(Ctx *, const ArrayP<float> &, const BallsP<float> &,
                                    const int64_t *, int, int64_t, const sbp_model *, const float *,
                                    float, uint32_t, const BallsP<float> &, void *, size_t,
-                                   hipStream_t, const int32_t *, AdjDeferred *);
+                                   hipStream_t, const int32_t *, AdjDeferred *, const AdjSrc *);
 template int launch_adjoint<double>(Ctx *, const ArrayP<double> &, const BallsP<double> &,
                                     const int64_t *, int, int64_t, const sbp_model *,
                                     const double *, double, uint32_t, const BallsP<double> &,
-                                    void *, size_t, hipStream_t, const int32_t *, AdjDeferred *);
+                                    void *, size_t, hipStream_t, const int32_t *, AdjDeferred *,
+                                    const AdjSrc *);
 
 }  // namespace sbp

@@ -271,17 +271,31 @@ static int check_tuning(const sbp_tuning *t) {
     return SBP_OK;
 }
 
-// One iteration, shared by sbp_step and the graph capture.
-// One iteration: forward, residual and loss, adjoint, Adam.  Without a
-// transducer response it runs as four kernels after the forward's prep: the
-// forward's conversion writes v = 2 (y - y_ref) and the loss partial sums, and
-// the Adam kernel adds the adjoint's transducer slices and reduces the loss
-// (the same bits as the separate kernels).  y_aux: F D T floats of scratch
+// One iteration, shared by sbp_step and the graph capture: forward, residual
+// and loss, adjoint, Adam.  Without a transducer response it runs as four
+// kernels after the forward's prep: the forward's conversion writes
+// v = 2 (y - y_ref) and the loss partial sums, and the Adam kernel adds the
+// adjoint's transducer slices and reduces the loss (the same bits as the
+// separate kernels).  On a small GAUSS-bin cloud whose rows the adjoint can
+// stage whole (adjoint_src_fits) there is no conversion: the adjoint forms
+// v from the edge sums as it stages its rows (AdjSrc; the frames' first ball
+// chunks write y_work and each row's loss sum to `partial`, which then holds
+// F x D row sums), and Adam sums the rows, covers the frames without balls
+// and, in a captured sequence, zeroes the edge sums.  y_aux: F D T floats of scratch
 // when the model has a response (the simulated record before it, then the
 // correlated cotangent).  `captured`: the forward's integer sums and device
 // words are zero on entry and are left zero (the conversion clears the sums,
 // Adam the words), so a captured sequence fills them once per launch; the
 // step count is *step_dev + step_add.
+// Pairs (balls x transducers) up to which a step forms the cotangent inside
+// the adjoint (clouds whose kernels cost about their launch and latency).
+constexpr double kSrcPairs = 2.0e7;
+
+// Bytes of a step's loss sums: F x kLossBlocks partial sums, or F x D row sums.
+static size_t step_res_bytes(int F, int D) {
+    return (size_t)F * (size_t)(D > kLossBlocks ? D : kLossBlocks) * sizeof(double);
+}
+
 static int step_body(Ctx *c, const sbp_array *arr, sbp_state *s, const sbp_model *model,
                      const float *y_ref, float *y_work, const sbp_adam_params *p,
                      const int32_t *step_dev, double *loss, double *partial, unsigned *misc,
@@ -292,13 +306,17 @@ static int step_body(Ctx *c, const sbp_array *arr, sbp_state *s, const sbp_model
     const BallsP<float> g = ballsp<float>(&s->grad);
     const int64_t n = (int64_t)arr->D * model->T;
     const bool fused = !model->response && s->B_cap > 0;
+    const bool src_mode = fused && profile_code(model) == GAUSS &&
+                          (double)s->B_cap * arr->D <= kSrcPairs &&
+                          adjoint_src_fits(c, arr->D, model->T);
     int rc;
     if (fused) {
         FwdStep fs;
         fs.ws_clean = captured;
         fs.clear_after = captured;
-        fs.y_ref = y_ref;
-        fs.partial = partial;
+        fs.sums_only = src_mode;
+        fs.y_ref = src_mode ? nullptr : y_ref;
+        fs.partial = src_mode ? nullptr : partial;
         rc = launch_forward<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 0, misc,
                                    fwd_ws, fwd_ws_bytes, st, &fs);
     } else {
@@ -312,14 +330,35 @@ static int step_body(Ctx *c, const sbp_array *arr, sbp_state *s, const sbp_model
         rc = adjoint_with_response<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work,
                                           1.0f, p->mask, g, adj_ws, adj_ws_bytes, y_aux, st);
     } else {
+        AdjSrc src;
+        if (src_mode) {
+            src.gacc = (const unsigned long long *)fwd_ws;
+            src.y_ref = y_ref;
+            src.misc = misc;
+            src.y_work = y_work;
+            src.row_loss = partial;
+        }
         rc = launch_adjoint<float>(c, a, b, s->ball_off, s->F, s->B_cap, model, y_work, 1.0f,
-                                   p->mask, g, adj_ws, adj_ws_bytes, st, nullptr, &af.adj);
+                                   p->mask, g, adj_ws, adj_ws_bytes, st, nullptr, &af.adj,
+                                   src_mode ? &src : nullptr);
     }
     if (rc) return rc;
     af.a_softplus = model->a_softplus;
     if (fused) {
-        af.loss_partial = partial;
         af.loss = loss;
+        if (src_mode) {
+            af.row_loss = partial;
+            af.D = arr->D;
+            af.T = model->T;
+            af.y_ref = y_ref;
+            af.y_work = y_work;
+            if (captured) {
+                af.gacc = (unsigned long long *)fwd_ws;
+                af.n_gacc = (int64_t)s->F * arr->D * ((int64_t)model->T + 1);
+            }
+        } else {
+            af.loss_partial = partial;
+        }
     }
     // the forward left its device words set; in a captured sequence Adam
     // clears them for the next forward (with fills skipped on entry).  Any
@@ -702,7 +741,7 @@ int sbp_step(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state, const sbp_mod
     if ((rc = set_device(ctx->c))) return rc;
     // scratch: [residual partial sums][forward integer sums][adjoint slices][record before
     //          the response]
-    const size_t r_bytes = up256(residual_ws_bytes(state->F));
+    const size_t r_bytes = up256(step_res_bytes(state->F, arr->D));
     const size_t f_bytes = up256(forward_ws_bytes(state->F, arr->D, model->T, state->B_cap, sizeof(float)));
     const size_t a_bytes = up256(adjoint_ws_bytes(&ctx->c, arr->D, state->B_cap, state->F, p->mask, sizeof(float)));
     const size_t x_bytes = response_ws_bytes(model, state->F, arr->D, sizeof(float));
@@ -735,7 +774,7 @@ int sbp_step_graph_create(sbp_ctx *ctx, const sbp_array *arr, sbp_state *state,
     g->device = ctx->c.device;
     // graph workspace: [residual partial sums][device words][forward integer sums][adjoint slices]
     //                  [record before the response]
-    const size_t ws_res = up256(residual_ws_bytes(state->F));
+    const size_t ws_res = up256(step_res_bytes(state->F, arr->D));
     const size_t ws_fwd = up256(forward_ws_bytes(state->F, arr->D, model->T, state->B_cap, sizeof(float)));
     const size_t ws_adj = up256(adjoint_ws_bytes(&ctx->c, arr->D, state->B_cap, state->F, p->mask, sizeof(float)));
     const size_t ws_aux = response_ws_bytes(model, state->F, arr->D, sizeof(float));

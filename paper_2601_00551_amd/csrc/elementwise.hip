@@ -140,6 +140,14 @@ struct AdamArgs {
     unsigned *misc_clear;
     int step_add;
     int n_adam;   // workgroups of the update; the F after them reduce the loss
+    // with the cotangent formed in the adjoint (AdamFuse): the row sums, and
+    // frames without balls handled here; the edge sums zeroed
+    const double *row_loss;
+    int D, T;
+    const float *y_ref;
+    float *y_work;
+    unsigned long long *gacc;
+    int64_t n_gacc;
 };
 
 // PyTorch's single-tensor Adam in FP32: m.lerp_(g, 1-b1); v = v*b2 + (1-b2) g g;
@@ -157,11 +165,34 @@ __global__ void k_adam(AdamArgs a, const int64_t *__restrict__ ball_off, int F,
         if (k != 0) return;
         const int f = (int)blockIdx.x - a.n_adam;
         double acc = 0.0;
-        for (int i = threadIdx.x; i < kLossBlocks; i += blockDim.x)
-            acc += a.loss_partial[(int64_t)f * kLossBlocks + i];
+        if (a.row_loss) {
+            if (ball_off[f + 1] > ball_off[f]) {
+                for (int i = threadIdx.x; i < a.D; i += blockDim.x)
+                    acc += a.row_loss[(int64_t)f * a.D + i];
+            } else {
+                // no balls, so no adjoint items: y = 0 and v = -2 y_ref here
+                const int64_t n = (int64_t)a.D * a.T;
+                const float *rr = a.y_ref + (int64_t)f * n;
+                float *yw = a.y_work + (int64_t)f * n;
+                for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+                    const float e = 0.0f - rr[i];
+                    yw[i] = 2.0f * e;
+                    acc += (double)e * (double)e;
+                }
+            }
+        } else {
+            for (int i = threadIdx.x; i < kLossBlocks; i += blockDim.x)
+                acc += a.loss_partial[(int64_t)f * kLossBlocks + i];
+        }
         const double t = block_sum(acc, s_part);
         if (threadIdx.x == 0) a.loss[f] = t;
         return;
+    }
+    if (a.gacc) {   // the forward's edge sums, zero again for the next forward
+        const int64_t stride = (int64_t)a.n_adam * 5 * blockDim.x;
+        for (int64_t i = ((int64_t)k * a.n_adam + blockIdx.x) * blockDim.x + threadIdx.x;
+             i < a.n_gacc; i += stride)
+            a.gacc[i] = 0ull;
     }
     if (a.misc_clear && blockIdx.x == 0 && k == 0)
         for (int i = threadIdx.x; i < kMiscFlags + SBP_MAX_FRAMES; i += blockDim.x) a.misc_clear[i] = 0u;
@@ -231,9 +262,16 @@ int launch_adam(const sbp_state *s, const sbp_adam_params *p, const int32_t *ste
     a.loss = fuse ? fuse->loss : nullptr;
     a.misc_clear = fuse ? fuse->misc_clear : nullptr;
     a.step_add = fuse ? fuse->step_add : 0;
+    a.row_loss = fuse ? fuse->row_loss : nullptr;
+    a.D = fuse ? fuse->D : 0;
+    a.T = fuse ? fuse->T : 0;
+    a.y_ref = fuse ? fuse->y_ref : nullptr;
+    a.y_work = fuse ? fuse->y_work : nullptr;
+    a.gacc = fuse ? fuse->gacc : nullptr;
+    a.n_gacc = fuse ? fuse->n_gacc : 0;
     a.n_adam = ew_grid(s->B_cap) < 2048 ? ew_grid(s->B_cap) : 2048;   // per parameter row
-    const int nloss = a.loss_partial ? s->F : 0;
-    if (s->B_cap == 0 && nloss == 0 && !a.misc_clear) return SBP_OK;
+    const int nloss = (a.loss_partial || a.row_loss) ? s->F : 0;
+    if (s->B_cap == 0 && nloss == 0 && !a.misc_clear && !a.gacc) return SBP_OK;
     hipLaunchKernelGGL(k_adam, dim3(a.n_adam + nloss, 5), dim3(kEw), 0, st, a, s->ball_off, s->F,
                        step_dev);
     SBP_HIP(hipGetLastError());

@@ -360,21 +360,6 @@ __device__ inline void flush_rows(typename FwdAcc<R>::T *__restrict__ rows, int 
     __syncthreads();
 }
 
-// Power-of-two scale with |bin value| * scale <= 2^30 (FP32 path).
-__device__ inline float fixed_scale(const unsigned *slot, int profile, const Level &lc) {
-    const float pa = __uint_as_float(*slot);
-    // point samples: |u e(u)| <= a e^{-1/2} and rho > K a, so |p| < |p0| / (2 K)
-    const float bound = profile == GPOINT ? pa * 0.5f / lc.K
-                                          : pa * lc.inv2cdt * (profile == GAUSS ? 1.0f / lc.K : 0.5f);
-    if (!(bound > 0.0f) || !(bound < 3.0e38f)) return 1.0f;
-    int e = 0;
-    frexpf(bound, &e);              // bound < 2^e
-    int k = 30 - e;
-    if (k > 120) k = 120;
-    if (k < -120) k = -120;
-    return ldexpf(1.0f, k);
-}
-
 // y = (accumulate ? y : 0) + q * sum, for every sample of the launch (grid.y =
 // frame); a flagged frame gets NaN.
 // Inside a step (y_ref given) the value written is v = 2 (y - y_ref), and the
@@ -876,6 +861,8 @@ int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const i
     const FwdStep &sp = step ? *step : none;
     if (sp.y_ref && (sizeof(R) != sizeof(float) || !sp.partial))
         return fail(SBP_E_ARG, "the fused residual needs the FP32 forward and a partial buffer");
+    if (sp.sums_only && (sizeof(R) != sizeof(float) || profile_code(m) != GAUSS || sp.y_ref || accumulate))
+        return fail(SBP_E_ARG, "edge sums alone need the FP32 GAUSS bin forward");
     const int64_t nper = (int64_t)arr.D * m->T;
     const int64_t ns = (int64_t)F * nper;
     if (B_cap == 0 || sizeof(R) != sizeof(float)) {
@@ -920,6 +907,7 @@ int launch_forward(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const i
         else
             rc = run_forward_gz<OMNI>(c, af, pb, ball_off, F, B_cap, lc, bound, gacc, st);
         if (rc) return rc;
+        if (sp.sums_only) return SBP_OK;
         int nbx = sp.y_ref ? kLossBlocks : (arr.D < 1024 ? arr.D : 1024);
         hipLaunchKernelGGL(k_fwd_convert_edges, dim3(nbx, F), dim3(256), 0, st, gacc, arr.D, m->T,
                            (const unsigned *)misc, lc, accumulate, (float *)y,

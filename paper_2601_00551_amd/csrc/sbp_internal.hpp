@@ -287,18 +287,37 @@ __device__ inline R slice_sum(const R *__restrict__ p, int nsl, int64_t step) {
     return s;
 }
 
+// Power-of-two scale with |bin value| * scale <= 2^30 (FP32 path).
+__device__ inline float fixed_scale(const unsigned *slot, int profile, const Level &lc) {
+    const float pa = __uint_as_float(*slot);
+    // point samples: |u e(u)| <= a e^{-1/2} and rho > K a, so |p| < |p0| / (2 K)
+    const float bound = profile == GPOINT ? pa * 0.5f / lc.K
+                                          : pa * lc.inv2cdt * (profile == GAUSS ? 1.0f / lc.K : 0.5f);
+    if (!(bound > 0.0f) || !(bound < 3.0e38f)) return 1.0f;
+    int e = 0;
+    frexpf(bound, &e);              // bound < 2^e
+    int k = 30 - e;
+    if (k > 120) k = 120;
+    if (k < -120) k = -120;
+    return ldexpf(1.0f, k);
+}
+
 // Partial sums of the loss per frame (a fixed count: a deterministic order).
 constexpr int kLossBlocks = 512;
 
 // The forward inside a reconstruction step (FP32):
 //   ws_clean     misc and the integer sums are zero on entry (no fills);
 //   clear_after  the conversion zeroes each integer sum once it has read it;
+//   sums_only    (GAUSS bins) no conversion: the edge sums stay in the
+//                workspace for an adjoint that forms the cotangent from them
+//                (AdjSrc);
 //   y_ref        when set, the conversion writes v = 2 (y - y_ref) instead of y,
 //                and the sums of (y - y_ref)^2 (FP64, kLossBlocks per frame)
 //                to partial[F][kLossBlocks].
 struct FwdStep {
     bool ws_clean = false;
     bool clear_after = false;
+    bool sums_only = false;
     const float *y_ref = nullptr;
     double *partial = nullptr;
 };
@@ -323,6 +342,24 @@ struct AdjDeferred {
     int64_t pstride = 0;
 };
 
+// The cotangent of a reconstruction step formed inside the adjoint (GAUSS
+// bins, FP32, small clouds): each work item stages its rows as
+// v = 2 (y - y_ref) from the forward's edge sums (y as the conversion forms
+// it, NaN in a flagged frame) and keeps v itself in LDS (for the telescoped
+// sum over a pair's edges); the items of each frame's first ball chunk also
+// write v to y_work and each row's sum of (y - y_ref)^2 (FP64, in a fixed
+// order) to row_loss[f][d].  Rows are staged whole (adjoint_src_fits).
+struct AdjSrc {
+    const unsigned long long *gacc = nullptr;   // [F][D][T + 1] edge sums
+    const float *y_ref = nullptr;               // [F][D][T]
+    const unsigned *misc = nullptr;             // fixed-point bound, frame flags
+    float *y_work = nullptr;                    // [F][D][T] receives v
+    double *row_loss = nullptr;                 // [F][D]
+};
+// Whether the adjoint can stage whole rows with their cotangents (LDS and the
+// tile limit) for this many transducers and samples.
+bool adjoint_src_fits(const Ctx *c, int D, int T);
+
 // vscale multiplies v (the filter passes y_ref with vscale = -2).  ws holds the
 // per-slice partial gradients when the launch splits the transducers into
 // slices (adjoint_ws_bytes of them; with less, the launch does not split).
@@ -331,7 +368,8 @@ template <typename R>
 int launch_adjoint(Ctx *c, const ArrayP<R> &arr, const BallsP<R> &balls, const int64_t *ball_off,
                    int F, int64_t B_cap, const sbp_model *m, const R *v, R vscale,
                    uint32_t mask, const BallsP<R> &grad, void *ws, size_t ws_bytes, hipStream_t st,
-                   const int32_t *order = nullptr, AdjDeferred *defer = nullptr);
+                   const int32_t *order = nullptr, AdjDeferred *defer = nullptr,
+                   const AdjSrc *src = nullptr);
 
 template <typename R>
 int launch_fill(R *p, int64_t n, R value, hipStream_t st);
@@ -357,6 +395,16 @@ struct AdamFuse {
     double *loss = nullptr;
     unsigned *misc_clear = nullptr;
     int step_add = 0;
+    // with an AdjSrc adjoint: the loss of a frame is the sum of its D row
+    // sums (row_loss); a frame without balls (no adjoint items) gets v and
+    // its loss here from y_ref; gacc (n_gacc words) is zeroed for the next
+    // forward when set
+    const double *row_loss = nullptr;
+    int D = 0, T = 0;
+    const float *y_ref = nullptr;
+    float *y_work = nullptr;
+    unsigned long long *gacc = nullptr;
+    int64_t n_gacc = 0;
 };
 int launch_adam(const sbp_state *s, const sbp_adam_params *p, const int32_t *step_dev,
                 int a_softplus, hipStream_t st, const AdamFuse *fuse = nullptr);
