@@ -395,8 +395,9 @@ def test_step_equals_composed_oracle(ctx):
         assert rel_l2(st.grad[k][:len(g[k])].cpu().numpy(), g[k]) <= GRAD_TOL, k
 
 
-@pytest.mark.parametrize("counts", [[1200, 0, 800], [0, 900]])
-def test_step_cotangent_and_loss_per_frame(ctx, counts):
+@pytest.mark.parametrize("counts,nd,T", [([1200, 0, 800], 15, 400), ([0, 900], 15, 400),
+                                         ([700, 500], 600, 333)])      # more rows than loss blocks
+def test_step_cotangent_and_loss_per_frame(ctx, counts, nd, T):
     """One step over uneven frames, one of them without balls, on a cloud small
     enough for the step to form the cotangent inside the adjoint: y_work holds
     v = 2 (y - y_ref) frame by frame (y_ref's own -2 y_ref where a frame has no
@@ -404,20 +405,19 @@ def test_step_cotangent_and_loss_per_frame(ctx, counts):
     residuals."""
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(sum(counts) + len(counts))
-    arr = synth.hemisphere_array(15, 12.0, rng, tilt_deg=20)
+    arr = synth.hemisphere_array(nd, 12.0, rng, tilt_deg=20)
     parts = [synth.uniform_balls(rng, n, 3.5, 0.15) for n in counts]
     balls = synth.concat_balls(parts)
     off = np.cumsum([0] + counts)
-    T = 400
     y_ref = np.stack([oracle.simulate(dict(p, p0=(p["p0"] * 0.7).astype(np.float32)), arr, otime(T))
-                      if len(p["x"]) else rng.normal(size=(15, T)) for p in parts]).astype(np.float32)
+                      if len(p["x"]) else rng.normal(size=(nd, T)) for p in parts]).astype(np.float32)
     st = api.State(balls, ball_off=off, device=dev)
-    y_work = torch.empty(len(counts), 15, T, device=dev)
+    y_work = torch.empty(len(counts), nd, T, device=dev)
     loss = api.step(ctx, to_dev(arr, dev), st, gmodel(T), torch.as_tensor(y_ref, device=dev), y_work,
                     api.AdamParams(step=1)).cpu().numpy()
     yw = y_work.cpu().numpy()
     for f, p in enumerate(parts):
-        ys = oracle.simulate(p, arr, otime(T)) if len(p["x"]) else np.zeros((15, T))
+        ys = oracle.simulate(p, arr, otime(T)) if len(p["x"]) else np.zeros((nd, T))
         L, v = oracle.residual_loss(ys, y_ref[f])
         assert loss[f] == pytest.approx(L, rel=1e-5), f
         assert rel_l2(yw[f], v) <= 1e-5, f
