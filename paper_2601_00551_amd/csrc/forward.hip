@@ -673,16 +673,30 @@ __global__ __launch_bounds__(512, 4) void k_forward_gz(ArrayP<float> arr, FwdPre
         const int thi = min(tlo + TT, TE);
         const int64_t base = s_off[f] + ck * CH;
         const int64_t end = min(base + CH, s_off[f + 1]);
-        for (int jb = 0; jb < bpt; ++jb) {
-            const int64_t i = base + (int64_t)jb * nth + tid;
-            float bx = 0.0f, by = 0.0f, bz = 0.0f, w = 0.0f, q0 = 0.0f, pa2 = 0.0f;
+        // the next ball's constants load while this one's pairs are added
+        float nbx = 0.0f, nby = 0.0f, nbz = 0.0f, nw = 0.0f, nq0 = 0.0f, npa2 = 0.0f;
+        {
+            const int64_t i = base + tid;
             if (i < end) {
-                bx = pb.x[i];
-                by = pb.y[i];
-                bz = pb.z[i];
-                w = pb.w[i];
-                q0 = pb.q0[i];
-                pa2 = pb.pa2[i];
+                nbx = pb.x[i];
+                nby = pb.y[i];
+                nbz = pb.z[i];
+                nw = pb.w[i];
+                nq0 = pb.q0[i];
+                npa2 = pb.pa2[i];
+            }
+        }
+        for (int jb = 0; jb < bpt; ++jb) {
+            const float bx = nbx, by = nby, bz = nbz, w = nw, q0 = nq0, pa2 = npa2;
+            const int64_t i = base + (int64_t)(jb + 1) * nth + tid;
+            nbx = nby = nbz = nw = nq0 = npa2 = 0.0f;
+            if (jb + 1 < bpt && i < end) {
+                nbx = pb.x[i];
+                nby = pb.y[i];
+                nbz = pb.z[i];
+                nw = pb.w[i];
+                nq0 = pb.q0[i];
+                npa2 = pb.pa2[i];
             }
             const bool nn = __all(pa2 >= 0.0f);   // wave-uniform
             if (pa2 == 0.0f) continue;
