@@ -130,6 +130,32 @@ __global__ __launch_bounds__(256) void k_lds_pattern(unsigned long long *out, in
 // (RES = 8: eight lanes per residue class; 16: four), and with only the first
 // ACTIVE lanes of each wave taking part (ACTIVE < 64: a partly masked
 // instruction, as at the end of a pair's edges).
+// Random 64-bit atomic adds confined to a span of SPAN consecutive entries
+// (a wave-uniform random base): more lanes of an instruction share an entry
+// as the span narrows (a transducer sees a chunk's balls over a few hundred
+// edges).
+template <int SPAN>
+__global__ __launch_bounds__(256) void k_lds_span(unsigned long long *out, int iters) {
+    __shared__ unsigned long long row[4096];
+    for (int i = threadIdx.x; i < 4096; i += blockDim.x) row[i] = 0ull;
+    __syncthreads();
+    uint32_t h = (blockIdx.x * 256u + threadIdx.x) * 2654435761u + 12345u;
+    uint32_t hw = __builtin_amdgcn_readfirstlane((blockIdx.x * 4u + (threadIdx.x >> 6)) * 2246822519u + 777u);
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            h = h * 1664525u + 1013904223u;
+            hw = hw * 1664525u + 1013904223u;
+            const uint32_t idx = (((hw >> 16) & 4095u) + ((h >> 16) % (uint32_t)SPAN)) & 4095u;
+            atomicAdd(&row[idx], (unsigned long long)(h & 7u));
+        }
+    }
+    __syncthreads();
+    unsigned long long s = 0;
+    for (int i = threadIdx.x; i < 4096; i += blockDim.x) s += row[i];
+    atomicAdd(out, s);
+}
+
 template <int RES, int ACTIVE>
 __global__ __launch_bounds__(256) void k_lds_residue(unsigned long long *out, int iters) {
     __shared__ unsigned long long row[4096];
@@ -258,6 +284,9 @@ int main() {
     if (run("lds_add_u64_four_lanes_per_entry", [&] { hipLaunchKernelGGL((k_lds_pattern<unsigned long long, PAT_CLUSTER4>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_u64_random_residue8", [&] { hipLaunchKernelGGL((k_lds_residue<8, 64>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_u64_random_residue16", [&] { hipLaunchKernelGGL((k_lds_residue<16, 64>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
+    if (run("lds_add_u64_random_span1024", [&] { hipLaunchKernelGGL(k_lds_span<1024>, dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
+    if (run("lds_add_u64_random_span512", [&] { hipLaunchKernelGGL(k_lds_span<512>, dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
+    if (run("lds_add_u64_random_span256", [&] { hipLaunchKernelGGL(k_lds_span<256>, dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_u64_random_48_lanes", [&] { hipLaunchKernelGGL((k_lds_residue<1, 48>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl * 48 / 64)) return 1;
     if (run("lds_add_u64_random_32_lanes", [&] { hipLaunchKernelGGL((k_lds_residue<1, 32>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl * 32 / 64)) return 1;
     if (run("lds_add_u64_random_16_lanes", [&] { hipLaunchKernelGGL((k_lds_residue<1, 16>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl * 16 / 64)) return 1;
