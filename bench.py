@@ -306,13 +306,14 @@ def suite(args):
         run()
         return out, _timed(run, 3)
 
-    # tiny: launch-latency bound
+    # tiny: launch-latency bound; a captured launch holds the workload's whole
+    # reconstruction (50 iterations)
     wl = synth.tiny_config()
     A, y = measured(wl, noise=0.0)
     model = api.Model(c=c, dt=wl.dt, T=wl.T, f=1)
     tuned = autotune.apply_cached(ctx, args.tuning, model, len(wl.array["qx"]), len(wl.init["x"]))
     st = api.State(wl.init, device=dev)
-    te, tg = iteration_rates(A, st, model, y, iters=10, reps=20)
+    te, tg = iteration_rates(A, st, model, y, iters=50, reps=4)
     print(json.dumps({"workload": wl.name, "balls": len(wl.init["x"]), "transducers": len(wl.array["qx"]),
                       "us_per_iteration_eager": te * 1e3, "us_per_iteration_graph": tg * 1e3,
                       "graph_speedup": te / tg, "tuning": tuned}), flush=True)
