@@ -145,46 +145,59 @@ __host__ __device__ inline int adj_row_stride(int TT) { return (TT + 3) & ~3; }
 // Stages the nd whole rows d0.. of frame f from the forward's edge sums
 // (AdjSrc): v_n = 2 (y_n - y_ref_n) with y_n = (W_{n+1} - W_n) q as the
 // conversion forms it (NaN in a flagged frame) into vrows (stride T), then
-// w_m = vscale (v_m - v_{m-1}) for m = 0..T into rows (stride TS).  `first`
-// (the frame's first ball chunk): also v to y_work and, one wave per row, each
-// row's sum of (y - y_ref)^2 in FP64 (lane n mod 64 adds its samples in order,
-// then a fixed tree), so the loss does not depend on the launch shape.
+// w_m = vscale (v_m - v_{m-1}) for m = 0..T into rows (stride TS).  A wave
+// takes a row at a time, lane l its samples n = l, l + 64, ..., eight at a
+// time with all their loads issued together (one round trip for 512
+// samples); `first` (the frame's first ball chunk): the wave also
+// writes v to y_work and the row's sum of (y - y_ref)^2 in FP64 (each lane in
+// sample order, then a fixed tree), so the loss does not depend on the
+// launch shape.
 __device__ inline void stage_rows_from_sums(const AdjSrc &src, int f, int D, int d0, int nd, int T,
                                             const Level &lc, float vscale, float *rows, int TS,
                                             float *vrows, bool first) {
+    constexpr int kU = 8;   // samples per lane whose loads are in flight together
     const int tid = threadIdx.x;
     const int nth = blockDim.x;
+    const int lane = tid & 63;
     const bool bad = src.misc[kMiscFlags + f] != 0;
     const float inv_scale = 1.0f / fixed_scale(src.misc + kMiscBound, GAUSS, lc);
-    // all rows' samples as one range, four per thread in flight (loads first)
-    const int total = nd * T;
-    for (int i0 = tid; i0 < total; i0 += 4 * nth) {
-        unsigned long long wa[4], wb[4];
-        float rv[4];
+    for (int dl = tid >> 6; dl < nd; dl += (nth + 63) >> 6) {
+        const int64_t r = (int64_t)f * D + d0 + dl;
+        const unsigned long long *w = src.gacc + r * (T + 1);
+        const float *rr = src.y_ref + r * T;
+        float *yw = src.y_work + r * T;
+        float *vr = vrows + (int64_t)dl * T;
+        double acc = 0.0;
+        for (int n0 = lane; n0 < T; n0 += 64 * kU) {
+            unsigned long long wa[kU], wb[kU];
+            float rv[kU];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = i0 + u * nth;
-            if (i < total) {
-                const int dl = i / T;
-                const int n = i - dl * T;
-                const int64_t r = (int64_t)f * D + d0 + dl;
-                wa[u] = src.gacc[r * (T + 1) + n];
-                wb[u] = src.gacc[r * (T + 1) + n + 1];
-                rv[u] = src.y_ref[r * T + n];
+            for (int u = 0; u < kU; ++u) {
+                const int n = n0 + 64 * u;
+                if (n < T) {
+                    wa[u] = w[n];
+                    wb[u] = w[n + 1];
+                    rv[u] = rr[n];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int n = n0 + 64 * u;
+                if (n < T) {
+                    const long long diff = (long long)(wb[u] - wa[u]);
+                    const float y = bad ? __builtin_nanf("") : (float)((double)diff * (double)inv_scale);
+                    const float e = y - rv[u];
+                    vr[n] = 2.0f * e;
+                    if (first) {
+                        yw[n] = 2.0f * e;
+                        acc += (double)e * (double)e;
+                    }
+                }
             }
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = i0 + u * nth;
-            if (i < total) {
-                const int dl = i / T;
-                const int n = i - dl * T;
-                const long long diff = (long long)(wb[u] - wa[u]);
-                const float y = bad ? __builtin_nanf("") : (float)((double)diff * (double)inv_scale);
-                const float v = 2.0f * (y - rv[u]);
-                vrows[(int64_t)dl * T + n] = v;
-                if (first) src.y_work[((int64_t)f * D + d0 + dl) * T + n] = v;
-            }
+        if (first) {
+            for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+            if (lane == 0) src.row_loss[r] = acc;
         }
     }
     __syncthreads();
@@ -195,20 +208,6 @@ __device__ inline void stage_rows_from_sums(const AdjSrc &src, int f, int D, int
             const float cur = m < T ? vr[m] : 0.0f;
             const float prv = m > 0 ? vr[m - 1] : 0.0f;
             wr[m] = vscale * (cur - prv);
-        }
-    }
-    if (first) {
-        // one wave per row (the order within a row does not depend on the block size)
-        const int lane = tid & 63;
-        for (int dl = tid >> 6; dl < nd; dl += (nth + 63) >> 6) {
-            const float *vr = vrows + (int64_t)dl * T;
-            double acc = 0.0;
-            for (int n = lane; n < T; n += 64) {
-                const double e = (double)(0.5f * vr[n]);
-                acc += e * e;
-            }
-            for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
-            if (lane == 0) src.row_loss[(int64_t)f * D + d0 + dl] = acc;
         }
     }
 }
@@ -226,9 +225,10 @@ template <typename R, int PROF, int DIR, bool FULL, bool SRC = false> struct Adj
     // all-gradient GAUSS / OMNI needs more registers than four waves per SIMD
     // leave it: three waves rather than spilling (UNIFORM / COS fits four with
     // a staging depth of three); the variants that form the cotangent from
-    // edge sums (small clouds) hold three
+    // edge sums (small clouds, latency-bound) hold two, for their eight
+    // samples per lane in flight while the balls load
     static constexpr int v = sizeof(R) == sizeof(double) ? 2
-                             : ((FULL && PROF == GAUSS && DIR == OMNI) || SRC) ? 3 : 4;
+                             : SRC ? 2 : (FULL && PROF == GAUSS && DIR == OMNI) ? 3 : 4;
 };
 
 // S: NoSrc, or AdjSrc (FP32 GAUSS bins only) for the cotangent formed from
@@ -279,6 +279,8 @@ __global__ __launch_bounds__(512, (AdjMinBlocks<R, PROF, DIR, FULL, S::on>::v)) 
         BallK<R, PROF> b[kMaxBpt];
         R acc[kMaxBpt][5];
         bool act[kMaxBpt];
+        // (small clouds: the loads are only issued here; their arithmetic
+        // waits until the rows are staged, so the two latencies overlap)
 #pragma unroll
         for (int jb = 0; jb < kMaxBpt; ++jb) {
             const int64_t i0 = base + (int64_t)jb * nth + tid;
@@ -287,11 +289,20 @@ __global__ __launch_bounds__(512, (AdjMinBlocks<R, PROF, DIR, FULL, S::on>::v)) 
             for (int k = 0; k < 5; ++k) acc[jb][k] = R(0);
             if (act[jb]) {
                 const int64_t i = order ? (int64_t)order[i0] : i0;
-                b[jb] = load_ball<R, PROF>(balls.x[i], balls.y[i], balls.z[i], balls.p0[i],
-                                           balls.a[i], lc);
-                act[jb] = b[jb].live;
+                if constexpr (S::on) {
+                    b[jb].x = balls.x[i];
+                    b[jb].y = balls.y[i];
+                    b[jb].z = balls.z[i];
+                    b[jb].p = balls.p0[i];
+                    b[jb].a = balls.a[i];
+                } else {
+                    b[jb] = load_ball<R, PROF>(balls.x[i], balls.y[i], balls.z[i], balls.p0[i],
+                                               balls.a[i], lc);
+                    act[jb] = b[jb].live;
+                }
             }
         }
+        [[maybe_unused]] bool pending = S::on;
         const R *vf = v + (int64_t)f * D * (int64_t)T;
         const int dbeg = sl * dsl;
         const int dend = min(D, dbeg + dsl);
@@ -308,6 +319,17 @@ __global__ __launch_bounds__(512, (AdjMinBlocks<R, PROF, DIR, FULL, S::on>::v)) 
                     stage_rows<R, PROF != GPOINT, StageDepth<PROF, DIR, FULL>::v>(vf, d0, nd, T, tlo,
                                                                                   thi, vscale, rows, TS);
                 __syncthreads();
+                if constexpr (S::on) {
+                    if (pending) {
+#pragma unroll
+                        for (int jb = 0; jb < kMaxBpt; ++jb)
+                            if (act[jb]) {
+                                finish_ball(b[jb], lc);
+                                act[jb] = b[jb].live;
+                            }
+                        pending = false;
+                    }
+                }
                 for (int dl = 0; dl < nd; ++dl) {
                     const int d = __builtin_amdgcn_readfirstlane(d0 + dl);
                     const R qx = ld_uniform(arr.qx + d), qy = ld_uniform(arr.qy + d),

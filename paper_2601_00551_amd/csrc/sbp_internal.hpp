@@ -113,14 +113,12 @@ struct BallK {
     bool live;        // a > 0
 };
 
+// The derived fields of a ball whose x, y, z, p and stored size parameter
+// (in b.a) are set.
 template <typename R, int PROF>
-SBP_HD inline BallK<R, PROF> load_ball(R x, R y, R z, R p, R araw, const Level &lc) {
-    BallK<R, PROF> b;
-    R a = lc.a_softplus ? softplus_dev(araw) : araw;
-    b.x = x;
-    b.y = y;
-    b.z = z;
-    b.p = p;
+SBP_HD inline void finish_ball(BallK<R, PROF> &b, const Level &lc) {
+    const R a = lc.a_softplus ? softplus_dev(b.a) : b.a;
+    const R p = b.p;
     b.a = a;
     b.live = a > R(0);
     if (PROF == UNIFORM) {
@@ -135,6 +133,17 @@ SBP_HD inline BallK<R, PROF> load_ball(R x, R y, R z, R p, R araw, const Level &
         const R c = LevelR<R>::cdt(lc);
         b.h = ex2(R(2) * b.q0 * c * c);
     }
+}
+
+template <typename R, int PROF>
+SBP_HD inline BallK<R, PROF> load_ball(R x, R y, R z, R p, R araw, const Level &lc) {
+    BallK<R, PROF> b;
+    b.x = x;
+    b.y = y;
+    b.z = z;
+    b.p = p;
+    b.a = araw;
+    finish_ball(b, lc);
     return b;
 }
 
