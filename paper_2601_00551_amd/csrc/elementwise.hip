@@ -201,8 +201,8 @@ __global__ void k_adam(AdamArgs a, const int64_t *__restrict__ ball_off, int F,
     __shared__ float s_bc[2];
     if (threadIdx.x == 0) {
         const int step = step_dev ? *step_dev + a.step_add : a.step;
-        const double bc1 = 1.0 - pow((double)a.beta1, (double)step);
-        const double bc2 = 1.0 - pow((double)a.beta2, (double)step);
+        const double bc1 = 1.0 - step_power((double)a.beta1, step);
+        const double bc2 = 1.0 - step_power((double)a.beta2, step);
         s_bc[0] = (float)sqrt(bc2);
         s_bc[1] = (float)(-(double)a.lr[k] / bc1);
     }

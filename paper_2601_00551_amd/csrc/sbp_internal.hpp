@@ -311,6 +311,19 @@ __device__ inline float fixed_scale(const unsigned *slot, int profile, const Lev
     return ldexpf(1.0f, k);
 }
 
+// b^t for an integer step t >= 0 by repeated squaring: at most 2 log2(t)
+// FP64 products, a relative error of about that many ulp (far below the FP32
+// rounding of the bias corrections it feeds), where the general pow costs a
+// lane about two microseconds of dependent FP64 work.
+__device__ inline double step_power(double b, int t) {
+    double r = 1.0, x = b;
+    for (unsigned n = (unsigned)t; n; n >>= 1) {
+        if (n & 1u) r *= x;
+        x *= x;
+    }
+    return r;
+}
+
 // Partial sums of the loss per frame (a fixed count: a deterministic order).
 constexpr int kLossBlocks = 512;
 
