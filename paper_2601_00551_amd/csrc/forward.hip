@@ -603,16 +603,34 @@ __device__ inline void gz_pair(float bx, float by, float bz, float w, float q0, 
     const float h = __builtin_amdgcn_exp2f(2.0f * X2);
     const float u0 = (float)(g.s - (double)m * lc.cdt);
     unsigned long long *p = row - tlo + m;
-    float k0 = 0.0f;
-    for (; cnt >= 8; cnt -= 8, p += 8, k0 += 8.0f) {
-        gz_edges<NN, 4>(p, fmaf(-k0, c, u0), q0, X2, Y1, h, namp, nampKh);
-        gz_edges<NN, 4>(p + 4, fmaf(-(k0 + 4.0f), c, u0), q0, X2, Y1, h, namp, nampKh);
+    // The whole four-edge blocks go in a rotated order, from block beta round
+    // to beta - 1.  A wave's 64-bit LDS adds run faster when its lanes' entries
+    // spread over the residues modulo 16 (random entries: about 6.2 adds per
+    // clock per CU, four lanes on each residue: 9.2); a lane's entry at step s
+    // is m + 4 beta + s until it wraps, so the lanes whose m has the same
+    // residue modulo 4 take, in lane order, the four starts m + 4 beta that
+    // cover that residue's four classes modulo 16.  The sums are integers, so
+    // the order changes no result.
+    const int nb = cnt >> 2;
+    int j = 0;
+    {
+        const unsigned cs = (unsigned)m & 3u;
+        unsigned long long mine = 0;
+#pragma unroll
+        for (unsigned v = 0; v < 4; ++v) {
+            const unsigned long long b = __ballot(cs == v);
+            if (cs == v) mine = b;
+        }
+        const unsigned rank = (unsigned)__popcll(mine & ((1ull << __lane_id()) - 1ull));
+        j = (int)(((cs + 4u * (rank & 3u) - (unsigned)m) & 15u) >> 2);
+        if (j >= nb) j = 0;
     }
-    if (cnt & 4) {
-        gz_edges<NN, 4>(p, fmaf(-k0, c, u0), q0, X2, Y1, h, namp, nampKh);
-        p += 4;
-        k0 += 4.0f;
+    for (int t = 0; t < nb; ++t) {
+        gz_edges<NN, 4>(p + 4 * j, fmaf(-(float)(4 * j), c, u0), q0, X2, Y1, h, namp, nampKh);
+        if (++j == nb) j = 0;
     }
+    p += 4 * nb;
+    float k0 = (float)(4 * nb);
     if (cnt & 2) {
         gz_edges<NN, 2>(p, fmaf(-k0, c, u0), q0, X2, Y1, h, namp, nampKh);
         p += 2;
