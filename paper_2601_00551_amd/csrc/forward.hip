@@ -625,9 +625,19 @@ __device__ inline void gz_pair(float bx, float by, float bz, float w, float q0, 
         j = (int)(((cs + 4u * (rank & 3u) - (unsigned)m) & 15u) >> 2);
         if (j >= nb) j = 0;
     }
-    for (int t = 0; t < nb; ++t) {
-        gz_edges<NN, 4>(p + 4 * j, fmaf(-(float)(4 * j), c, u0), q0, X2, Y1, h, namp, nampKh);
-        if (++j == nb) j = 0;
+    if (nb > 0) {
+        unsigned long long *const p0 = p + 4 * j, *const pend = p + 4 * nb;
+        unsigned long long *q = p0;
+        float kf = (float)(4 * j);
+        do {
+            gz_edges<NN, 4>(q, fmaf(-kf, c, u0), q0, X2, Y1, h, namp, nampKh);
+            q += 4;
+            kf += 4.0f;
+            if (q == pend) {
+                q = p;
+                kf = 0.0f;
+            }
+        } while (q != p0);
     }
     p += 4 * nb;
     float k0 = (float)(4 * nb);

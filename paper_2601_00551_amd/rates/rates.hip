@@ -214,6 +214,48 @@ __global__ __launch_bounds__(256) void k_lds_split(unsigned long long *out, int 
     atomicAdd(out, s);
 }
 
+// The forward's edge pattern: a lane adds 40 consecutive entries from a
+// random first entry m, as ten blocks of four.  ROT = 0 takes the blocks in
+// order (the entries of a wave's lanes at one step have random residues
+// modulo 16); ROT = 1 starts each lane at block beta and wraps, beta chosen so
+// that the lanes whose m has one residue modulo 4 take, in lane order, the four
+// starts m + 4 beta covering that residue's classes modulo 16.
+template <int ROT>
+__global__ __launch_bounds__(256) void k_lds_blocks(unsigned long long *out, int iters) {
+    __shared__ unsigned long long row[4096];
+    for (int i = threadIdx.x; i < 4096; i += blockDim.x) row[i] = 0ull;
+    __syncthreads();
+    uint32_t h = (blockIdx.x * 256u + threadIdx.x) * 2654435761u + 12345u;
+    const unsigned long long below = (1ull << (threadIdx.x & 63u)) - 1ull;
+    for (int it = 0; it < iters; ++it) {
+        h = h * 1664525u + 1013904223u;
+        const uint32_t m = h >> 20;
+        uint32_t beta = 0;
+        if (ROT) {
+            const uint32_t cs = m & 3u;
+            unsigned long long mine = 0;
+#pragma unroll
+            for (uint32_t v = 0; v < 4; ++v) {
+                const unsigned long long b = __ballot(cs == v);
+                if (cs == v) mine = b;
+            }
+            const uint32_t rank = (uint32_t)__popcll(mine & below);
+            beta = ((cs + 4u * (rank & 3u) - m) & 15u) >> 2;
+        }
+#pragma unroll
+        for (int t = 0; t < 10; ++t) {
+            uint32_t j = beta + t;
+            if (j >= 10u) j -= 10u;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) atomicAdd(&row[(m + 4u * j + i) & 4095u], (unsigned long long)(i + 1));
+        }
+    }
+    __syncthreads();
+    unsigned long long s = 0;
+    for (int i = threadIdx.x; i < 4096; i += blockDim.x) s += row[i];
+    atomicAdd(out, s);
+}
+
 // Aligned random reads of W dwords per lane (the row holds 4096 dwords).
 template <int W>
 __global__ __launch_bounds__(256) void k_lds_wide(unsigned long long *out, int iters) {
@@ -293,6 +335,8 @@ int main() {
     if (run("lds_add_u64_as_u32_carry_v22", [&] { hipLaunchKernelGGL(k_lds_split<22>, dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_u64_as_u32_carry_v26", [&] { hipLaunchKernelGGL(k_lds_split<26>, dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_u64_as_u32_carry_v29", [&] { hipLaunchKernelGGL(k_lds_split<29>, dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
+    if (run("lds_add_u64_forward_blocks_in_order", [&] { hipLaunchKernelGGL(k_lds_blocks<0>, dim3(blocks), dim3(threads), 0, 0, outl, li / 5); }, (double)blocks * threads * (li / 5) * 40)) return 1;
+    if (run("lds_add_u64_forward_blocks_rotated", [&] { hipLaunchKernelGGL(k_lds_blocks<1>, dim3(blocks), dim3(threads), 0, 0, outl, li / 5); }, (double)blocks * threads * (li / 5) * 40)) return 1;
     if (run("lds_add_u32_consecutive", [&] { hipLaunchKernelGGL((k_lds_pattern<unsigned int, PAT_CONSEC>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_f64_random", [&] { hipLaunchKernelGGL((k_lds<double, false>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_f64_consecutive", [&] { hipLaunchKernelGGL((k_lds_pattern<double, PAT_CONSEC>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
