@@ -179,7 +179,8 @@ def main(argv=None):
     from . import api, synth
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", choices=("large", "conformal", "tiny"), default="large")
-    ap.add_argument("--balls", type=int, default=2_000_000)
+    ap.add_argument("--balls", type=int, default=None,
+                    help="initial cloud size (default: 2 M for large, 200 k for conformal)")
     ap.add_argument("--out", default=DEFAULT_PATH)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--levels", default="1")
@@ -192,13 +193,13 @@ def main(argv=None):
     dev = torch.device("cuda:0")
     ctx = api.Context(0)
     if args.workload == "large":
-        wl = synth.large_config(n_balls=args.balls)
+        wl = synth.large_config(n_balls=args.balls or 2_000_000)
         balls = wl.init
     elif args.workload == "tiny":
         wl = synth.tiny_config()
         balls = wl.init
     else:
-        wl = synth.conformal_config()
+        wl = synth.conformal_config(n_init=args.balls or 200_000)
         balls = wl.init
     if args.subsample < 1.0:
         n = len(balls["x"])
