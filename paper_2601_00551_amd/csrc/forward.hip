@@ -149,6 +149,29 @@ __device__ inline void uniform_bins(typename FwdAcc<R>::T *p, R ub, R q0, R c, R
     prev = q0 - ue * ue;
 }
 
+// The block a lane starts from when it adds a pair's nb four-entry blocks in
+// a rotated order (block j, j + 1, ..., wrapping to 0, ..., j - 1) starting at
+// row entry m.  A wave's 64-bit LDS adds run faster when its lanes' entries
+// spread over the residues modulo 16 (random entries: about 6.2 adds per clock
+// per CU; four lanes on each residue: 9.2); a lane's entry at step s is
+// m + 4 j + s until it wraps, so the lanes whose m has the same residue modulo
+// 4 take, in lane order, the four starts m + 4 j that cover that residue's
+// four classes modulo 16 (about 7.5 per clock with the wraps).  Lanes that are
+// not active take no part.  The sums are integers, so the order changes no
+// result.
+__device__ inline int rotated_block(int m, int nb) {
+    const unsigned cs = (unsigned)m & 3u;
+    unsigned long long mine = 0;
+#pragma unroll
+    for (unsigned v = 0; v < 4; ++v) {
+        const unsigned long long b = __ballot(cs == v);
+        if (cs == v) mine = b;
+    }
+    const unsigned rank = (unsigned)__popcll(mine & ((1ull << __lane_id()) - 1ull));
+    const int j = (int)(((cs + 4u * (rank & 3u) - (unsigned)m) & 15u) >> 2);
+    return j < nb ? j : 0;
+}
+
 // N consecutive point samples from sample m (u_m = ub): sample k (k = 0..N-1)
 // adds amp u_k e_k, u_k = ub - k c, e_k = 2^(X0 + k (X1 + k X2)).
 template <typename R, int N>
@@ -603,28 +626,9 @@ __device__ inline void gz_pair(float bx, float by, float bz, float w, float q0, 
     const float h = __builtin_amdgcn_exp2f(2.0f * X2);
     const float u0 = (float)(g.s - (double)m * lc.cdt);
     unsigned long long *p = row - tlo + m;
-    // The whole four-edge blocks go in a rotated order, from block beta round
-    // to beta - 1.  A wave's 64-bit LDS adds run faster when its lanes' entries
-    // spread over the residues modulo 16 (random entries: about 6.2 adds per
-    // clock per CU, four lanes on each residue: 9.2); a lane's entry at step s
-    // is m + 4 beta + s until it wraps, so the lanes whose m has the same
-    // residue modulo 4 take, in lane order, the four starts m + 4 beta that
-    // cover that residue's four classes modulo 16.  The sums are integers, so
-    // the order changes no result.
+    // the whole four-edge blocks in a rotated order (rotated_block)
     const int nb = cnt >> 2;
-    int j = 0;
-    {
-        const unsigned cs = (unsigned)m & 3u;
-        unsigned long long mine = 0;
-#pragma unroll
-        for (unsigned v = 0; v < 4; ++v) {
-            const unsigned long long b = __ballot(cs == v);
-            if (cs == v) mine = b;
-        }
-        const unsigned rank = (unsigned)__popcll(mine & ((1ull << __lane_id()) - 1ull));
-        j = (int)(((cs + 4u * (rank & 3u) - (unsigned)m) & 15u) >> 2);
-        if (j >= nb) j = 0;
-    }
+    const int j = rotated_block(m, nb);
     if (nb > 0) {
         unsigned long long *const p0 = p + 4 * j, *const pend = p + 4 * nb;
         unsigned long long *q = p0;
