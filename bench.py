@@ -53,11 +53,14 @@ OPS_FWD_EDGE_UNIFORM = 7  # per edge, UNIFORM profile: u, u^2, a^2 - u^2, clamp,
 OPS_FWD_SAMPLE_POINT = 8  # per sample, point sampling: u, u^2 k, exp, u e, scale, accumulate
 VALU_PEAK = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock = 3.93e13 lane-ops/s
 # 64-bit LDS atomic adds, lane-operations per clock per CU, measured by
-# `bench.py --rates` (profiles/issue_rates.md): consecutive addresses (no two
-# lanes on one bank or address), and pseudo-random addresses in a 4096-entry row
-LDS_U64_CONFLICT_FREE = 8.60
-LDS_U64_RANDOM = 6.23
-LDS_PEAK = 256 * 2.4e9 * LDS_U64_CONFLICT_FREE
+# `bench.py --rates` (profiles/issue_rates.md): the fastest pattern measured
+# (four lanes on each residue modulo 16, random otherwise), pseudo-random
+# addresses in a 4096-entry row, and the forward's own pattern (40 edges per
+# lane as ten four-edge blocks from a rotated start)
+LDS_U64_BEST = 9.33
+LDS_U64_RANDOM = 6.26
+LDS_U64_FORWARD_ROTATED = 7.58
+LDS_PEAK = 256 * 2.4e9 * LDS_U64_BEST
 
 
 def edges_per_pair(a_sup, cdt):
@@ -78,8 +81,8 @@ def algorithmic_ops(E):
 
 KERNEL_SOURCES = {"k_forward_gz": ("paper_2601_00551_amd/csrc/forward.hip", "paper_2601_00551_amd/csrc/sbp_internal.hpp"),
                   "k_adjoint": ("paper_2601_00551_amd/csrc/adjoint.hip", "paper_2601_00551_amd/csrc/sbp_internal.hpp")}
-KERNEL_NAMES = {"forward": "k_forward_gz<1>", "adjoint": "k_adjoint<float, 1, 1, true>",
-                "filter": "k_adjoint<float, 1, 1, false>"}
+KERNEL_NAMES = {"forward": "k_forward_gz<1>", "adjoint": "k_adjoint<float, 1, 1, true, sbp::NoSrc>",
+                "filter": "k_adjoint<float, 1, 1, false, sbp::NoSrc>"}
 
 
 def measured_traffic(kernel):
@@ -647,7 +650,8 @@ def main():
     lds = pairs["forward"] * E / (avg["forward"] * 1e-3)      # one LDS add per support edge
     kernels["forward"]["lds_atomics"] = {
         "per_pair": E, "achieved_per_s": lds, "peak_per_s": LDS_PEAK, "frac": lds / LDS_PEAK,
-        "frac_of_random_address_rate": lds / (256 * 2.4e9 * LDS_U64_RANDOM)}
+        "frac_of_random_address_rate": lds / (256 * 2.4e9 * LDS_U64_RANDOM),
+        "frac_of_rotated_pattern_rate": lds / (256 * 2.4e9 * LDS_U64_FORWARD_ROTATED)}
     dominant = max(("forward", "adjoint", "filter"), key=lambda n: avg[n])
     achieved = kernels[dominant]["achieved_TOPs"] * 1e12
     fwd_adj = kept * D / ((avg["forward"] + avg["adjoint"]) * 1e-3)
