@@ -57,9 +57,9 @@ VALU_PEAK = 256 * 4 * 16 * 2.4e9   # CUs x SIMDs x lanes x clock = 3.93e13 lane-
 # (four lanes on each residue modulo 16, random otherwise), pseudo-random
 # addresses in a 4096-entry row, and the forward's own pattern (40 edges per
 # lane as ten four-edge blocks from a rotated start)
-LDS_U64_BEST = 9.33
-LDS_U64_RANDOM = 6.26
-LDS_U64_FORWARD_ROTATED = 7.58
+LDS_U64_BEST = 9.27
+LDS_U64_RANDOM = 6.21
+LDS_U64_FORWARD_ROTATED = 7.50
 LDS_PEAK = 256 * 2.4e9 * LDS_U64_BEST
 
 

@@ -256,6 +256,33 @@ __global__ __launch_bounds__(256) void k_lds_blocks(unsigned long long *out, int
     atomicAdd(out, s);
 }
 
+// The same 40 edges per lane started at any edge: lane l begins at the edge
+// whose entry is congruent to l modulo 16 and wraps (what steering to the
+// exact residue would give; the forward cannot start inside a four-edge block
+// without restarting its recurrence there).
+__global__ __launch_bounds__(256) void k_lds_edges_exact(unsigned long long *out, int iters) {
+    __shared__ unsigned long long row[4096];
+    for (int i = threadIdx.x; i < 4096; i += blockDim.x) row[i] = 0ull;
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t h = (blockIdx.x * 256u + threadIdx.x) * 2654435761u + 12345u;
+    for (int it = 0; it < iters; ++it) {
+        h = h * 1664525u + 1013904223u;
+        const uint32_t m = h >> 20;
+        const uint32_t r = ((lane & 15u) - m) & 15u;
+#pragma unroll
+        for (int t = 0; t < 40; ++t) {
+            uint32_t k = r + t;
+            if (k >= 40u) k -= 40u;
+            atomicAdd(&row[(m + k) & 4095u], (unsigned long long)(t & 7) + 1ull);
+        }
+    }
+    __syncthreads();
+    unsigned long long s = 0;
+    for (int i = threadIdx.x; i < 4096; i += blockDim.x) s += row[i];
+    atomicAdd(out, s);
+}
+
 // Aligned random reads of W dwords per lane (the row holds 4096 dwords).
 template <int W>
 __global__ __launch_bounds__(256) void k_lds_wide(unsigned long long *out, int iters) {
@@ -337,6 +364,7 @@ int main() {
     if (run("lds_add_u64_as_u32_carry_v29", [&] { hipLaunchKernelGGL(k_lds_split<29>, dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_u64_forward_blocks_in_order", [&] { hipLaunchKernelGGL(k_lds_blocks<0>, dim3(blocks), dim3(threads), 0, 0, outl, li / 5); }, (double)blocks * threads * (li / 5) * 40)) return 1;
     if (run("lds_add_u64_forward_blocks_rotated", [&] { hipLaunchKernelGGL(k_lds_blocks<1>, dim3(blocks), dim3(threads), 0, 0, outl, li / 5); }, (double)blocks * threads * (li / 5) * 40)) return 1;
+    if (run("lds_add_u64_forward_edges_exact_start", [&] { hipLaunchKernelGGL(k_lds_edges_exact, dim3(blocks), dim3(threads), 0, 0, outl, li / 5); }, (double)blocks * threads * (li / 5) * 40)) return 1;
     if (run("lds_add_u32_consecutive", [&] { hipLaunchKernelGGL((k_lds_pattern<unsigned int, PAT_CONSEC>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_f64_random", [&] { hipLaunchKernelGGL((k_lds<double, false>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
     if (run("lds_add_f64_consecutive", [&] { hipLaunchKernelGGL((k_lds_pattern<double, PAT_CONSEC>), dim3(blocks), dim3(threads), 0, 0, outl, li); }, nl)) return 1;
