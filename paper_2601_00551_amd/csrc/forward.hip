@@ -149,29 +149,6 @@ __device__ inline void uniform_bins(typename FwdAcc<R>::T *p, R ub, R q0, R c, R
     prev = q0 - ue * ue;
 }
 
-// The block a lane starts from when it adds a pair's nb four-entry blocks in
-// a rotated order (block j, j + 1, ..., wrapping to 0, ..., j - 1) starting at
-// row entry m.  A wave's 64-bit LDS adds run faster when its lanes' entries
-// spread over the residues modulo 16 (random entries: about 6.2 adds per clock
-// per CU; four lanes on each residue: 9.2); a lane's entry at step s is
-// m + 4 j + s until it wraps, so the lanes whose m has the same residue modulo
-// 4 take, in lane order, the four starts m + 4 j that cover that residue's
-// four classes modulo 16 (about 7.5 per clock with the wraps).  Lanes that are
-// not active take no part.  The sums are integers, so the order changes no
-// result.
-__device__ inline int rotated_block(int m, int nb) {
-    const unsigned cs = (unsigned)m & 3u;
-    unsigned long long mine = 0;
-#pragma unroll
-    for (unsigned v = 0; v < 4; ++v) {
-        const unsigned long long b = __ballot(cs == v);
-        if (cs == v) mine = b;
-    }
-    const unsigned rank = (unsigned)__popcll(mine & ((1ull << __lane_id()) - 1ull));
-    const int j = (int)(((cs + 4u * (rank & 3u) - (unsigned)m) & 15u) >> 2);
-    return j < nb ? j : 0;
-}
-
 // N consecutive point samples from sample m (u_m = ub): sample k (k = 0..N-1)
 // adds amp u_k e_k, u_k = ub - k c, e_k = 2^(X0 + k (X1 + k X2)).
 template <typename R, int N>
@@ -578,6 +555,29 @@ __device__ inline void edge_add(unsigned long long *p, float vh) {
         asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(iv) : "v"(vh));
         atomicAdd(p, (unsigned long long)(long long)iv);
     }
+}
+
+// The block a lane starts from when it adds a pair's nb four-entry blocks in
+// a rotated order (block j, j + 1, ..., wrapping to 0, ..., j - 1) starting at
+// row entry m.  A wave's 64-bit LDS adds run faster when its lanes' entries
+// spread over the residues modulo 16 (random entries: about 6.2 adds per clock
+// per CU; four lanes on each residue: 9.3); a lane's entry at step s is
+// m + 4 j + s until it wraps, so the lanes whose m has the same residue modulo
+// 4 take, in lane order, the four starts m + 4 j that cover that residue's
+// four classes modulo 16 (about 7.5 per clock with the wraps).  Lanes that are
+// not active take no part.  The sums are integers, so the order changes no
+// result.
+__device__ inline int rotated_block(int m, int nb) {
+    const unsigned cs = (unsigned)m & 3u;
+    unsigned long long mine = 0;
+#pragma unroll
+    for (unsigned v = 0; v < 4; ++v) {
+        const unsigned long long b = __ballot(cs == v);
+        if (cs == v) mine = b;
+    }
+    const unsigned rank = (unsigned)__popcll(mine & ((1ull << __lane_id()) - 1ull));
+    const int j = (int)(((cs + 4u * (rank & 3u) - (unsigned)m) & 15u) >> 2);
+    return j < nb ? j : 0;
 }
 
 // N consecutive inside edges from offset u0 (edge k at u0 - k c), adding
