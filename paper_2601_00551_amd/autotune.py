@@ -15,7 +15,7 @@ import json
 import math
 import os
 
-FWD_SPACE = {"fwd_dets": (1, 2, 4, 8), "fwd_block": (256, 512), "fwd_bpt": (1, 2, 4),
+FWD_SPACE = {"fwd_dets": (1, 2, 4, 8), "fwd_block": (256, 512), "fwd_bpt": (1, 2, 4, 8, 16),
              "fwd_tile": (0, 2048, 1024)}
 ADJ_SPACE = {"adj_dets": (1, 2, 4, 8), "adj_block": (128, 256, 512), "adj_bpt": (1, 2, 3),
              "adj_tile": (0, 2048)}
