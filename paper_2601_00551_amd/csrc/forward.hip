@@ -150,16 +150,24 @@ __device__ inline void uniform_bins(typename FwdAcc<R>::T *p, R ub, R q0, R c, R
 }
 
 // N consecutive point samples from sample m (u_m = ub): sample k (k = 0..N-1)
-// adds amp u_k e_k, u_k = ub - k c, e_k = 2^(X0 + k (X1 + k X2)).
+// adds amp u_k e_k, u_k = ub - k c, with e_k = 2^(q0 u_k^2) by the
+// two-multiply recurrence e_{k+1} = e_k g_k, g_{k+1} = g_k h restarted here
+// (e_0 = 2^(q0 ub^2), g_0 = 2^(Y1 ub + X2), h = 2^(2 X2)).  A sample is the
+// value itself, not a difference of neighbours, so the recurrence's rounding
+// over a block of eight (a few ulp of e) stays a few ulp of the sample.
 template <typename R, int N>
-__device__ inline void point_samples(typename FwdAcc<R>::T *p, R ub, R q0, R c, R X2, R Y1, R amp) {
-    const R X0 = q0 * ub * ub;
-    const R X1 = Y1 * ub;
+__device__ inline void point_samples(typename FwdAcc<R>::T *p, R ub, R q0, R c, R X2, R Y1, R h,
+                                     R amp) {
+    R e = ex2(q0 * ub * ub);
+    R g = ex2(fma(Y1, ub, X2));
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         const R u = fma(R(-k), c, ub);
-        const R e = ex2(fma(R(k), fma(R(k), X2, X1), X0));
         FwdAcc<R>::add(p + k, amp * u * e);
+        if (k + 1 < N) {
+            e *= g;
+            g *= h;
+        }
     }
 }
 
@@ -184,19 +192,20 @@ __device__ inline void fwd_pair_point(const BallK<R, GPOINT> &b, R qx, R qy, R q
     if (FwdBlocks<R>::on) {
         const R X2 = b.q0 * c * c;
         const R Y1 = R(-2) * b.q0 * c;
+        const R h = ex2(R(2) * X2);
         for (; cnt >= kFwdBlock; cnt -= kFwdBlock, p += kFwdBlock, m += kFwdBlock)
-            point_samples<R, kFwdBlock>(p, (R)(g.s - (double)m * lc.cdt), b.q0, c, X2, Y1, amp);
+            point_samples<R, kFwdBlock>(p, (R)(g.s - (double)m * lc.cdt), b.q0, c, X2, Y1, h, amp);
         if (cnt & 4) {
-            point_samples<R, 4>(p, (R)(g.s - (double)m * lc.cdt), b.q0, c, X2, Y1, amp);
+            point_samples<R, 4>(p, (R)(g.s - (double)m * lc.cdt), b.q0, c, X2, Y1, h, amp);
             p += 4;
             m += 4;
         }
         if (cnt & 2) {
-            point_samples<R, 2>(p, (R)(g.s - (double)m * lc.cdt), b.q0, c, X2, Y1, amp);
+            point_samples<R, 2>(p, (R)(g.s - (double)m * lc.cdt), b.q0, c, X2, Y1, h, amp);
             p += 2;
             m += 2;
         }
-        if (cnt & 1) point_samples<R, 1>(p, (R)(g.s - (double)m * lc.cdt), b.q0, c, X2, Y1, amp);
+        if (cnt & 1) point_samples<R, 1>(p, (R)(g.s - (double)m * lc.cdt), b.q0, c, X2, Y1, h, amp);
     } else {
         for (; cnt > 0; --cnt, ++p, ++m) {
             const R u = (R)(g.s - (double)m * lc.cdt);
